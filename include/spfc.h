@@ -1,0 +1,185 @@
+/*
+ * spfc.h - C ABI of the GPU time stepper for the square phase field crystal
+ * (SPFC) equation with the second-order SAV-BDF2 scheme of
+ * M. Wang, Q. Huang, C. Wang, arXiv 2012.15133.
+ *
+ * Problem (Section 1, eq. equation-SPFC): on a periodic box of side L_j,
+ *     d_t phi = Delta mu,  mu = -c4 div(|grad phi|^2 grad phi) + a phi + 2 Delta phi + Delta^2 phi,
+ * a = 1 - epsilon > 0 and c4 = 1 in the paper.  Space: Fourier pseudo-spectral
+ * collocation on n_x x n_y (x n_z) points (Section 2.1).  Time: the SAV scheme
+ * eq. scheme-SAV-1 solved as in Section 2.3 (two constant-coefficient Fourier
+ * solves and one scalar equation per step).
+ *
+ * Conventions shared by every call:
+ *  - Real grid functions are arrays x-fastest: index x + n_x*(y + n_y*z).
+ *  - Derivatives of odd order drop the Nyquist mode, those of even order keep it
+ *    (the paper assumes odd n; its experiments and this library use even n).
+ *  - Every pointer argument whose name ends in _dev is device memory of the
+ *    current HIP device; all others are host memory.
+ *  - All calls return an int status (SPFC_OK or an SPFC_E_* code) and leave their
+ *    outputs untouched on error.  No exception crosses this boundary.
+ *  - One host thread at a time per context.
+ *  - The library allocates no device memory: the caller passes a workspace
+ *    that must stay alive and untouched until spfc_destroy.
+ */
+#ifndef SPFC_H
+#define SPFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    SPFC_OK = 0,
+    SPFC_E_INVAL = 1,      /* bad argument: null pointer, unsupported size, a <= 0, dt <= 0, NaN input ... */
+    SPFC_E_NOMEM = 2,      /* workspace smaller than spfc_workspace_bytes() */
+    SPFC_E_DEVICE = 3,     /* a HIP call failed; the context is unusable afterwards */
+    SPFC_E_NONFINITE = 4,  /* a query found the sticky NONFINITE flag set */
+    SPFC_E_STATE = 5       /* call out of order (e.g. history not held), or bad checkpoint size */
+};
+
+/* sticky flags reported by spfc_status */
+enum {
+    SPFC_FLAG_NONFINITE = 1u,       /* E_1, an inner product or xi was not finite */
+    SPFC_FLAG_E1_BELOW_OMEGA = 2u,  /* E_1 < |Omega|, against eq. energy-SPFC-split-2-2 */
+    SPFC_FLAG_P1_POSITIVE = 4u,     /* <N, A^-1 Delta N> > 0, against eq. solver-5 */
+    SPFC_FLAG_ENERGY_RISE = 8u      /* modified energy rose by more than energy_tol (Theorem 3.1) */
+};
+
+/* start-up of the two-step scheme */
+enum {
+    SPFC_STARTUP_SAV1 = 0,   /* first step: first-order SAV (weights (1,1,0), phihat = phi^0) */
+    SPFC_STARTUP_GHOST = 1,  /* phi^-1 = phi^0 - dt Delta_N mu^0 (eq. scheme-SAV-initial-1) */
+    SPFC_STARTUP_COPY = 2    /* phi^-1 = phi^0, r^-1 = r^0 (the restart rule of Section 5.2) */
+};
+
+/* storage and transform precision (inner products, energies, r and xi are FP64 in both) */
+enum { SPFC_FP64 = 0, SPFC_FP32 = 1 };
+
+typedef struct spfc_ctx spfc_ctx;
+
+/* Grid (Section 2.1).  dim = 2 or 3; n[j] points along axis j (x, y, z), each a
+ * power of two in [8, 1024]; L[j] > 0 the box side.  Unused entries ignored. */
+typedef struct {
+    int dim;
+    int n[3];
+    double L[3];
+} spfc_grid;
+
+/* Model and run parameters.
+ *  epsilon  : a = 1 - epsilon must be > 0 (Section 1).
+ *  c4       : > 0, multiplies (1/4)|grad phi|^4 in the energy (paper: 1).  E_1 then carries
+ *             the constant (1 + 1/c4)|Omega| (= 2|Omega| at c4 = 1, Section 2.2).
+ *  startup  : SPFC_STARTUP_*.
+ *  precision: SPFC_FP64 or SPFC_FP32.
+ *  history  : capacity of the per-step record ring (>= 1).
+ *  energy_tol: relative rise of the modified energy that sets SPFC_FLAG_ENERGY_RISE
+ *             (<= 0 picks 1e-12 for FP64, 1e-6 for FP32). */
+typedef struct {
+    double epsilon;
+    double c4;
+    int startup;
+    int precision;
+    int64_t history;
+    double energy_tol;
+} spfc_params;
+
+/* Per-step record (index n = state phi^n).  energy is the modified energy
+ * E(phi^n, phi^{n-1}, r^n, r^{n-1}) of Theorem 3.1 (eq. discrete energy), mean the
+ * mean of phi^n, r = r^n.  xi = r^n / sqrt(E_1(phihat)), E1 = E_1(phihat) and
+ * p1 = <N, A_N^-1 Delta_N N> belong to the step that produced phi^n (0 for n = 0). */
+typedef struct {
+    double energy;
+    double mean;
+    double r;
+    double xi;
+    double E1;
+    double p1;
+    double S;
+    double reserved;
+} spfc_record;
+
+/* Energies of the current state phi^n (spfc_energy). */
+typedef struct {
+    double modified_energy;  /* E(phi^n, phi^{n-1}, r^n, r^{n-1}), Theorem 3.1 */
+    double energy;           /* E_N(phi^n), eq. energy-discrete-spectral (with c4) */
+    double sav_energy;       /* a/2||phi||^2 + 1/2||Delta_N phi||^2 + r^2 (Section 5.2) */
+    double r;                /* r^n */
+    double E1;               /* E_{1,N}(phi^n) */
+    double mean;             /* mean of phi^n */
+    int64_t step;            /* n */
+} spfc_energy_t;
+
+/* Bytes of device workspace a context needs for this grid and parameters. */
+int spfc_workspace_bytes(const spfc_grid* grid, const spfc_params* params, size_t* bytes);
+
+/* Create a context.  phi0_dev: N_total doubles (x fastest), read during the call
+ * only (the call synchronizes the stream before returning, so the caller may
+ * free phi0_dev afterwards).  workspace_dev: at least spfc_workspace_bytes bytes,
+ * 256-byte aligned, owned by the caller.  hip_stream: the hipStream_t every
+ * later call enqueues on (0 = null stream).  Computes r^0 = sqrt(E_1(phi^0))
+ * (after eq. scheme-SAV-initial-1).  Errors: SPFC_E_INVAL (bad grid/params,
+ * null pointer, non-finite phi0), SPFC_E_NOMEM, SPFC_E_DEVICE. */
+int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev,
+              void* workspace_dev, size_t workspace_bytes, void* hip_stream, spfc_ctx** out);
+
+/* Advance n >= 0 steps of size dt > 0 (eq. scheme-SAV-1, solved as in Section 2.3).
+ * The first step of a run uses the start-up mode.  A call with a dt different from
+ * the previous one restarts the two-step scheme with phi^{-1} = phi^0 and
+ * r = sqrt(E_1(phi^0)) at the current state (Section 5.2).  Asynchronous: only
+ * kernel launches are enqueued.  Errors: SPFC_E_INVAL, SPFC_E_DEVICE. */
+int spfc_step(spfc_ctx* ctx, double dt, int64_t n);
+
+/* Mean of phi^n (synchronizes).  Theorem 2.1 keeps it at the mean of phi^0. */
+int spfc_mass(spfc_ctx* ctx, double* mean);
+
+/* Energies of the current state (synchronizes).  Returns SPFC_E_NONFINITE if the
+ * NONFINITE flag is set (the struct is still filled). */
+int spfc_energy(spfc_ctx* ctx, spfc_energy_t* out);
+
+/* Copy records first .. first+count-1 to out (host).  SPFC_E_STATE if a record
+ * is not held (not yet computed, or overwritten in the ring). Synchronizes. */
+int spfc_history(spfc_ctx* ctx, int64_t first, int64_t count, spfc_record* out);
+
+/* Number of the current step n (records 0..n exist). */
+int spfc_step_count(spfc_ctx* ctx, int64_t* n);
+
+/* Write phi^n in real space to out_dev (N_total values, x fastest), as doubles
+ * (dtype SPFC_FP64) or floats (SPFC_FP32).  Asynchronous on the context stream. */
+int spfc_get_phi(spfc_ctx* ctx, void* out_dev, int dtype);
+
+/* Checkpoint: bytes needed, save into / load from caller device memory.  The state
+ * is (phi^n, phi^{n-1}, r^n, r^{n-1}, n, dt of the last step, start-up status);
+ * a run resumed from it continues bit for bit.  Synchronizes. */
+int spfc_state_bytes(spfc_ctx* ctx, size_t* bytes);
+int spfc_save_state(spfc_ctx* ctx, void* out_dev, size_t bytes);
+int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes);
+
+/* Sticky SPFC_FLAG_* bits (synchronizes). */
+int spfc_status(spfc_ctx* ctx, uint32_t* flags);
+
+/* Per-kernel timing of the step kernels, measured with HIP events on the context
+ * stream.  spfc_profile(ctx, 1) starts recording (events around every launch of a
+ * step kernel, which adds gaps between launches), 0 stops.  spfc_kernel_times
+ * fills up to `cap` entries: name[i] (static string), average milliseconds per
+ * launch, launches, and the algorithmic HBM bytes one launch must move.
+ * Synchronizes. */
+int spfc_profile(spfc_ctx* ctx, int enable);
+int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms,
+                      int64_t* launches, double* bytes_per_launch, int* count);
+
+/* Static description of a status code. */
+const char* spfc_strerror(int status);
+
+/* Free the host context.  Does not touch caller memory. */
+int spfc_destroy(spfc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPFC_H */

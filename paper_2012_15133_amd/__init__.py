@@ -1,0 +1,13 @@
+"""MI355X-native time stepper for the square phase field crystal equation with the
+SAV-BDF2 scheme of Wang, Huang and Wang (arXiv 2012.15133).
+
+The GPU path is the HIP library libspfc.so (C ABI in include/spfc.h); `binding`
+wraps it.  `inputs` draws the seeded synthetic initial data.
+"""
+
+from .binding import (  # noqa: F401
+    Solver, SpfcError, load_library, make_grid, make_params,
+    spfc_workspace_bytes, spfc_init, spfc_step, spfc_mass, spfc_energy, spfc_history,
+    spfc_step_count, spfc_get_phi, spfc_state_bytes, spfc_save_state, spfc_load_state,
+    spfc_status, spfc_profile, spfc_kernel_times, spfc_strerror, spfc_destroy,
+)

@@ -1,0 +1,309 @@
+"""ctypes binding of libspfc.so (include/spfc.h): the C ABI calls under the same
+names, plus a small `Solver` class that takes device memory and the stream from
+PyTorch.  Argument marshalling only: every step of the method runs in the HIP
+kernels of the library.  There is no fallback: if the library is missing the
+calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SPFC_LIB", os.path.join(HERE, "libspfc.so"))
+
+SPFC_OK, SPFC_E_INVAL, SPFC_E_NOMEM, SPFC_E_DEVICE, SPFC_E_NONFINITE, SPFC_E_STATE = range(6)
+SPFC_FLAG_NONFINITE, SPFC_FLAG_E1_BELOW_OMEGA, SPFC_FLAG_P1_POSITIVE, SPFC_FLAG_ENERGY_RISE = 1, 2, 4, 8
+SPFC_STARTUP_SAV1, SPFC_STARTUP_GHOST, SPFC_STARTUP_COPY = 0, 1, 2
+SPFC_FP64, SPFC_FP32 = 0, 1
+STARTUPS = {"sav1": SPFC_STARTUP_SAV1, "ghost": SPFC_STARTUP_GHOST, "copy": SPFC_STARTUP_COPY}
+PRECISIONS = {"fp64": SPFC_FP64, "fp32": SPFC_FP32}
+
+EXPORTS = [
+    "spfc_workspace_bytes", "spfc_init", "spfc_step", "spfc_mass", "spfc_energy", "spfc_history",
+    "spfc_step_count", "spfc_get_phi", "spfc_state_bytes", "spfc_save_state", "spfc_load_state",
+    "spfc_status", "spfc_profile", "spfc_kernel_times", "spfc_strerror", "spfc_destroy",
+]
+
+
+class spfc_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3)]
+
+
+class spfc_params(ctypes.Structure):
+    _fields_ = [("epsilon", ctypes.c_double), ("c4", ctypes.c_double), ("startup", ctypes.c_int),
+                ("precision", ctypes.c_int), ("history", ctypes.c_int64), ("energy_tol", ctypes.c_double)]
+
+
+class spfc_record(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("energy", "mean", "r", "xi", "E1", "p1", "S", "reserved")]
+
+
+class spfc_energy_t(ctypes.Structure):
+    _fields_ = [("modified_energy", ctypes.c_double), ("energy", ctypes.c_double),
+                ("sav_energy", ctypes.c_double), ("r", ctypes.c_double), ("E1", ctypes.c_double),
+                ("mean", ctypes.c_double), ("step", ctypes.c_int64)]
+
+
+class SpfcError(RuntimeError):
+    def __init__(self, call, status):
+        self.status = status
+        super().__init__(f"{call} failed: {status} ({strerror(status)})")
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libspfc.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} is missing (run python -m paper_2012_15133_amd.build)")
+    lib = ctypes.CDLL(p)
+    vp, sz, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "spfc_workspace_bytes": [P(spfc_grid), P(spfc_params), P(sz)],
+        "spfc_init": [P(spfc_grid), P(spfc_params), vp, vp, sz, vp, P(vp)],
+        "spfc_step": [vp, dbl, i64],
+        "spfc_mass": [vp, P(dbl)],
+        "spfc_energy": [vp, P(spfc_energy_t)],
+        "spfc_history": [vp, i64, i64, P(spfc_record)],
+        "spfc_step_count": [vp, P(i64)],
+        "spfc_get_phi": [vp, vp, i32],
+        "spfc_state_bytes": [vp, P(sz)],
+        "spfc_save_state": [vp, vp, sz],
+        "spfc_load_state": [vp, vp, sz],
+        "spfc_status": [vp, P(ctypes.c_uint32)],
+        "spfc_profile": [vp, i32],
+        "spfc_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
+        "spfc_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.spfc_strerror.argtypes = [ctypes.c_int]
+    lib.spfc_strerror.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load_library().spfc_strerror(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _check(call, status):
+    if status != SPFC_OK:
+        raise SpfcError(call, status)
+
+
+def make_grid(n, L) -> spfc_grid:
+    n = list(n)
+    L = list(L)
+    g = spfc_grid()
+    g.dim = len(n)
+    for j in range(3):
+        g.n[j] = int(n[j]) if j < len(n) else 1
+        g.L[j] = float(L[j]) if j < len(L) else 1.0
+    return g
+
+
+def make_params(epsilon, c4=1.0, startup="sav1", precision="fp64", history=4096, energy_tol=0.0) -> spfc_params:
+    p = spfc_params()
+    p.epsilon = float(epsilon)
+    p.c4 = float(c4)
+    p.startup = STARTUPS[startup] if isinstance(startup, str) else int(startup)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.history = int(history)
+    p.energy_tol = float(energy_tol)
+    return p
+
+
+# ------------------------------------------------------------------ thin wrappers, same names as the ABI
+
+def spfc_workspace_bytes(grid: spfc_grid, params: spfc_params) -> int:
+    out = ctypes.c_size_t(0)
+    _check("spfc_workspace_bytes", load_library().spfc_workspace_bytes(ctypes.byref(grid), ctypes.byref(params),
+                                                                       ctypes.byref(out)))
+    return out.value
+
+
+def spfc_init(grid, params, phi0_ptr: int, workspace_ptr: int, workspace_bytes: int, stream_ptr: int):
+    ctx = ctypes.c_void_p()
+    _check("spfc_init", load_library().spfc_init(ctypes.byref(grid), ctypes.byref(params), phi0_ptr, workspace_ptr,
+                                                 workspace_bytes, stream_ptr, ctypes.byref(ctx)))
+    return ctx
+
+
+def spfc_step(ctx, dt: float, n: int):
+    _check("spfc_step", load_library().spfc_step(ctx, float(dt), int(n)))
+
+
+def spfc_mass(ctx) -> float:
+    m = ctypes.c_double()
+    _check("spfc_mass", load_library().spfc_mass(ctx, ctypes.byref(m)))
+    return m.value
+
+
+def spfc_energy(ctx, allow_nonfinite: bool = False) -> dict:
+    e = spfc_energy_t()
+    st = load_library().spfc_energy(ctx, ctypes.byref(e))
+    if not (st == SPFC_OK or (allow_nonfinite and st == SPFC_E_NONFINITE)):
+        _check("spfc_energy", st)
+    return {k: getattr(e, k) for k, _ in spfc_energy_t._fields_}
+
+
+def spfc_history(ctx, first: int, count: int) -> list:
+    buf = (spfc_record * max(count, 1))()
+    _check("spfc_history", load_library().spfc_history(ctx, int(first), int(count), buf))
+    return [{k: getattr(buf[i], k) for k, _ in spfc_record._fields_ if k != "reserved"} for i in range(count)]
+
+
+def spfc_step_count(ctx) -> int:
+    n = ctypes.c_int64()
+    _check("spfc_step_count", load_library().spfc_step_count(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def spfc_get_phi(ctx, out_ptr: int, dtype: int = SPFC_FP64):
+    _check("spfc_get_phi", load_library().spfc_get_phi(ctx, out_ptr, int(dtype)))
+
+
+def spfc_state_bytes(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check("spfc_state_bytes", load_library().spfc_state_bytes(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def spfc_save_state(ctx, out_ptr: int, nbytes: int):
+    _check("spfc_save_state", load_library().spfc_save_state(ctx, out_ptr, int(nbytes)))
+
+
+def spfc_load_state(ctx, in_ptr: int, nbytes: int):
+    _check("spfc_load_state", load_library().spfc_load_state(ctx, in_ptr, int(nbytes)))
+
+
+def spfc_status(ctx) -> int:
+    f = ctypes.c_uint32()
+    _check("spfc_status", load_library().spfc_status(ctx, ctypes.byref(f)))
+    return f.value
+
+
+def spfc_profile(ctx, enable: bool):
+    _check("spfc_profile", load_library().spfc_profile(ctx, 1 if enable else 0))
+
+
+def spfc_kernel_times(ctx) -> list:
+    cap = 8
+    names = (ctypes.c_char_p * cap)()
+    avg = (ctypes.c_double * cap)()
+    nl = (ctypes.c_int64 * cap)()
+    by = (ctypes.c_double * cap)()
+    cnt = ctypes.c_int()
+    _check("spfc_kernel_times", load_library().spfc_kernel_times(ctx, cap, names, avg, nl, by, ctypes.byref(cnt)))
+    return [{"name": names[i].decode(), "avg_ms": avg[i], "launches": nl[i], "bytes": by[i]}
+            for i in range(min(cnt.value, cap))]
+
+
+def spfc_strerror(status: int) -> str:
+    return strerror(status)
+
+
+def spfc_destroy(ctx):
+    _check("spfc_destroy", load_library().spfc_destroy(ctx))
+
+
+# ------------------------------------------------------------------ convenience class (PyTorch memory + stream)
+
+class Solver:
+    """One run on the current HIP device.  phi0: array of shape (n_y, n_x) or
+    (n_z, n_y, n_x) (x fastest), copied to the device as float64."""
+
+    def __init__(self, n, L, phi0, epsilon, c4=1.0, startup="sav1", precision="fp64", history=4096,
+                 energy_tol=0.0, stream=None):
+        import numpy as np
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a HIP device")
+        load_library()
+        self.torch = torch
+        self.n = tuple(int(v) for v in n)
+        self.grid = make_grid(n, L)
+        self.params = make_params(epsilon, c4, startup, precision, history, energy_tol)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = spfc_workspace_bytes(self.grid, self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ws_bytes = nbytes
+        shape = tuple(reversed(self.n))
+        if isinstance(phi0, torch.Tensor):
+            p0 = phi0.to(device="cuda", dtype=torch.float64).contiguous()
+        else:
+            p0 = torch.from_numpy(np.ascontiguousarray(np.asarray(phi0, dtype=np.float64))).to("cuda")
+        if tuple(p0.shape) != shape:
+            raise ValueError(f"phi0 shape {tuple(p0.shape)} != {shape}")
+        self.ctx = spfc_init(self.grid, self.params, p0.data_ptr(), self._ws_ptr, nbytes, self.stream.cuda_stream)
+        del p0
+
+    def step(self, dt, n=1):
+        spfc_step(self.ctx, dt, n)
+
+    def energy(self):
+        return spfc_energy(self.ctx)
+
+    def mass(self):
+        return spfc_mass(self.ctx)
+
+    def history(self, first, count):
+        return spfc_history(self.ctx, first, count)
+
+    def step_count(self):
+        return spfc_step_count(self.ctx)
+
+    def status(self):
+        return spfc_status(self.ctx)
+
+    def phi(self, dtype="fp64"):
+        torch = self.torch
+        shape = tuple(reversed(self.n))
+        out = torch.empty(shape, dtype=torch.float64 if dtype == "fp64" else torch.float32, device="cuda")
+        spfc_get_phi(self.ctx, out.data_ptr(), SPFC_FP64 if dtype == "fp64" else SPFC_FP32)
+        self.stream.synchronize()
+        return out
+
+    def save_state(self):
+        torch = self.torch
+        nb = spfc_state_bytes(self.ctx)
+        buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        spfc_save_state(self.ctx, buf.data_ptr(), nb)
+        return buf
+
+    def load_state(self, buf):
+        spfc_load_state(self.ctx, buf.data_ptr(), buf.numel())
+
+    def profile(self, enable=True):
+        spfc_profile(self.ctx, enable)
+
+    def kernel_times(self):
+        return spfc_kernel_times(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            spfc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,178 @@
+// Types shared by the host driver and the kernels.
+#pragma once
+
+#include <cstdint>
+
+#include "fft_core.hpp"
+
+namespace spfc {
+
+// Grid geometry and model constants in the form the kernels use.
+struct Geo {
+    int dim;
+    int nx, ny, nz;       // points per axis (nz = 1 in 2-D)
+    int nxh;              // nx/2 + 1: kept x wavenumbers of the half spectrum
+    double k0x, k0y, k0z; // 2 pi / L_j
+    double a, c4;
+    double inv_npts;      // 1 / (nx ny nz)
+    double cell;          // h^d
+    double volume;        // |Omega|
+    double pscale;        // |Omega| / N_total^2: inner product from two spectra (Parseval)
+    double e1_const;      // (1 + 1/c4) |Omega|
+};
+
+// Device-resident scalars of the run.  Written by single lanes of the finalize
+// code only (vector stores), read by the next launches.
+struct DevScalars {
+    double xi;            // xi of the latest solved step (used by the pending update)
+    double r_n;           // r of the newest state of the pair
+    double r_nm1;         // r of the older state of the pair
+    double energy_prev;   // modified energy of the newest finalized record
+    double E1, p1, p2, ppsi, S;   // latest step
+    double q_E1;          // E_1 of the latest query / start-up pass
+    double q_norm[4];     // latest ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2
+    double mean;          // mean of the newest state
+    double mean_raw;      // Re X(k = 0), written by the pass that forms X
+    unsigned int flags;   // sticky SPFC_FLAG_* bits
+    unsigned int ticket;  // arrival counter of the solve pass (0 between launches)
+    long long last_record;
+    double pad[4];
+};
+
+struct Record {
+    double energy, mean, r, xi, E1, p1, S, reserved;
+};
+
+enum : unsigned int {
+    FLAG_NONFINITE = 1u,
+    FLAG_E1_BELOW_OMEGA = 2u,
+    FLAG_P1_POSITIVE = 4u,
+    FLAG_ENERGY_RISE = 8u,
+};
+
+// ------------------------------------------------------------------ kernel arguments
+
+// Spectral state -> (optional pending update) -> gradient spectra -> inverse
+// transform along the contiguous (last) axis, written rotated [L][a][b].
+template <typename T>
+struct SpecInvArgs {
+    const cpx<T>* cur;      // X of the pair (or phi^n before the update)
+    const cpx<T>* prev;     // Y of the pair (or phi^{n-1} before the update)
+    const cpx<T>* nhat;     // N of the previous step (update only)
+    cpx<T>* out_new;        // where the updated state goes (update only)
+    cpx<T>* out[3];         // d gradient fields
+    const cpx<T>* tw;
+    int tws;
+    int nlines, B;          // lines = A * B, b fastest
+    int G;                  // lines per workgroup
+    int update;             // apply the pending update
+    double ua0, ua1, ua2, udt;   // weights and dt of the step that produced nhat
+    const double* xi;       // its xi (device)
+    double e1, e2;          // phihat = e1 X + e2 Y
+    int want_grad;          // 0: only the energy partials (no transform, no output)
+    double* part;           // 4 partials per workgroup
+    double* mean_raw;
+    Geo geo;
+};
+
+// Rows of the half spectrum along x -> C2R (two real rows per complex line) ->
+// pointwise SPFC flux -> R2C, written rotated [X][rows].
+template <typename T>
+struct RealArgs {
+    const cpx<T>* in[3];
+    cpx<T>* out[3];
+    const cpx<T>* tw;
+    int tws;
+    int nrows;              // rows (a, b) in the input, b fastest
+    int G;                  // row groups per workgroup
+    double* part;           // E_1 partial per workgroup
+    Geo geo;
+};
+
+// Flux spectra along the last axis -> forward transform -> N, the two solves
+// and the inner products; the last workgroup finishes the step.
+template <typename T>
+struct SpecFwdArgs {
+    const cpx<T>* in[3];
+    const cpx<T>* X;
+    const cpx<T>* Y;
+    cpx<T>* nhat;           // SOLVE: N out
+    cpx<T>* ghost_out;      // GHOST: phi^{-1} out
+    const cpx<T>* tw;
+    int tws;
+    int nlines, B, G;
+    double a0, a1, a2, dt, e1, e2;
+    double* partC;          // 3 partials per workgroup (this pass)
+    const double* partA;    // 4 per workgroup of the spectral inverse pass
+    int nA;
+    const double* partB;    // 1 per workgroup of the real pass
+    int nB;
+    DevScalars* sc;
+    Record* hist;
+    long long hist_cap;
+    long long step;         // index of the state X
+    int check_rise;
+    double energy_tol;
+    Geo geo;
+};
+
+// Generic batched line transform along the contiguous axis, with the output
+// written in place ([a][b][L]), swapped ([a][L][b]) or rotated ([L][a][b]).
+enum { OUT_KEEP = 0, OUT_SWAP = 1, OUT_ROTATE = 2 };
+
+template <typename T>
+struct PassArgs {
+    const cpx<T>* in[3];
+    cpx<T>* out[3];
+    const cpx<T>* tw;
+    int tws;
+    int nlines, B, G;
+};
+
+// Real rows <-> half-spectrum rows (set-up and queries).
+template <typename T>
+struct RowArgs {
+    const void* in;
+    void* out;
+    const cpx<T>* tw;
+    int tws;
+    int nrows, G;
+    double scale;
+};
+
+// Pending update applied elementwise (end of a run of steps).
+template <typename T>
+struct UpdateArgs {
+    const cpx<T>* cur;
+    const cpx<T>* prev;
+    const cpx<T>* nhat;
+    cpx<T>* out_new;
+    long long total;         // complex entries of one spectrum
+    int NL, B;               // line length (last axis) and b extent
+    double ua0, ua1, ua2, udt;
+    const double* xi;
+    double* part;            // 4 partials per workgroup
+    double* mean_raw;
+    Geo geo;
+};
+
+enum { FWD_SOLVE = 0, FWD_GHOST = 1 };
+
+enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RESTART = 4 };
+
+struct FinalizeArgs {
+    int mode;
+    const double* partA;
+    int nA;
+    const double* partB;
+    int nB;
+    DevScalars* sc;
+    Record* hist;
+    long long hist_cap;
+    long long step;
+    int check_rise;
+    double energy_tol;
+    Geo geo;
+};
+
+}  // namespace spfc

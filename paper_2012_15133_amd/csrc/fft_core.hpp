@@ -1,0 +1,267 @@
+// Line FFT building blocks for gfx950: complex arithmetic, register radix-2/4/8/16
+// butterflies and a Stockham autosort schedule exchanging through LDS.
+//
+// A line of length N (power of two, 8..1024) is owned by P = N / E threads of
+// one workgroup; thread t keeps E complex values in registers.  On entry and on
+// exit v[m] is element t + P*m of the line (natural order in both domains), so
+// the first pass can load straight from HBM with coalesced accesses and the last
+// pass result can be used in registers (pointwise work, spectral symbols) without
+// another trip through LDS.  Between passes the values go through LDS.
+//
+// Each pass with radix R and span Ns (product of the earlier radices) does
+// N/R butterflies; butterfly b reads elements b + r*N/R (r = 0..R-1), scales
+// input r by exp(dir 2 pi i r (b mod Ns) / (Ns R)), runs a length-R DFT and
+// writes output r to position (b / Ns) * Ns * R + (b mod Ns) + r * Ns.
+// This is the Stockham formulation of the Cooley-Tukey FFT.
+//
+// The per-thread steps are __host__ __device__ so that a host program can run
+// the schedule thread by thread (the CPU tests do) with the same code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace spfc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ inline cpx<T> mk(T a, T b) {
+    cpx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__host__ __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__host__ __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__host__ __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__host__ __device__ inline cpx<T> scale(cpx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <typename T>
+__host__ __device__ inline cpx<T> conj(cpx<T> a) { return mk<T>(a.x, -a.y); }
+// a * (s i), s = +1 or -1
+template <int S, typename T>
+__host__ __device__ inline cpx<T> mul_si(cpx<T> a) {
+    return S > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+// ------------------------------------------------------------------ schedule
+
+// E values per thread: 16 for N >= 16, else N.  Radices: 16 while at least 16
+// remain, then the leftover factor (2, 4 or 8) as the last pass.
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+template <int N>
+struct Plan {
+    static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "line length must be a power of two >= 8");
+    static constexpr int E = N >= 16 ? 16 : N;
+    static constexpr int P = N / E;
+    static constexpr int n16 = ilog2(N) / 4;          // radix-16 passes
+    static constexpr int rest = 1 << (ilog2(N) % 4);  // leftover radix (1 = none)
+    static constexpr int NP = n16 + (rest > 1 ? 1 : 0);
+    static constexpr int radix(int p) { return p < n16 ? 16 : rest; }
+    static constexpr int span(int p) {
+        int s = 1;
+        for (int q = 0; q < p; ++q) s *= radix(q);
+        return s;
+    }
+};
+
+// ------------------------------------------------------------------ small DFTs
+// DIR = -1: X[k] = sum x[n] exp(-2 pi i n k / R); DIR = +1: exp(+...).  In place,
+// natural order in and out.
+
+template <int DIR, typename T>
+__host__ __device__ inline void dft2(cpx<T>& a, cpx<T>& b) {
+    cpx<T> t = a - b;
+    a = a + b;
+    b = t;
+}
+
+template <int DIR, typename T>
+__host__ __device__ inline void dft4(cpx<T>& x0, cpx<T>& x1, cpx<T>& x2, cpx<T>& x3) {
+    cpx<T> t0 = x0 + x2, t1 = x0 - x2, t2 = x1 + x3, t3 = mul_si<DIR>(x1 - x3);
+    x0 = t0 + t2;
+    x2 = t0 - t2;
+    x1 = t1 + t3;
+    x3 = t1 - t3;
+}
+
+template <int DIR, typename T>
+__host__ __device__ inline void dft8(cpx<T> (&x)[8]) {
+    // n = 2 n1 + n2: two length-4 DFTs over n1, twiddle exp(DIR 2 pi i n2 k1 / 8), length-2 over n2.
+    const T h = T(0.70710678118654752440);
+    cpx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    cpx<T> o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = mk<T>(h * o1.x - T(DIR) * h * o1.y, T(DIR) * h * o1.x + h * o1.y);   // * h (1 + DIR i)
+    o2 = mul_si<DIR>(o2);                                                      // * DIR i
+    o3 = mk<T>(-h * o3.x - T(DIR) * h * o3.y, T(DIR) * h * o3.x - h * o3.y);  // * h (-1 + DIR i)
+    x[0] = e0 + o0; x[4] = e0 - o0;
+    x[1] = e1 + o1; x[5] = e1 - o1;
+    x[2] = e2 + o2; x[6] = e2 - o2;
+    x[3] = e3 + o3; x[7] = e3 - o3;
+}
+
+template <int DIR, typename T>
+__host__ __device__ inline void dft16(cpx<T> (&x)[16]) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle exp(DIR 2 pi i n2 k1 / 16), DFT4 over n2.
+    const T c1 = T(0.92387953251128675613);  // cos(pi/8)
+    const T s1 = T(0.38268343236508977173);  // sin(pi/8)
+    const T h = T(0.70710678118654752440);   // cos(pi/4)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<DIR>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
+    // now x[4 k1 + n2] = Y[n2][k1]; apply W16^(n2 k1) with W16 = exp(DIR 2 pi i / 16)
+    const T cs[10] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1};   // cos(pi j / 8)
+    const T sn[10] = {T(0), s1, h, c1, T(1), c1, h, s1, T(0), -s1};       // sin(pi j / 8)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) {
+            const int j = n2 * k1;
+            cpx<T> w = mk<T>(cs[j], T(DIR) * sn[j]);
+            x[4 * k1 + n2] = x[4 * k1 + n2] * w;
+        }
+    }
+    cpx<T> y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cpx<T> a0 = x[4 * k1], a1 = x[4 * k1 + 1], a2 = x[4 * k1 + 2], a3 = x[4 * k1 + 3];
+        dft4<DIR>(a0, a1, a2, a3);
+        y[k1] = a0;
+        y[k1 + 4] = a1;
+        y[k1 + 8] = a2;
+        y[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = y[i];
+}
+
+template <int R, int DIR, typename T>
+__host__ __device__ inline void dftR(cpx<T> (&a)[R]) {
+    if constexpr (R == 2) {
+        dft2<DIR>(a[0], a[1]);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(a[0], a[1], a[2], a[3]);
+    } else if constexpr (R == 8) {
+        dft8<DIR>(a);
+    } else {
+        static_assert(R == 16, "radix must be 2, 4, 8 or 16");
+        dft16<DIR>(a);
+    }
+}
+
+// ------------------------------------------------------------------ passes
+// Twiddle table: tw[j] = exp(-2 pi i j / ntab) for j < ntab, ntab = N * tws.
+
+template <typename T, int N, int DIR, int C, int PASS>
+__host__ __device__ inline void pass_compute(cpx<T> (&v)[C][Plan<N>::E], int t, const cpx<T>* __restrict__ tw,
+                                             int tws) {
+    constexpr int E = Plan<N>::E, P = Plan<N>::P;
+    constexpr int R = Plan<N>::radix(PASS), Ns = Plan<N>::span(PASS), NB = E / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        cpx<T> w[R];
+        if constexpr (Ns > 1) {
+            const int k = (t + P * u) & (Ns - 1);
+            const int step = k * (N / (Ns * R)) * tws;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cpx<T> q = tw[r * step];
+                w[r] = DIR > 0 ? conj(q) : q;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            cpx<T> a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                a[r] = v[c][u + r * NB];
+                if constexpr (Ns > 1) {
+                    if (r > 0) a[r] = a[r] * w[r];
+                }
+            }
+            dftR<R, DIR>(a);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c][u + r * NB] = a[r];
+        }
+    }
+}
+
+// LDS line stride: N plus one element of padding per 16, which breaks the
+// power-of-two strides of the stores into different banks.
+template <int N>
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+template <int N>
+struct LdsLine {
+    static constexpr int size = N + N / 16;
+};
+
+template <typename T, int N, int C, int PASS>
+__host__ __device__ inline void pass_store(const cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t) {
+    constexpr int E = Plan<N>::E, P = Plan<N>::P;
+    constexpr int R = Plan<N>::radix(PASS), Ns = Plan<N>::span(PASS), NB = E / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int b = t + P * u;
+        const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[c * LdsLine<N>::size + lds_pad<N>(base + r * Ns)] = v[c][u + r * NB];
+        }
+    }
+}
+
+template <typename T, int N, int C, int PASS>
+__host__ __device__ inline void pass_load(cpx<T> (&v)[C][Plan<N>::E], const cpx<T>* lds, int t) {
+    constexpr int E = Plan<N>::E, P = Plan<N>::P;
+    constexpr int R = Plan<N>::radix(PASS), NB = E / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int b = t + P * u;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c][u + r * NB] = lds[c * LdsLine<N>::size + lds_pad<N>(b + r * (N / R))];
+        }
+    }
+}
+
+// natural-order store / load of the whole line (element t + P m)
+template <typename T, int N, int C>
+__host__ __device__ inline void line_store(const cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int m = 0; m < Plan<N>::E; ++m) lds[c * LdsLine<N>::size + lds_pad<N>(t + Plan<N>::P * m)] = v[c][m];
+}
+
+// Whole transform on the device: all threads of the workgroup must call it
+// (it contains workgroup barriers).  lds points at this thread group's
+// C * LdsLine<N>::size elements.
+template <typename T, int N, int DIR, int C, int PASS = 0>
+__device__ inline void fft_run(cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ tw,
+                               int tws) {
+    if constexpr (PASS == 0) {
+        pass_compute<T, N, DIR, C, 0>(v, t, tw, tws);
+        if constexpr (Plan<N>::NP > 1) fft_run<T, N, DIR, C, 1>(v, lds, t, tw, tws);
+    } else {
+        __syncthreads();
+        pass_store<T, N, C, PASS - 1>(v, lds, t);
+        __syncthreads();
+        pass_load<T, N, C, PASS>(v, lds, t);
+        pass_compute<T, N, DIR, C, PASS>(v, t, tw, tws);
+        if constexpr (PASS + 1 < Plan<N>::NP) fft_run<T, N, DIR, C, PASS + 1>(v, lds, t, tw, tws);
+    }
+}
+
+}  // namespace spfc

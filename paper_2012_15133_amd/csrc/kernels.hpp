@@ -1,0 +1,579 @@
+// HIP kernels of one SAV-BDF2 step of the square phase field crystal equation
+// (arXiv 2012.15133, Section 2.3) and of the set-up / query transforms.
+//
+// Spectral state: the half spectrum (x wavenumbers 0..nx/2) stored [kx][ky]
+// (2-D) or [kx][ky][kz] (3-D), last axis contiguous.  One step is
+//   2-D: spec_inv (along y) -> real_pass (along x) -> spec_fwd (along y)
+//   3-D: spec_inv (z) -> pass (y) -> real_pass (x) -> pass (y) -> spec_fwd (z)
+// Every kernel reads whole lines along the contiguous axis of its input and
+// writes its output with the axes rotated so that the next kernel again reads
+// contiguous lines.  Nothing but the state, N and the transform
+// intermediates touches HBM; symbols come from indices, in registers.
+#pragma once
+
+#include "common.hpp"
+
+namespace spfc {
+
+// ------------------------------------------------------------------ symbols (Section 2.1)
+
+// odd-order symbol 2 pi mt / L, Nyquist mode dropped
+__device__ inline double sym1(int m, int n, double k0) {
+    if (2 * m == n) return 0.0;
+    return k0 * (double)(2 * m < n ? m : m - n);
+}
+// even-order symbol (2 pi mt / L)^2, Nyquist kept
+__device__ inline double sym2(int m, int n, double k0) {
+    const double v = k0 * (double)(2 * m <= n ? m : m - n);
+    return v * v;
+}
+// Hermitian weight of x wavenumber kx in a sum over the full spectrum
+__device__ inline double hweight(int kx, int nx) { return (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0; }
+
+// ------------------------------------------------------------------ reductions (FP64, fixed order)
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup and store them at dst[0..NV-1] (thread 0).
+template <int NV>
+__device__ inline void block_sum_store(double (&acc)[NV], double* dst) {
+    __shared__ double red[NV][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[i][wave] = acc[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[i][w];
+            dst[i] = s;
+        }
+    }
+}
+
+// Sum the NV-strided partials part[j*NV + i], j < n, over the workgroup: every
+// thread reads a fixed subset (vector loads), then a fixed-order tree.  Result
+// valid in thread 0.
+template <int NV>
+__device__ inline void block_sum_partials(const double* part, int n, double (&out)[NV]) {
+    __shared__ double red[NV][16];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += __builtin_nontemporal_load(part + (size_t)j * NV + i);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[i][wave] = acc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[i][w];
+        out[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------ index helpers
+
+// wavenumber indices of element e of spectral line `line` ([a][b][L] layout)
+template <int DIM>
+__device__ inline void spec_index(int line, int B, int e, int& kx, int& ky, int& kz) {
+    if constexpr (DIM == 2) {
+        kx = line;
+        ky = e;
+        kz = 0;
+    } else {
+        kx = line / B;
+        ky = line - kx * B;
+        kz = e;
+    }
+}
+
+template <int DIM>
+__device__ inline void spec_symbols(const Geo& g, int kx, int ky, int kz, double& k2, double (&k1)[3]) {
+    k1[0] = sym1(kx, g.nx, g.k0x);
+    k1[1] = sym1(ky, g.ny, g.k0y);
+    k2 = sym2(kx, g.nx, g.k0x) + sym2(ky, g.ny, g.k0y);
+    if constexpr (DIM == 3) {
+        k1[2] = sym1(kz, g.nz, g.k0z);
+        k2 += sym2(kz, g.nz, g.k0z);
+    } else {
+        k1[2] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ spectral inverse pass
+
+// One group of P threads per spectral line.  Optional pending update
+//   X = (udt xi (-|k|^2) N + ua1 C + ua2 P) / (ua0 + udt |k|^2 (a + |k|^4)),  Y = C
+// (eq. scheme-SAV-1 solved for phi^{n+1}), else X = C, Y = P.  Partials of
+// ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2 (modified energy,
+// eq. discrete energy; E_N, eq. energy-discrete-spectral).  Then
+// Z_j = i kappa1_j (e1 X + e2 Y) and the inverse transform along the line.
+template <typename T, int NL, int DIM>
+__global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
+    constexpr int E = Plan<NL>::E, P = Plan<NL>::P, C = DIM;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int line = blockIdx.x * p.G + g;
+    const bool act = line < p.nlines;
+    const Geo& geo = p.geo;
+    const size_t lbase = (size_t)(act ? line : 0) * NL;
+    const double xi = p.update ? p.xi[0] : 0.0;
+
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    cpx<T> v[C][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int e = t + P * m;
+        cpx<T> X = mk<T>(0, 0), Y = mk<T>(0, 0);
+        int kx = 0, ky = 0, kz = 0;
+        double k2 = 0.0, k1[3] = {0.0, 0.0, 0.0};
+        if (act) {
+            spec_index<DIM>(line, p.B, e, kx, ky, kz);
+            spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
+            const cpx<T> cur = p.cur[lbase + e];
+            if (p.update) {
+                const cpx<T> prv = p.prev[lbase + e];
+                const cpx<T> nh = p.nhat[lbase + e];
+                const double A = p.ua0 + p.udt * k2 * (geo.a + k2 * k2);
+                const T f1 = T(-p.udt * xi * k2 / A), f2 = T(p.ua1 / A), f3 = T(p.ua2 / A);
+                X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
+                Y = cur;
+                p.out_new[lbase + e] = X;
+            } else {
+                X = cur;
+                Y = p.prev[lbase + e];
+            }
+            const double w = hweight(kx, geo.nx);
+            const double Lk = geo.a + k2 * k2;
+            const double xx = (double)X.x * X.x + (double)X.y * X.y;
+            const double zx = 2.0 * X.x - Y.x, zy = 2.0 * X.y - Y.y;
+            acc[0] += w * Lk * xx;
+            acc[1] += w * Lk * (zx * zx + zy * zy);
+            acc[2] += w * xx;
+            acc[3] += w * k2 * k2 * xx;
+            if (line == 0 && e == 0) p.mean_raw[0] = (double)X.x;
+        }
+        const T h1 = T(p.e1), h2 = T(p.e2);
+        const cpx<T> ph = mk<T>(h1 * X.x + h2 * Y.x, h1 * X.y + h2 * Y.y);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const T kk = T(k1[j]);
+            v[j][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1_j phihat
+        }
+    }
+    if (p.want_grad) {
+        fft_run<T, NL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                cpx<T>* o = p.out[j];
+#pragma unroll
+                for (int m = 0; m < E; ++m) o[(size_t)(t + P * m) * p.nlines + line] = v[j][m];
+            }
+        }
+    }
+    block_sum_store<4>(acc, p.part + 4 * blockIdx.x);
+}
+
+// ------------------------------------------------------------------ real-space pass
+
+// Packing of real rows into complex lines.  2-D: one row per group, line 0 =
+// g_x + i g_y.  3-D: two rows per group, lines (g_x + i g_y)(row 0),
+// (g_x + i g_y)(row 1), g_z(row 0) + i g_z(row 1).
+template <int DIM>
+struct RealPack {
+    static constexpr int C = DIM == 2 ? 1 : 3;
+    static constexpr int RPG = DIM == 2 ? 1 : 2;
+    __device__ static constexpr int fa(int c) { return DIM == 2 ? 0 : (c < 2 ? 0 : 2); }
+    __device__ static constexpr int fb(int c) { return DIM == 2 ? 1 : (c < 2 ? 1 : 2); }
+    __device__ static constexpr int ra(int c) { return DIM == 2 ? 0 : (c == 1 ? 1 : 0); }
+    __device__ static constexpr int rb(int c) { return DIM == 2 ? 0 : (c == 0 ? 0 : 1); }
+};
+
+// Load element e (0..N-1) of the complex line whose real part is the real row
+// with half spectrum h1 and whose imaginary part has half spectrum h2:
+// W(e) = H1(e) + i H2(e), H(e) = conj(H(N - e)) above N/2; the self-conjugate
+// bins 0 and N/2 keep their real parts only.
+template <typename T, int N>
+__device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e) {
+    cpx<T> a, b;
+    if (2 * e <= N) {
+        a = h1[e];
+        b = h2[e];
+        if (e == 0 || 2 * e == N) {
+            a.y = T(0);
+            b.y = T(0);
+        }
+    } else {
+        a = conj(h1[N - e]);
+        b = conj(h2[N - e]);
+    }
+    return mk<T>(a.x - b.y, a.y + b.x);
+}
+
+// Gradient rows (half spectra along x) -> C2R -> s = |grad phihat|^2,
+// E_1 partial sum (c4/4) s^2 - s, q = c4 s grad phihat (eq. nonlinear chem pot-1) ->
+// R2C -> flux spectra written rotated [kx][rows].  FWD = false: E_1 only.
+template <typename T, int NX, int DIM, bool FWD>
+__global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
+    using PK = RealPack<DIM>;
+    constexpr int E = Plan<NX>::E, P = Plan<NX>::P, C = PK::C, RPG = PK::RPG;
+    constexpr int NXH = NX / 2 + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * C * LdsLine<NX>::size;
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int row0 = (blockIdx.x * p.G + g) * RPG;
+    const bool act = row0 < p.nrows;
+    const Geo& geo = p.geo;
+
+    cpx<T> v[C][E];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const cpx<T>* h1 = p.in[PK::fa(c)] + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
+        const cpx<T>* h2 = p.in[PK::fb(c)] + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+    }
+    fft_run<T, NX, +1, C>(v, lds, t, p.tw, p.tws);
+
+    const T sc = T(geo.inv_npts), c4 = T(geo.c4);
+    const double qc4 = 0.25 * geo.c4;
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if constexpr (DIM == 2) {
+            const T gx = v[0][m].x * sc, gy = v[0][m].y * sc;
+            const T s = gx * gx + gy * gy;
+            acc[0] += qc4 * (double)s * (double)s - (double)s;
+            const T q = c4 * s;
+            v[0][m] = mk<T>(q * gx, q * gy);
+        } else {
+            const T ax = v[0][m].x * sc, ay = v[0][m].y * sc, az = v[2][m].x * sc;
+            const T bx = v[1][m].x * sc, by = v[1][m].y * sc, bz = v[2][m].y * sc;
+            const T sa = ax * ax + ay * ay + az * az;
+            const T sb = bx * bx + by * by + bz * bz;
+            acc[0] += qc4 * (double)sa * (double)sa - (double)sa + qc4 * (double)sb * (double)sb - (double)sb;
+            const T qa = c4 * sa, qb = c4 * sb;
+            v[0][m] = mk<T>(qa * ax, qa * ay);
+            v[1][m] = mk<T>(qb * bx, qb * by);
+            v[2][m] = mk<T>(qa * az, qb * bz);
+        }
+    }
+    if (!act) acc[0] = 0.0;
+
+    if constexpr (FWD) {
+        fft_run<T, NX, -1, C>(v, lds, t, p.tw, p.tws);
+        // split V = Q1 + i Q2 into the two half spectra: Q1(k) = (V(k) + conj V(-k)) / 2,
+        // Q2(k) = (V(k) - conj V(-k)) / (2 i).
+        __syncthreads();
+        line_store<T, NX, C>(v, lds, t);
+        __syncthreads();
+        if (act) {
+            const T half = T(0.5);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                cpx<T>* o1 = p.out[PK::fa(c)];
+                cpx<T>* o2 = p.out[PK::fb(c)];
+                const int r1 = row0 + PK::ra(c), r2 = row0 + PK::rb(c);
+#pragma unroll
+                for (int m = 0; m <= E / 2; ++m) {
+                    const int k = t + P * m;
+                    if (m == E / 2 && t != 0) break;
+                    const cpx<T> Vk = lds[c * LdsLine<NX>::size + lds_pad<NX>(k)];
+                    const cpx<T> Vm = lds[c * LdsLine<NX>::size + lds_pad<NX>((NX - k) & (NX - 1))];
+                    const cpx<T> q1 = mk<T>(half * (Vk.x + Vm.x), half * (Vk.y - Vm.y));
+                    const cpx<T> q2 = mk<T>(half * (Vk.y + Vm.y), half * (Vm.x - Vk.x));
+                    o1[(size_t)k * p.nrows + r1] = q1;
+                    o2[(size_t)k * p.nrows + r2] = q2;
+                }
+            }
+        }
+    }
+    block_sum_store<1>(acc, p.part + blockIdx.x);
+}
+
+// ------------------------------------------------------------------ generic line pass
+
+template <typename T, int NL, int DIR, int OMODE, int C>
+__global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
+    constexpr int E = Plan<NL>::E, P = Plan<NL>::P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int line = blockIdx.x * p.G + g;
+    const bool act = line < p.nlines;
+    const size_t lbase = (size_t)(act ? line : 0) * NL;
+    cpx<T> v[C][E];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][lbase + t + P * m] : mk<T>(0, 0);
+    fft_run<T, NL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+    if (!act) return;
+    const int a = line / p.B, b = line - a * p.B;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        cpx<T>* o = p.out[c];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = t + P * m;
+            size_t idx;
+            if constexpr (OMODE == OUT_KEEP) idx = lbase + e;
+            else if constexpr (OMODE == OUT_SWAP) idx = ((size_t)a * NL + e) * p.B + b;
+            else idx = (size_t)e * p.nlines + line;
+            o[idx] = v[c][m];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ spectral forward pass + solve
+
+// Finish one step from the reduced sums (one lane).  Follows Section 2.3 in the
+// form xi = r^{n+1} / sqrt(E_1): with phi^{n+1} = dt xi b1 + b2, b1 = A^-1 Delta N,
+// b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
+//   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
+// p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1).
+__device__ inline void finish_step(double E1sum, const double (&nA)[4],
+                                   const double (&sC)[3], DevScalars* sc, Record* hist, long long cap,
+                                   long long step, double a0, double a1, double a2, double dt, int check_rise,
+                                   double tol, const Geo& geo) {
+    const double E1 = geo.cell * E1sum + geo.e1_const;
+    const double n0 = geo.pscale * nA[0], n1 = geo.pscale * nA[1];
+    const double p1 = geo.pscale * sC[0], p2 = geo.pscale * sC[1], pp = geo.pscale * sC[2];
+    const double rn = sc->r_n, rnm1 = sc->r_nm1;
+    const double S = sqrt(E1);
+    const double rho = a1 * rn + a2 * rnm1;
+    const double xi = (rho + (a0 * p2 - pp) / (2.0 * S)) / (a0 * (S - dt * p1 / (2.0 * S)));
+    const double rnew = xi * S;
+    const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
+    const double mean = sc->mean_raw * geo.inv_npts;
+    unsigned int fl = sc->flags;
+    if (!isfinite(E1) || !isfinite(p1) || !isfinite(p2) || !isfinite(pp) || !isfinite(xi) || !isfinite(energy))
+        fl |= FLAG_NONFINITE;
+    if (E1 < geo.volume * (1.0 - 1e-12)) fl |= FLAG_E1_BELOW_OMEGA;
+    if (p1 > 0.0) fl |= FLAG_P1_POSITIVE;
+    if (check_rise && energy > sc->energy_prev * (1.0 + tol)) fl |= FLAG_ENERGY_RISE;
+    Record* rc = hist + (step % cap);
+    rc->energy = energy;
+    rc->mean = mean;
+    rc->r = rn;
+    Record* rn1 = hist + ((step + 1) % cap);
+    rn1->energy = 0.0;
+    rn1->mean = 0.0;
+    rn1->r = rnew;
+    rn1->xi = xi;
+    rn1->E1 = E1;
+    rn1->p1 = p1;
+    rn1->S = S;
+    rn1->reserved = 0.0;
+    sc->xi = xi;
+    sc->r_nm1 = rn;
+    sc->r_n = rnew;
+    sc->energy_prev = energy;
+    sc->E1 = E1;
+    sc->p1 = p1;
+    sc->p2 = p2;
+    sc->ppsi = pp;
+    sc->S = S;
+    sc->mean = mean;
+    sc->flags = fl;
+    sc->last_record = step;
+}
+
+template <typename T, int NL, int DIM, int MODE>
+__global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
+    constexpr int E = Plan<NL>::E, P = Plan<NL>::P, C = DIM;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int line = blockIdx.x * p.G + g;
+    const bool act = line < p.nlines;
+    const Geo& geo = p.geo;
+    const size_t lbase = (size_t)(act ? line : 0) * NL;
+
+    cpx<T> v[C][E];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[j][m] = act ? p.in[j][lbase + t + P * m] : mk<T>(0, 0);
+    fft_run<T, NL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = t + P * m;
+            int kx, ky, kz;
+            double k2, k1[3];
+            spec_index<DIM>(line, p.B, e, kx, ky, kz);
+            spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
+            const cpx<T> X = p.X[lbase + e], Y = p.Y[lbase + e];
+            const double phx = p.e1 * X.x + p.e2 * Y.x, phy = p.e1 * X.y + p.e2 * Y.y;
+            // div of the flux: sum_j i kappa1_j Q_j; N = -div - 2 |k|^2 phihat
+            double dx = 0.0, dy = 0.0;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                dx += k1[j] * (double)v[j][m].x;
+                dy += k1[j] * (double)v[j][m].y;
+            }
+            const double Nx = dy - 2.0 * k2 * phx;
+            const double Ny = -dx - 2.0 * k2 * phy;
+            if constexpr (MODE == FWD_SOLVE) {
+                const double psx = p.a1 * X.x + p.a2 * Y.x, psy = p.a1 * X.y + p.a2 * Y.y;
+                const double A = p.a0 + p.dt * k2 * (geo.a + k2 * k2);
+                const double w = hweight(kx, geo.nx);
+                const double re = Nx * psx + Ny * psy;
+                acc[0] += -w * k2 * (Nx * Nx + Ny * Ny) / A;
+                acc[1] += w * re / A;
+                acc[2] += w * re;
+                p.nhat[lbase + e] = mk<T>(T(Nx), T(Ny));
+            } else {
+                // phi^{-1} = phi^0 - dt Delta_N (N + L_N phi^0)  (eq. scheme-SAV-initial-1)
+                const double Lk = geo.a + k2 * k2;
+                p.ghost_out[lbase + e] = mk<T>(T(X.x + p.dt * k2 * (Nx + Lk * X.x)), T(X.y + p.dt * k2 * (Ny + Lk * X.y)));
+            }
+        }
+    }
+    if constexpr (MODE == FWD_SOLVE) {
+        block_sum_store<3>(acc, p.partC + 3 * blockIdx.x);
+        // last workgroup to arrive reduces every partial of the step and finishes it
+        __shared__ int is_last;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned int prev = atomicAdd(&p.sc->ticket, 1u);
+            is_last = (prev == gridDim.x - 1) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!is_last) return;
+        __threadfence();
+        double sA[4], sB[1], sC[3];
+        block_sum_partials<4>(p.partA, p.nA, sA);
+        block_sum_partials<1>(p.partB, p.nB, sB);
+        block_sum_partials<3>(p.partC, gridDim.x, sC);
+        if (tid == 0) {
+            finish_step(sB[0], sA, sC, p.sc, p.hist, p.hist_cap, p.step, p.a0, p.a1, p.a2, p.dt,
+                        p.check_rise, p.energy_tol, geo);
+            p.sc->ticket = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ elementwise pending update
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
+    const Geo& geo = p.geo;
+    const double xi = p.xi[0];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < p.total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int line = (int)(i / p.NL), e = (int)(i - (long long)line * p.NL);
+        int kx, ky, kz;
+        double k2, k1[3];
+        spec_index<DIM>(line, p.B, e, kx, ky, kz);
+        spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
+        const cpx<T> cur = p.cur[i], prv = p.prev[i], nh = p.nhat[i];
+        const double A = p.ua0 + p.udt * k2 * (geo.a + k2 * k2);
+        const T f1 = T(-p.udt * xi * k2 / A), f2 = T(p.ua1 / A), f3 = T(p.ua2 / A);
+        const cpx<T> X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
+        p.out_new[i] = X;
+        const double w = hweight(kx, geo.nx);
+        const double Lk = geo.a + k2 * k2;
+        const double xx = (double)X.x * X.x + (double)X.y * X.y;
+        const double zx = 2.0 * X.x - cur.x, zy = 2.0 * X.y - cur.y;
+        acc[0] += w * Lk * xx;
+        acc[1] += w * Lk * (zx * zx + zy * zy);
+        acc[2] += w * xx;
+        acc[3] += w * k2 * k2 * xx;
+        if (i == 0) p.mean_raw[0] = (double)X.x;
+    }
+    block_sum_store<4>(acc, p.part + 4 * blockIdx.x);
+}
+
+// ------------------------------------------------------------------ rows: real <-> half spectrum
+
+// Two real rows per complex line: W = row0 + i row1, forward transform, split.
+template <typename T, int NX, typename InT>
+__global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
+    constexpr int E = Plan<NX>::E, P = Plan<NX>::P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * LdsLine<NX>::size;
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int row0 = (blockIdx.x * p.G + g) * 2;
+    const bool act = row0 < p.nrows;
+    const InT* in = reinterpret_cast<const InT*>(p.in);
+    cpx<T> v[1][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = t + P * m;
+        v[0][m] = act ? mk<T>(T(in[(size_t)row0 * NX + x]), T(in[(size_t)(row0 + 1) * NX + x])) : mk<T>(0, 0);
+    }
+    fft_run<T, NX, -1, 1>(v, lds, t, p.tw, p.tws);
+    __syncthreads();
+    line_store<T, NX, 1>(v, lds, t);
+    __syncthreads();
+    if (!act) return;
+    cpx<T>* out = reinterpret_cast<cpx<T>*>(p.out);
+    const T half = T(0.5);
+#pragma unroll
+    for (int m = 0; m <= E / 2; ++m) {
+        const int k = t + P * m;
+        if (m == E / 2 && t != 0) break;
+        const cpx<T> Vk = lds[lds_pad<NX>(k)];
+        const cpx<T> Vm = lds[lds_pad<NX>((NX - k) & (NX - 1))];
+        out[(size_t)k * p.nrows + row0] = mk<T>(half * (Vk.x + Vm.x), half * (Vk.y - Vm.y));
+        out[(size_t)k * p.nrows + row0 + 1] = mk<T>(half * (Vk.y + Vm.y), half * (Vm.x - Vk.x));
+    }
+}
+
+// Two half-spectrum rows -> one complex line -> inverse transform -> two real rows, scaled.
+template <typename T, int NX, typename OutT>
+__global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
+    constexpr int E = Plan<NX>::E, P = Plan<NX>::P;
+    constexpr int NXH = NX / 2 + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * LdsLine<NX>::size;
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int row0 = (blockIdx.x * p.G + g) * 2;
+    const bool act = row0 < p.nrows;
+    const cpx<T>* in = reinterpret_cast<const cpx<T>*>(p.in);
+    const cpx<T>* h1 = in + (size_t)(act ? row0 : 0) * NXH;
+    const cpx<T>* h2 = in + (size_t)(act ? row0 + 1 : 0) * NXH;
+    cpx<T> v[1][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[0][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+    fft_run<T, NX, +1, 1>(v, lds, t, p.tw, p.tws);
+    if (!act) return;
+    OutT* out = reinterpret_cast<OutT*>(p.out);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = t + P * m;
+        out[(size_t)row0 * NX + x] = OutT((double)v[0][m].x * p.scale);
+        out[(size_t)(row0 + 1) * NX + x] = OutT((double)v[0][m].y * p.scale);
+    }
+}
+
+}  // namespace spfc

@@ -1,0 +1,52 @@
+// Host-side launchers: pick the template instance for a line length and the
+// workgroup shape (line groups per workgroup) for the kernels of kernels.hpp.
+#pragma once
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace spfc {
+
+// Shape of one launch of a line kernel.
+struct LaunchShape {
+    int G;          // line groups per workgroup
+    int block;      // threads per workgroup
+    int grid;       // workgroups
+    size_t shmem;   // dynamic LDS bytes
+};
+
+// P threads per group, C complex lines per group, groups needed in total.
+inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int want_threads = 256,
+                              size_t lds_cap = 65536) {
+    const int E = N >= 16 ? 16 : N;
+    const int P = N / E;
+    const size_t per = (size_t)C * (size_t)(N + N / 16) * elem;
+    int G = std::max(1, want_threads / P);
+    while (G > 1 && (size_t)G * per > lds_cap) --G;
+    G = std::max(1, std::min(G, ngroups));
+    LaunchShape s;
+    s.G = G;
+    s.block = G * P;
+    s.grid = (ngroups + G - 1) / G;
+    s.shmem = (size_t)G * per;
+    return s;
+}
+
+template <typename T>
+struct Kern {
+    static hipError_t spec_inv(int nl, int dim, const SpecInvArgs<T>& a, const LaunchShape& s, hipStream_t st);
+    static hipError_t real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, const LaunchShape& s,
+                                hipStream_t st);
+    static hipError_t spec_fwd(int nl, int dim, int mode, const SpecFwdArgs<T>& a, const LaunchShape& s,
+                               hipStream_t st);
+    static hipError_t pass(int nl, int dir, int omode, int c, const PassArgs<T>& a, const LaunchShape& s,
+                           hipStream_t st);
+    static hipError_t update(int dim, const UpdateArgs<T>& a, int grid, int block, hipStream_t st);
+    static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
+    static hipError_t c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
+};
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+
+}  // namespace spfc

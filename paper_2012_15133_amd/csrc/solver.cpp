@@ -1,0 +1,888 @@
+// Host driver and C ABI (include/spfc.h): validation, workspace carving, the
+// per-step launch sequence, start-up, queries and checkpoints.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "launch.hpp"
+#include "spfc.h"
+
+using namespace spfc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool pow2_ok(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+
+enum Role { R_SPEC_INV = 0, R_MID_INV, R_REAL, R_MID_FWD, R_SPEC_FWD, R_COUNT };
+const char* const kRoleNames[R_COUNT] = {"spec_inv", "pass_y_inv", "real_pass", "pass_y_fwd", "spec_fwd"};
+
+struct Sizes {
+    int dim, nx, ny, nz, nxh;
+    size_t elem;
+};
+
+struct Shapes {
+    LaunchShape A, B, Cf, midI, midF, r2c, keep, swapInit, rot, swapGet, c2r;
+    int updGrid;
+};
+
+struct Layout {
+    size_t F;  // bytes of one half-spectrum field
+    size_t off_slot[2], off_nhat, off_bufA, off_bufB, off_tw, off_partA, off_partB, off_partC, off_sc, off_hist;
+    size_t total;
+    int nA, nB, nC;
+    int ntab;
+};
+
+Sizes sizes_of(const spfc_grid& g, int prec) {
+    Sizes s;
+    s.dim = g.dim;
+    s.nx = g.n[0];
+    s.ny = g.n[1];
+    s.nz = g.dim == 3 ? g.n[2] : 1;
+    s.nxh = s.nx / 2 + 1;
+    s.elem = prec == SPFC_FP32 ? 2 * sizeof(float) : 2 * sizeof(double);
+    return s;
+}
+
+Shapes shapes_of(const Sizes& s) {
+    Shapes h{};
+    const int d = s.dim;
+    const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
+    const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines
+    h.A = line_shape(nl, d, s.elem, nlines);
+    h.Cf = line_shape(nl, d, s.elem, nlines);
+    const int rowgroups = d == 2 ? s.ny : s.nz * s.ny / 2;
+    h.B = line_shape(s.nx, d == 2 ? 1 : 3, s.elem, rowgroups);
+    if (d == 3) {
+        h.midI = line_shape(s.ny, 3, s.elem, s.nz * s.nxh);
+        h.midF = line_shape(s.ny, 3, s.elem, s.nxh * s.nz);
+        h.swapInit = line_shape(s.ny, 1, s.elem, s.nxh * s.nz);
+        h.swapGet = line_shape(s.ny, 1, s.elem, s.nz * s.nxh);
+    }
+    h.r2c = line_shape(s.nx, 1, s.elem, s.ny * s.nz / 2);
+    h.c2r = line_shape(s.nx, 1, s.elem, s.ny * s.nz / 2);
+    h.keep = line_shape(nl, 1, s.elem, nlines);
+    h.rot = line_shape(nl, 1, s.elem, nlines);
+    const long long total = (long long)s.nxh * s.ny * s.nz;
+    h.updGrid = (int)std::min<long long>((total + 255) / 256, 2048);
+    return h;
+}
+
+Layout layout_of(const Sizes& s, const Shapes& h, int64_t hist_cap) {
+    Layout L{};
+    L.F = (size_t)s.nxh * s.ny * s.nz * s.elem;
+    const size_t Fa = align_up(L.F);
+    size_t o = 0;
+    L.off_slot[0] = o; o += Fa;
+    L.off_slot[1] = o; o += Fa;
+    L.off_nhat = o; o += Fa;
+    L.off_bufA = o; o += 3 * Fa;
+    L.off_bufB = o; o += 3 * Fa;
+    L.ntab = std::max(s.nx, std::max(s.ny, s.nz));
+    L.off_tw = o; o += align_up((size_t)L.ntab * s.elem);
+    L.nA = std::max(h.A.grid, h.updGrid);
+    L.nB = h.B.grid;
+    L.nC = h.Cf.grid;
+    L.off_partA = o; o += align_up((size_t)L.nA * 4 * sizeof(double));
+    L.off_partB = o; o += align_up((size_t)L.nB * sizeof(double));
+    L.off_partC = o; o += align_up((size_t)L.nC * 3 * sizeof(double));
+    L.off_sc = o; o += align_up(sizeof(DevScalars));
+    L.off_hist = o; o += align_up((size_t)hist_cap * sizeof(Record));
+    L.total = o;
+    return L;
+}
+
+int validate(const spfc_grid* g, const spfc_params* p) {
+    if (!g || !p) return SPFC_E_INVAL;
+    if (g->dim != 2 && g->dim != 3) return SPFC_E_INVAL;
+    for (int j = 0; j < g->dim; ++j) {
+        if (!pow2_ok(g->n[j])) return SPFC_E_INVAL;
+        if (!(g->L[j] > 0.0) || !std::isfinite(g->L[j])) return SPFC_E_INVAL;
+    }
+    if (!std::isfinite(p->epsilon) || !(1.0 - p->epsilon > 0.0)) return SPFC_E_INVAL;
+    if (!std::isfinite(p->c4) || !(p->c4 > 0.0)) return SPFC_E_INVAL;
+    if (p->startup < SPFC_STARTUP_SAV1 || p->startup > SPFC_STARTUP_COPY) return SPFC_E_INVAL;
+    if (p->precision != SPFC_FP64 && p->precision != SPFC_FP32) return SPFC_E_INVAL;
+    if (p->history < 1) return SPFC_E_INVAL;
+    if (!std::isfinite(p->energy_tol)) return SPFC_E_INVAL;
+    return SPFC_OK;
+}
+
+struct CkptHeader {
+    uint64_t magic;
+    int64_t step;
+    double dt_prev;
+    int32_t started, slot_same, prec, dim;
+    int32_t n[3];
+    int32_t pad;
+    DevScalars sc;
+};
+constexpr uint64_t kMagic = 0x5350464353415631ull;
+
+}  // namespace
+
+struct spfc_ctx {
+    spfc_grid grid;
+    spfc_params prm;
+    Sizes sz;
+    Shapes sh;
+    Layout lay;
+    Geo geo;
+    hipStream_t stream;
+    char* ws;
+    int slotX, slotY;  // slots of the newest (X) and older (Y) state of the pair
+    int64_t step;      // index of the newest state
+    double dt_prev;
+    bool started;
+    bool broken;
+    double energy_tol;
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    double role_ms[R_COUNT];
+    int64_t role_n[R_COUNT];
+
+    char* slot(int i) const { return ws + lay.off_slot[i]; }
+    char* nhat() const { return ws + lay.off_nhat; }
+    char* bufA(int j) const { return ws + lay.off_bufA + j * align_up(lay.F); }
+    char* bufB(int j) const { return ws + lay.off_bufB + j * align_up(lay.F); }
+    char* tw() const { return ws + lay.off_tw; }
+    double* partA() const { return reinterpret_cast<double*>(ws + lay.off_partA); }
+    double* partB() const { return reinterpret_cast<double*>(ws + lay.off_partB); }
+    double* partC() const { return reinterpret_cast<double*>(ws + lay.off_partC); }
+    DevScalars* sc() const { return reinterpret_cast<DevScalars*>(ws + lay.off_sc); }
+    Record* hist() const { return reinterpret_cast<Record*>(ws + lay.off_hist); }
+    int nl() const { return sz.dim == 2 ? sz.ny : sz.nz; }
+    int nlines() const { return sz.dim == 2 ? sz.nxh : sz.nxh * sz.ny; }
+    int lineB() const { return sz.dim == 2 ? sz.nxh : sz.ny; }
+};
+
+namespace {
+
+#define CK(x)                   \
+    do {                        \
+        hipError_t e_ = (x);    \
+        if (e_ != hipSuccess) { \
+            ctx->broken = true; \
+            return SPFC_E_DEVICE; \
+        }                       \
+    } while (0)
+
+// ---------------------------------------------------------------- profiling
+
+hipEvent_t take_event(spfc_ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int drain_events(spfc_ctx* ctx) {
+    if (ctx->ev_used.empty()) return SPFC_OK;
+    CK(hipStreamSynchronize(ctx->stream));
+    for (auto& u : ctx->ev_used) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, u.second.first, u.second.second));
+        ctx->role_ms[u.first] += ms;
+        ctx->role_n[u.first] += 1;
+        ctx->ev_pool.push_back(u.second.first);
+        ctx->ev_pool.push_back(u.second.second);
+    }
+    ctx->ev_used.clear();
+    return SPFC_OK;
+}
+
+struct Timed {
+    spfc_ctx* ctx;
+    int role;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(spfc_ctx* c, int r, bool on) : ctx(c), role(r) {
+        if (on && ctx->profiling) {
+            a = take_event(ctx);
+            b = take_event(ctx);
+            if (a && b) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~Timed() {
+        if (a && b) {
+            (void)hipEventRecord(b, ctx->stream);
+            ctx->ev_used.push_back({role, {a, b}});
+        }
+    }
+};
+
+// ---------------------------------------------------------------- pipeline (one precision)
+
+template <typename T>
+struct Pipe {
+    using C = cpx<T>;
+    spfc_ctx* ctx;
+
+    // spectral state (cur, prev) -> gradient transforms along the last axis -> bufA
+    int spec_inv(const char* cur, const char* prev, char* out_new, bool update, double ua0, double ua1, double ua2,
+                 double udt, double e1, double e2, bool want_grad, bool timed) {
+        SpecInvArgs<T> a{};
+        a.cur = (const C*)cur;
+        a.prev = (const C*)prev;
+        a.nhat = (const C*)ctx->nhat();
+        a.out_new = (C*)out_new;
+        for (int j = 0; j < 3; ++j) a.out[j] = (C*)ctx->bufA(j);
+        a.tw = (const C*)ctx->tw();
+        a.tws = ctx->lay.ntab / ctx->nl();
+        a.nlines = ctx->nlines();
+        a.B = ctx->lineB();
+        a.G = ctx->sh.A.G;
+        a.update = update ? 1 : 0;
+        a.ua0 = ua0;
+        a.ua1 = ua1;
+        a.ua2 = ua2;
+        a.udt = udt;
+        a.xi = &ctx->sc()->xi;
+        a.e1 = e1;
+        a.e2 = e2;
+        a.want_grad = want_grad ? 1 : 0;
+        a.part = ctx->partA();
+        a.mean_raw = &ctx->sc()->mean_raw;
+        a.geo = ctx->geo;
+        Timed tm(ctx, R_SPEC_INV, timed);
+        CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, a, ctx->sh.A, ctx->stream));
+        return SPFC_OK;
+    }
+
+    // 3-D middle pass along y: in -> out, [a][b][Y] -> [a][Y][b]
+    int mid(int dir, char* const* in, char* const* out, const LaunchShape& s, int nlines, int B, int role,
+            bool timed) {
+        PassArgs<T> a{};
+        for (int j = 0; j < 3; ++j) {
+            a.in[j] = (const C*)in[j];
+            a.out[j] = (C*)out[j];
+        }
+        a.tw = (const C*)ctx->tw();
+        a.tws = ctx->lay.ntab / ctx->sz.ny;
+        a.nlines = nlines;
+        a.B = B;
+        a.G = s.G;
+        Timed tm(ctx, role, timed);
+        CK(Kern<T>::pass(ctx->sz.ny, dir, OUT_SWAP, 3, a, s, ctx->stream));
+        return SPFC_OK;
+    }
+
+    // gradient rows -> flux spectra (or E_1 only)
+    int real_pass(char* const* in, char* const* out, bool fwd, bool timed) {
+        RealArgs<T> a{};
+        for (int j = 0; j < 3; ++j) {
+            a.in[j] = (const C*)in[j];
+            a.out[j] = (C*)out[j];
+        }
+        a.tw = (const C*)ctx->tw();
+        a.tws = ctx->lay.ntab / ctx->sz.nx;
+        a.nrows = ctx->sz.ny * ctx->sz.nz;
+        a.G = ctx->sh.B.G;
+        a.part = ctx->partB();
+        a.geo = ctx->geo;
+        Timed tm(ctx, R_REAL, timed);
+        CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, a, ctx->sh.B, ctx->stream));
+        return SPFC_OK;
+    }
+
+    int spec_fwd(char* const* in, const char* X, const char* Y, int mode, char* ghost_out, double a0, double a1,
+                 double a2, double dt, double e1, double e2, int check_rise, bool timed) {
+        SpecFwdArgs<T> a{};
+        for (int j = 0; j < 3; ++j) a.in[j] = (const C*)in[j];
+        a.X = (const C*)X;
+        a.Y = (const C*)Y;
+        a.nhat = (C*)ctx->nhat();
+        a.ghost_out = (C*)ghost_out;
+        a.tw = (const C*)ctx->tw();
+        a.tws = ctx->lay.ntab / ctx->nl();
+        a.nlines = ctx->nlines();
+        a.B = ctx->lineB();
+        a.G = ctx->sh.Cf.G;
+        a.a0 = a0;
+        a.a1 = a1;
+        a.a2 = a2;
+        a.dt = dt;
+        a.e1 = e1;
+        a.e2 = e2;
+        a.partC = ctx->partC();
+        a.partA = ctx->partA();
+        a.nA = ctx->sh.A.grid;
+        a.partB = ctx->partB();
+        a.nB = ctx->sh.B.grid;
+        a.sc = ctx->sc();
+        a.hist = ctx->hist();
+        a.hist_cap = ctx->prm.history;
+        a.step = ctx->step;
+        a.check_rise = check_rise;
+        a.energy_tol = ctx->energy_tol;
+        a.geo = ctx->geo;
+        Timed tm(ctx, R_SPEC_FWD, timed);
+        CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, a, ctx->sh.Cf, ctx->stream));
+        return SPFC_OK;
+    }
+
+    int finalize(int mode, int nA, int check_rise) {
+        FinalizeArgs f{};
+        f.mode = mode;
+        f.partA = ctx->partA();
+        f.nA = nA;
+        f.partB = ctx->partB();
+        f.nB = ctx->sh.B.grid;
+        f.sc = ctx->sc();
+        f.hist = ctx->hist();
+        f.hist_cap = ctx->prm.history;
+        f.step = ctx->step;
+        f.check_rise = check_rise;
+        f.energy_tol = ctx->energy_tol;
+        f.geo = ctx->geo;
+        CK(launch_finalize(f, ctx->stream));
+        return SPFC_OK;
+    }
+
+    char* const* A3() { static thread_local char* p[3]; for (int j = 0; j < 3; ++j) p[j] = ctx->bufA(j); return p; }
+    char* const* B3() { static thread_local char* p[3]; for (int j = 0; j < 3; ++j) p[j] = ctx->bufB(j); return p; }
+
+    // E_1 of the state `field` (and the norms of (field, prev)) -> finalize(mode)
+    int e1_pass(const char* field, const char* prev, int fin_mode) {
+        int rc;
+        if ((rc = spec_inv(field, prev, nullptr, false, 0, 0, 0, 0, 1.0, 0.0, true, false))) return rc;
+        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
+        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
+        if (ctx->sz.dim == 3) {
+            if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, false)))
+                return rc;
+            if ((rc = real_pass(bB, bA, false, false))) return rc;
+        } else {
+            if ((rc = real_pass(bA, bB, false, false))) return rc;
+        }
+        return finalize(fin_mode, ctx->sh.A.grid, 0);
+    }
+
+    // Ghost start (eq. scheme-SAV-initial-1): phi^{-1} into the other slot, r^0 and r^{-1}.
+    int ghost(double dt) {
+        int rc;
+        const int o = 1 - ctx->slotX;
+        char* X = ctx->slot(ctx->slotX);
+        if ((rc = spec_inv(X, X, nullptr, false, 0, 0, 0, 0, 1.0, 0.0, true, false))) return rc;
+        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
+        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
+        char** flux = bB;
+        if (ctx->sz.dim == 3) {
+            if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, false)))
+                return rc;
+            if ((rc = real_pass(bB, bA, true, false))) return rc;
+            if ((rc = mid(-1, bA, bB, ctx->sh.midF, ctx->sz.nxh * ctx->sz.nz, ctx->sz.nz, R_MID_FWD, false)))
+                return rc;
+        } else {
+            if ((rc = real_pass(bA, bB, true, false))) return rc;
+        }
+        if ((rc = spec_fwd(flux, X, X, FWD_GHOST, ctx->slot(o), 1.0, 0.0, 0.0, dt, 1.0, 0.0, 0, false))) return rc;
+        if ((rc = finalize(FIN_GHOST_R0, ctx->sh.A.grid, 0))) return rc;
+        if ((rc = e1_pass(ctx->slot(o), ctx->slot(o), FIN_GHOST_RM1))) return rc;
+        ctx->slotY = o;
+        return SPFC_OK;
+    }
+
+    int steps(double dt, int64_t n) {
+        int rc;
+        const bool restart = !ctx->started || dt != ctx->dt_prev;
+        bool first_order = false;
+        if (restart) {
+            if (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_GHOST) {
+                if ((rc = ghost(dt))) return rc;
+            } else {
+                // phi^{-1} = phi^0, r^{-1} = r^0 = sqrt(E_1(phi^0))
+                ctx->slotY = ctx->slotX;
+                if ((rc = e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotX), FIN_RESTART))) return rc;
+                first_order = (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_SAV1);
+            }
+        }
+        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
+        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
+        const int d = ctx->sz.dim;
+        double pa0 = 0, pa1 = 0, pa2 = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const bool sav1 = first_order && i == 0;
+            const double a0 = sav1 ? 1.0 : 1.5, a1 = sav1 ? 1.0 : 2.0, a2 = sav1 ? 0.0 : -0.5;
+            const double e1 = sav1 ? 1.0 : 2.0, e2 = sav1 ? 0.0 : -1.0;
+            if (i == 0) {
+                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, false, 0, 0, 0, 0, e1, e2,
+                                   true, true)))
+                    return rc;
+            } else {
+                const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
+                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), ctx->slot(target), true, pa0, pa1,
+                                   pa2, dt, e1, e2, true, true)))
+                    return rc;
+                ctx->slotY = ctx->slotX;
+                ctx->slotX = target;
+                ctx->step += 1;
+            }
+            char** flux = bB;
+            if (d == 3) {
+                if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, true)))
+                    return rc;
+                if ((rc = real_pass(bB, bA, true, true))) return rc;
+                if ((rc = mid(-1, bA, bB, ctx->sh.midF, ctx->sz.nxh * ctx->sz.nz, ctx->sz.nz, R_MID_FWD, true)))
+                    return rc;
+            } else {
+                if ((rc = real_pass(bA, bB, true, true))) return rc;
+            }
+            const int check = (i == 0 && restart) ? 0 : 1;
+            if ((rc = spec_fwd(flux, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt,
+                               e1, e2, check, true)))
+                return rc;
+            pa0 = a0;
+            pa1 = a1;
+            pa2 = a2;
+        }
+        // apply the last update and record the state it reaches
+        const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
+        UpdateArgs<T> u{};
+        u.cur = (const C*)ctx->slot(ctx->slotX);
+        u.prev = (const C*)ctx->slot(ctx->slotY);
+        u.nhat = (const C*)ctx->nhat();
+        u.out_new = (C*)ctx->slot(target);
+        u.total = (long long)ctx->sz.nxh * ctx->sz.ny * ctx->sz.nz;
+        u.NL = ctx->nl();
+        u.B = ctx->lineB();
+        u.ua0 = pa0;
+        u.ua1 = pa1;
+        u.ua2 = pa2;
+        u.udt = dt;
+        u.xi = &ctx->sc()->xi;
+        u.part = ctx->partA();
+        u.mean_raw = &ctx->sc()->mean_raw;
+        u.geo = ctx->geo;
+        CK(Kern<T>::update(d, u, ctx->sh.updGrid, 256, ctx->stream));
+        ctx->slotY = ctx->slotX;
+        ctx->slotX = target;
+        ctx->step += 1;
+        if ((rc = finalize(FIN_STATE, ctx->sh.updGrid, 1))) return rc;
+        ctx->started = true;
+        ctx->dt_prev = dt;
+        return SPFC_OK;
+    }
+
+    // real field (doubles, x fastest) -> half spectrum in slot `s`
+    int forward_real(const double* phi, int s) {
+        RowArgs<T> r{};
+        r.in = phi;
+        r.out = ctx->bufA(0);
+        r.tw = (const C*)ctx->tw();
+        r.tws = ctx->lay.ntab / ctx->sz.nx;
+        r.nrows = ctx->sz.ny * ctx->sz.nz;
+        r.G = ctx->sh.r2c.G;
+        r.scale = 1.0;
+        CK(Kern<T>::r2c_rows(ctx->sz.nx, r, ctx->sh.r2c, ctx->stream));
+        PassArgs<T> p{};
+        p.tw = (const C*)ctx->tw();
+        if (ctx->sz.dim == 3) {
+            // [X][Z][Y] -> transform y -> [X][Y][Z]
+            p.in[0] = (const C*)ctx->bufA(0);
+            p.out[0] = (C*)ctx->bufB(0);
+            p.tws = ctx->lay.ntab / ctx->sz.ny;
+            p.nlines = ctx->sz.nxh * ctx->sz.nz;
+            p.B = ctx->sz.nz;
+            p.G = ctx->sh.swapInit.G;
+            CK(Kern<T>::pass(ctx->sz.ny, -1, OUT_SWAP, 1, p, ctx->sh.swapInit, ctx->stream));
+            p.in[0] = (const C*)ctx->bufB(0);
+        } else {
+            p.in[0] = (const C*)ctx->bufA(0);
+        }
+        p.out[0] = (C*)ctx->slot(s);
+        p.tws = ctx->lay.ntab / ctx->nl();
+        p.nlines = ctx->nlines();
+        p.B = ctx->lineB();
+        p.G = ctx->sh.keep.G;
+        CK(Kern<T>::pass(ctx->nl(), -1, OUT_KEEP, 1, p, ctx->sh.keep, ctx->stream));
+        return SPFC_OK;
+    }
+
+    // half spectrum of the newest state -> real field
+    int inverse_real(void* out, bool out_fp32) {
+        PassArgs<T> p{};
+        p.tw = (const C*)ctx->tw();
+        p.in[0] = (const C*)ctx->slot(ctx->slotX);
+        p.out[0] = (C*)ctx->bufA(0);
+        p.tws = ctx->lay.ntab / ctx->nl();
+        p.nlines = ctx->nlines();
+        p.B = ctx->lineB();
+        p.G = ctx->sh.rot.G;
+        CK(Kern<T>::pass(ctx->nl(), +1, OUT_ROTATE, 1, p, ctx->sh.rot, ctx->stream));
+        const char* rows = ctx->bufA(0);
+        if (ctx->sz.dim == 3) {
+            // [Z][X][Y] -> transform y -> [Z][Y][X]
+            p.in[0] = (const C*)ctx->bufA(0);
+            p.out[0] = (C*)ctx->bufB(0);
+            p.tws = ctx->lay.ntab / ctx->sz.ny;
+            p.nlines = ctx->sz.nz * ctx->sz.nxh;
+            p.B = ctx->sz.nxh;
+            p.G = ctx->sh.swapGet.G;
+            CK(Kern<T>::pass(ctx->sz.ny, +1, OUT_SWAP, 1, p, ctx->sh.swapGet, ctx->stream));
+            rows = ctx->bufB(0);
+        }
+        RowArgs<T> r{};
+        r.in = rows;
+        r.out = out;
+        r.tw = (const C*)ctx->tw();
+        r.tws = ctx->lay.ntab / ctx->sz.nx;
+        r.nrows = ctx->sz.ny * ctx->sz.nz;
+        r.G = ctx->sh.c2r.G;
+        r.scale = ctx->geo.inv_npts;
+        CK(Kern<T>::c2r_rows(ctx->sz.nx, out_fp32, r, ctx->sh.c2r, ctx->stream));
+        return SPFC_OK;
+    }
+
+    int write_twiddles() {
+        const int n = ctx->lay.ntab;
+        std::vector<C> h(n);
+        for (int j = 0; j < n; ++j) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)n;
+            h[j] = mk<T>(T(cosl(ang)), T(sinl(ang)));
+        }
+        CK(hipMemcpyAsync(ctx->tw(), h.data(), n * sizeof(C), hipMemcpyHostToDevice, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        return SPFC_OK;
+    }
+};
+
+template <typename F>
+int with_pipe(spfc_ctx* ctx, F&& f) {
+    if (ctx->prm.precision == SPFC_FP32) {
+        Pipe<float> p{ctx};
+        return f(p);
+    }
+    Pipe<double> p{ctx};
+    return f(p);
+}
+
+Geo make_geo(const spfc_grid& g, const spfc_params& prm) {
+    Geo geo{};
+    geo.dim = g.dim;
+    geo.nx = g.n[0];
+    geo.ny = g.n[1];
+    geo.nz = g.dim == 3 ? g.n[2] : 1;
+    geo.nxh = geo.nx / 2 + 1;
+    const double twopi = 6.283185307179586476925286766559;
+    geo.k0x = twopi / g.L[0];
+    geo.k0y = twopi / g.L[1];
+    geo.k0z = g.dim == 3 ? twopi / g.L[2] : 0.0;
+    geo.a = 1.0 - prm.epsilon;
+    geo.c4 = prm.c4;
+    const double npts = (double)geo.nx * geo.ny * geo.nz;
+    geo.inv_npts = 1.0 / npts;
+    double vol = g.L[0] * g.L[1] * (g.dim == 3 ? g.L[2] : 1.0);
+    geo.volume = vol;
+    geo.cell = vol / npts;
+    geo.pscale = vol / (npts * npts);
+    geo.e1_const = (1.0 + 1.0 / prm.c4) * vol;
+    return geo;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+const char* spfc_strerror(int status) {
+    switch (status) {
+        case SPFC_OK: return "ok";
+        case SPFC_E_INVAL: return "invalid argument";
+        case SPFC_E_NOMEM: return "workspace too small";
+        case SPFC_E_DEVICE: return "HIP device error";
+        case SPFC_E_NONFINITE: return "non-finite value detected";
+        case SPFC_E_STATE: return "call out of order or bad checkpoint";
+        default: return "unknown status";
+    }
+}
+
+int spfc_workspace_bytes(const spfc_grid* grid, const spfc_params* params, size_t* bytes) {
+    if (!bytes) return SPFC_E_INVAL;
+    int rc = validate(grid, params);
+    if (rc) return rc;
+    Sizes s = sizes_of(*grid, params->precision);
+    Shapes h = shapes_of(s);
+    *bytes = layout_of(s, h, params->history).total;
+    return SPFC_OK;
+}
+
+int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev, void* workspace_dev,
+              size_t workspace_bytes, void* hip_stream, spfc_ctx** out) {
+    if (!out || !phi0_dev || !workspace_dev) return SPFC_E_INVAL;
+    int rc = validate(grid, params);
+    if (rc) return rc;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) return SPFC_E_INVAL;
+    Sizes s = sizes_of(*grid, params->precision);
+    Shapes h = shapes_of(s);
+    Layout lay = layout_of(s, h, params->history);
+    if (workspace_bytes < lay.total) return SPFC_E_NOMEM;
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    // reject non-finite initial data (host copy of phi0)
+    const size_t npts = (size_t)s.nx * s.ny * s.nz;
+    {
+        std::vector<double> host(npts);
+        if (hipMemcpyAsync(host.data(), phi0_dev, npts * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+            return SPFC_E_DEVICE;
+        if (hipStreamSynchronize(stream) != hipSuccess) return SPFC_E_DEVICE;
+        for (size_t i = 0; i < npts; ++i)
+            if (!std::isfinite(host[i])) return SPFC_E_INVAL;
+    }
+
+    spfc_ctx* ctx = new (std::nothrow) spfc_ctx();
+    if (!ctx) return SPFC_E_NOMEM;
+    ctx->grid = *grid;
+    ctx->prm = *params;
+    ctx->sz = s;
+    ctx->sh = h;
+    ctx->lay = lay;
+    ctx->geo = make_geo(*grid, *params);
+    ctx->stream = stream;
+    ctx->ws = reinterpret_cast<char*>(workspace_dev);
+    ctx->slotX = 0;
+    ctx->slotY = 0;
+    ctx->step = 0;
+    ctx->dt_prev = 0.0;
+    ctx->started = false;
+    ctx->broken = false;
+    ctx->energy_tol = params->energy_tol > 0 ? params->energy_tol : (params->precision == SPFC_FP32 ? 1e-6 : 1e-12);
+    ctx->profiling = false;
+    for (int i = 0; i < R_COUNT; ++i) {
+        ctx->role_ms[i] = 0;
+        ctx->role_n[i] = 0;
+    }
+
+    auto fail = [&](int code) {
+        delete ctx;
+        return code;
+    };
+    if (hipMemsetAsync(ctx->ws + lay.off_sc, 0, lay.total - lay.off_sc, stream) != hipSuccess)
+        return fail(SPFC_E_DEVICE);
+    rc = with_pipe(ctx, [&](auto& p) {
+        int r;
+        if ((r = p.write_twiddles())) return r;
+        if ((r = p.forward_real(phi0_dev, 0))) return r;
+        // r^0 = sqrt(E_1(phi^0)) (after eq. scheme-SAV-initial-1)
+        return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
+    });
+    if (rc) return fail(rc);
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(SPFC_E_DEVICE);
+    *out = ctx;
+    return SPFC_OK;
+}
+
+int spfc_step(spfc_ctx* ctx, double dt, int64_t n) {
+    if (!ctx) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
+    if (n == 0) return SPFC_OK;
+    return with_pipe(ctx, [&](auto& p) { return p.steps(dt, n); });
+}
+
+int spfc_step_count(spfc_ctx* ctx, int64_t* n) {
+    if (!ctx || !n) return SPFC_E_INVAL;
+    *n = ctx->step;
+    return SPFC_OK;
+}
+
+int spfc_status(spfc_ctx* ctx, uint32_t* flags) {
+    if (!ctx || !flags) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    unsigned int f = 0;
+    CK(hipMemcpyAsync(&f, &ctx->sc()->flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    *flags = f;
+    return SPFC_OK;
+}
+
+int spfc_mass(spfc_ctx* ctx, double* mean) {
+    if (!ctx || !mean) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    double re = 0.0;
+    if (ctx->prm.precision == SPFC_FP32) {
+        float v[2];
+        CK(hipMemcpyAsync(v, ctx->slot(ctx->slotX), sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        re = v[0];
+    } else {
+        double v[2];
+        CK(hipMemcpyAsync(v, ctx->slot(ctx->slotX), sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        re = v[0];
+    }
+    *mean = re * ctx->geo.inv_npts;
+    return SPFC_OK;
+}
+
+int spfc_energy(spfc_ctx* ctx, spfc_energy_t* out) {
+    if (!ctx || !out) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    int rc = with_pipe(ctx, [&](auto& p) {
+        return p.e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FIN_QUERY);
+    });
+    if (rc) return rc;
+    DevScalars sc;
+    CK(hipMemcpyAsync(&sc, ctx->sc(), sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    const Geo& g = ctx->geo;
+    const double rn = sc.r_n, rm = sc.r_nm1;
+    out->modified_energy = 0.25 * (sc.q_norm[0] + sc.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm));
+    out->E1 = sc.q_E1;
+    out->energy = sc.q_E1 - g.e1_const + 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3];
+    out->sav_energy = 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3] + rn * rn;
+    out->r = rn;
+    out->mean = sc.mean;
+    out->step = ctx->step;
+    return (sc.flags & SPFC_FLAG_NONFINITE) ? SPFC_E_NONFINITE : SPFC_OK;
+}
+
+int spfc_history(spfc_ctx* ctx, int64_t first, int64_t count, spfc_record* out) {
+    if (!ctx || (!out && count > 0) || first < 0 || count < 0) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (count == 0) return SPFC_OK;
+    const int64_t cap = ctx->prm.history;
+    const int64_t last = first + count - 1;
+    if (last > ctx->step || first < ctx->step + 1 - cap) return SPFC_E_STATE;
+    static_assert(sizeof(Record) == sizeof(spfc_record), "record layout");
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int64_t i = first; i <= last;) {
+        const int64_t s = i % cap;
+        const int64_t run = std::min<int64_t>(last - i + 1, cap - s);
+        CK(hipMemcpy(out + (i - first), ctx->hist() + s, run * sizeof(Record), hipMemcpyDeviceToHost));
+        i += run;
+    }
+    return SPFC_OK;
+}
+
+int spfc_get_phi(spfc_ctx* ctx, void* out_dev, int dtype) {
+    if (!ctx || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    return with_pipe(ctx, [&](auto& p) { return p.inverse_real(out_dev, dtype == SPFC_FP32); });
+}
+
+int spfc_state_bytes(spfc_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return SPFC_E_INVAL;
+    *bytes = align_up(sizeof(CkptHeader)) + 2 * align_up(ctx->lay.F);
+    return SPFC_OK;
+}
+
+int spfc_save_state(spfc_ctx* ctx, void* out_dev, size_t bytes) {
+    if (!ctx || !out_dev) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    size_t need = 0;
+    spfc_state_bytes(ctx, &need);
+    if (bytes < need) return SPFC_E_STATE;
+    CkptHeader hd{};
+    hd.magic = kMagic;
+    hd.step = ctx->step;
+    hd.dt_prev = ctx->dt_prev;
+    hd.started = ctx->started ? 1 : 0;
+    hd.slot_same = ctx->slotX == ctx->slotY ? 1 : 0;
+    hd.prec = ctx->prm.precision;
+    hd.dim = ctx->sz.dim;
+    hd.n[0] = ctx->sz.nx;
+    hd.n[1] = ctx->sz.ny;
+    hd.n[2] = ctx->sz.nz;
+    CK(hipMemcpyAsync(&hd.sc, ctx->sc(), sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    char* o = reinterpret_cast<char*>(out_dev);
+    CK(hipMemcpyAsync(o, &hd, sizeof(hd), hipMemcpyHostToDevice, ctx->stream));
+    const size_t off = align_up(sizeof(CkptHeader));
+    CK(hipMemcpyAsync(o + off, ctx->slot(ctx->slotX), ctx->lay.F, hipMemcpyDeviceToDevice, ctx->stream));
+    CK(hipMemcpyAsync(o + off + align_up(ctx->lay.F), ctx->slot(ctx->slotY), ctx->lay.F, hipMemcpyDeviceToDevice,
+                      ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return SPFC_OK;
+}
+
+int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes) {
+    if (!ctx || !in_dev) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    size_t need = 0;
+    spfc_state_bytes(ctx, &need);
+    if (bytes < need) return SPFC_E_STATE;
+    CkptHeader hd{};
+    const char* in = reinterpret_cast<const char*>(in_dev);
+    CK(hipMemcpyAsync(&hd, in, sizeof(hd), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    if (hd.magic != kMagic || hd.prec != ctx->prm.precision || hd.dim != ctx->sz.dim || hd.n[0] != ctx->sz.nx ||
+        hd.n[1] != ctx->sz.ny || hd.n[2] != ctx->sz.nz)
+        return SPFC_E_STATE;
+    const size_t off = align_up(sizeof(CkptHeader));
+    CK(hipMemcpyAsync(ctx->slot(0), in + off, ctx->lay.F, hipMemcpyDeviceToDevice, ctx->stream));
+    if (!hd.slot_same)
+        CK(hipMemcpyAsync(ctx->slot(1), in + off + align_up(ctx->lay.F), ctx->lay.F, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    hd.sc.ticket = 0;
+    CK(hipMemcpyAsync(ctx->sc(), &hd.sc, sizeof(DevScalars), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->slotX = 0;
+    ctx->slotY = hd.slot_same ? 0 : 1;
+    ctx->step = hd.step;
+    ctx->dt_prev = hd.dt_prev;
+    ctx->started = hd.started != 0;
+    return SPFC_OK;
+}
+
+int spfc_profile(spfc_ctx* ctx, int enable) {
+    if (!ctx) return SPFC_E_INVAL;
+    int rc = drain_events(ctx);
+    if (rc) return rc;
+    ctx->profiling = enable != 0;
+    if (enable) {
+        for (int i = 0; i < R_COUNT; ++i) {
+            ctx->role_ms[i] = 0;
+            ctx->role_n[i] = 0;
+        }
+    }
+    return SPFC_OK;
+}
+
+int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms, int64_t* launches,
+                      double* bytes_per_launch, int* count) {
+    if (!ctx || !count) return SPFC_E_INVAL;
+    int rc = drain_events(ctx);
+    if (rc) return rc;
+    const double F = (double)ctx->lay.F;
+    const int d = ctx->sz.dim;
+    const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F};
+    int k = 0;
+    for (int i = 0; i < R_COUNT; ++i) {
+        if (ctx->role_n[i] == 0) continue;
+        if (k < cap) {
+            if (names) names[k] = kRoleNames[i];
+            if (avg_ms) avg_ms[k] = ctx->role_ms[i] / (double)ctx->role_n[i];
+            if (launches) launches[k] = ctx->role_n[i];
+            if (bytes_per_launch) bytes_per_launch[k] = bytes[i];
+        }
+        ++k;
+    }
+    *count = k;
+    return SPFC_OK;
+}
+
+int spfc_destroy(spfc_ctx* ctx) {
+    if (!ctx) return SPFC_E_INVAL;
+    if (!ctx->broken) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& u : ctx->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return SPFC_OK;
+}
+
+}  // extern "C"

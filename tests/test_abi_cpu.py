@@ -1,0 +1,112 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, it exports every
+function include/spfc.h declares, argument validation and workspace sizing, and
+the line-FFT schedule of the kernels run thread by thread on the host."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spfc.h")
+LIB = os.path.join(ROOT, "paper_2012_15133_amd", "libspfc.so")
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        from paper_2012_15133_amd import build as B
+        B.build()
+    from paper_2012_15133_amd import binding
+    return binding
+
+
+def test_header_declares_and_library_exports_all():
+    decl = set(re.findall(r"\b(spfc_[a-z_]+)\s*\(", open(HEADER).read()))
+    decl -= {"spfc_ctx"}
+    B = _lib()
+    assert set(B.EXPORTS) == decl
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (spfc_[a-z_]+)", out))
+    assert decl <= exported, decl - exported
+    lib = B.load_library()
+    for name in decl:
+        assert getattr(lib, name) is not None
+
+
+def test_workspace_and_validation():
+    B = _lib()
+    g = B.make_grid((1024, 1024), (128 * np.pi,) * 2)
+    p = B.make_params(0.25)
+    n64 = B.spfc_workspace_bytes(g, p)
+    n32 = B.spfc_workspace_bytes(g, B.make_params(0.25, precision="fp32"))
+    F = 513 * 1024 * 16
+    assert 9 * F <= n64 < 9 * F + 4 * 2 ** 20
+    assert n32 < n64
+    bad = [
+        (B.make_grid((100, 64), (1, 1)), p),
+        (B.make_grid((4, 64), (1, 1)), p),
+        (B.make_grid((2048, 64), (1, 1)), p),
+        (B.make_grid((64, 64), (0.0, 1)), p),
+        (B.make_grid((64, 64), (float("nan"), 1)), p),
+        (g, B.make_params(1.0)),
+        (g, B.make_params(0.25, c4=0.0)),
+        (g, B.make_params(0.25, startup=7)),
+        (g, B.make_params(0.25, precision=5)),
+        (g, B.make_params(0.25, history=0)),
+    ]
+    for gg, pp in bad:
+        with pytest.raises(B.SpfcError) as ei:
+            B.spfc_workspace_bytes(gg, pp)
+        assert ei.value.status == B.SPFC_E_INVAL
+
+
+def test_init_rejects_null_pointers_without_touching_the_device():
+    B = _lib()
+    lib = B.load_library()
+    g = B.make_grid((64, 64), (1.0, 1.0))
+    p = B.make_params(0.25)
+    ctx = ctypes.c_void_p()
+    assert lib.spfc_init(ctypes.byref(g), ctypes.byref(p), None, None, 0, None, ctypes.byref(ctx)) == B.SPFC_E_INVAL
+    assert lib.spfc_init(None, ctypes.byref(p), 1, 256, 1 << 30, None, ctypes.byref(ctx)) == B.SPFC_E_INVAL
+    # misaligned workspace
+    assert lib.spfc_init(ctypes.byref(g), ctypes.byref(p), 256, 257, 1 << 30, None,
+                         ctypes.byref(ctx)) == B.SPFC_E_INVAL
+    assert lib.spfc_step(None, 0.01, 1) == B.SPFC_E_INVAL
+    assert lib.spfc_destroy(None) == B.SPFC_E_INVAL
+    for code in range(6):
+        assert B.strerror(code)
+
+
+# ----------------------------------------------------------------- line FFT schedule on the host
+
+def _emu():
+    from paper_2012_15133_amd import build as B
+    path = os.path.join(ROOT, "_build", "libfft_emul.so")
+    if not os.path.exists(path):
+        path = B.build_emulator()
+    lib = ctypes.CDLL(path)
+    lib.emu_fft_lines.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 2
+    return lib
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024])
+def test_line_fft_schedule_matches_dft(fp32, n):
+    """The Stockham schedule of the kernels (fft_core.hpp), run thread by thread on the
+    host, against the DFT definition evaluated by matrix product."""
+    lib = _emu()
+    rng = np.random.default_rng(n + fp32)
+    j = np.arange(n)
+    for sign in (-1, 1):
+        W = np.exp(sign * 2j * np.pi * (np.outer(j, j) % n) / n)
+        for c in (1, 3):
+            x = rng.standard_normal((c, n)) + 1j * rng.standard_normal((c, n))
+            out = np.zeros((c, n), complex)
+            assert lib.emu_fft_lines(fp32, n, sign, c, np.ascontiguousarray(x).ctypes.data, out.ctypes.data) == 0
+            ref = x @ W.T
+            err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+            # FFT rounding grows like eps * log2(n)
+            assert err <= (4e-7 if fp32 else 2e-15 * np.log2(n)), (n, sign, c, err)

@@ -1,0 +1,155 @@
+"""GPU path (libspfc.so through its C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances (FP64).  Both sides round differently (different FFT algorithms,
+spectral vs real-space inner products); each FFT costs O(eps log n) relative
+error and the dynamics amplifies differences at most by exp(0.264 t) (the
+largest linear growth rate at epsilon = 0.25), so at t <= 2 a 1e-11 bound on
+phi and 1e-12 on the modified energy leaves room of several hundred times the
+expected difference.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spfc_oracle as O
+from paper_2012_15133_amd.inputs import noise_ic
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(n, L, phi0, eps=0.25, **kw):
+    from paper_2012_15133_amd import Solver
+    return Solver(n, L, phi0, eps, **kw)
+
+
+def _rel_inf(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# ----------------------------------------------------------------- transforms and queries
+
+@pytest.mark.parametrize("n", [(64, 64), (32, 16), (8, 8), (1024, 1024), (16, 16, 16), (8, 16, 32)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_phi_roundtrip(n, precision):
+    L = tuple(2 * math.pi * v / 8 for v in n)
+    shape = tuple(reversed(n))
+    phi0 = noise_ic(shape, -0.2, 11)
+    s = _solver(n, L, phi0, precision=precision)
+    back = s.phi().cpu().numpy()
+    tol = 1e-14 if precision == "fp64" else 2e-6
+    assert _rel_inf(back, phi0) <= tol
+    assert abs(s.mass() - np.mean(phi0)) <= (1e-15 if precision == "fp64" else 1e-7)
+    s.close()
+
+
+@pytest.mark.parametrize("n", [(64, 64), (32, 64), (16, 16, 16), (8, 16, 8)])
+def test_initial_energies_match_oracle(n):
+    L = tuple(2 * math.pi * v / 8 for v in n)
+    g = O.Grid(n, L)
+    prm = O.Params(0.25)
+    phi0 = noise_ic(g.shape, -0.2, 3)
+    s = _solver(n, L, phi0)
+    e = s.energy()
+    E1 = O.E1(g, prm, phi0)
+    assert abs(e["E1"] - E1) <= 1e-13 * E1
+    EN = O.E_N(g, prm, phi0)
+    assert abs(e["energy"] - EN) <= 1e-12 * (abs(EN) + g.volume)
+    assert abs(e["r"] - math.sqrt(E1)) <= 1e-13 * math.sqrt(E1)
+    ref = O.modified_energy(g, prm, phi0, phi0, math.sqrt(E1), math.sqrt(E1))
+    assert abs(e["modified_energy"] - ref) <= 1e-12 * ref
+    sav = O.sav_energy(g, prm, phi0, math.sqrt(E1))
+    assert abs(e["sav_energy"] - sav) <= 1e-12 * sav
+    s.close()
+
+
+# ----------------------------------------------------------------- trajectories
+
+def _compare_run(n, L, eps, dt, steps, seed, mean, startup="sav1", tol_phi=1e-11, tol_e=1e-12, chunks=(None,)):
+    g = O.Grid(n, L)
+    prm = O.Params(eps)
+    phi0 = noise_ic(g.shape, mean, seed)
+    ref = O.run(g, prm, phi0, dt, steps, startup=startup)
+    s = _solver(n, L, phi0, eps, startup=startup, history=steps + 1)
+    done = 0
+    for c in chunks:
+        k = steps - done if c is None else c
+        s.step(dt, k)
+        done += k
+    assert done == steps and s.step_count() == steps
+    hist = s.history(0, steps + 1)
+    phi = s.phi().cpu().numpy()
+    m0 = np.mean(phi0)
+    for k, (hr, rr) in enumerate(zip(hist, ref["records"])):
+        assert abs(hr["energy"] - rr["energy"]) <= tol_e * rr["energy"], (k, hr, rr)
+        assert abs(hr["mean"] - rr["mean"]) <= 1e-14 * (1 + k) ** 0.5 * max(1.0, abs(m0)) + 1e-15, (k, hr, rr)
+        assert abs(hr["r"] - rr["r"]) <= tol_e * rr["r"], (k, hr, rr)
+        if k > 0:
+            assert abs(hr["xi"] - rr["xi"]) <= 1e3 * tol_e, (k, hr, rr)
+            assert abs(hr["E1"] - rr["E1"]) <= tol_e * rr["E1"], (k, hr, rr)
+    assert _rel_inf(phi, ref["phi"]) <= tol_phi
+    assert s.status() == 0
+    return s, hist, ref
+
+
+def test_c1_trajectory_fp64():
+    """64^2, L = 8 pi, epsilon 0.25, phi0 = -0.2 + 0.05 U(-1,1) (seed 1), dt 0.01, 200 steps,
+    first step first-order SAV: modified energy and mean after every step, final phi."""
+    s, hist, ref = _compare_run((64, 64), (8 * math.pi,) * 2, 0.25, 0.01, 200, 1, -0.2)
+    e = [h["energy"] for h in hist]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:]))
+    s.close()
+
+
+def test_c1_split_calls_match_single_call():
+    """Steps issued in several calls give the same result as one call."""
+    s, hist, ref = _compare_run((64, 64), (8 * math.pi,) * 2, 0.25, 0.01, 50, 1, -0.2, chunks=(1, 7, 30, None))
+    s.close()
+
+
+@pytest.mark.parametrize("startup", ["ghost", "copy"])
+def test_startup_modes(startup):
+    s, hist, ref = _compare_run((32, 32), (4 * math.pi,) * 2, 0.25, 0.02, 40, 5, -0.1, startup=startup)
+    s.close()
+
+
+def test_nonsquare_2d():
+    s, hist, ref = _compare_run((64, 16), (8 * math.pi, 2 * math.pi), 0.3, 0.01, 30, 8, 0.05)
+    s.close()
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 8)])
+def test_3d_trajectory(n):
+    L = tuple(v * math.pi / 8 for v in n)
+    s, hist, ref = _compare_run(n, L, 0.25, 0.005, 20, 3, -0.25)
+    s.close()
+
+
+def test_c2_full_size_sampled_fp64():
+    """1024^2, L = 128 pi, dt 0.01 (the large 2-D run) in the launch shape the benchmark uses:
+    the first 3 steps against the oracle, element by element."""
+    n = (1024, 1024)
+    L = (128 * math.pi,) * 2
+    s, hist, ref = _compare_run(n, L, 0.25, 0.01, 3, 2, -0.2, tol_phi=1e-12, tol_e=1e-12)
+    s.close()
+
+
+def test_c2_full_length_properties():
+    """2000 steps at 1024^2: mass conserved (Theorem 2.1), modified energy non-increasing
+    (Theorem 3.1), p1 <= 0 and E_1 >= |Omega| (no sticky flag)."""
+    n = (1024, 1024)
+    L = (128 * math.pi,) * 2
+    phi0 = noise_ic((1024, 1024), -0.2, 2)
+    s = _solver(n, L, phi0, history=2001)
+    s.step(0.01, 2000)
+    hist = s.history(0, 2001)
+    assert s.status() == 0
+    m0 = np.mean(phi0)
+    for k, h in enumerate(hist):
+        assert abs(h["mean"] - m0) <= 1e-13
+        if k > 0:
+            assert h["energy"] <= hist[k - 1]["energy"] * (1 + 1e-12)
+            assert h["p1"] <= 0.0
+            assert h["E1"] >= (128 * math.pi) ** 2
+    s.close()
