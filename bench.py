@@ -1,0 +1,162 @@
+"""Benchmark of the SAV-BDF2 time stepper for the square phase field crystal equation.
+
+Workload (default): the large single 2-D run, 1024 x 1024 points, L = 128 pi,
+epsilon = 0.25, c4 = 1, phi0 = -0.2 + 0.05 U(-1,1) (SplitMix64 seed 2), dt = 0.01,
+FP64, first step first-order SAV then BDF2.  One "step" is one full SAV-BDF2
+step (all transforms, the pointwise flux, the reductions, the SAV scalar and both
+Fourier solves).  Warm-up steps continue the same run; then K steps are timed
+with HIP events on the solver's stream, inputs resident in HBM.
+
+Prints one JSON line: grid-point-steps/s, the roofline of the dominant kernel
+(algorithmic bytes / average launch time from HIP events, against 8 TB/s) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (n, L, epsilon, mean, seed, dt, precision)
+    "spfc2d_1024_fp64": ((1024, 1024), (128 * math.pi,) * 2, 0.25, -0.2, 2, 0.01, "fp64"),
+    "spfc2d_1024_fp32": ((1024, 1024), (128 * math.pi,) * 2, 0.25, -0.2, 2, 0.01, "fp32"),
+    "spfc3d_256_fp32": ((256, 256, 256), (32 * math.pi,) * 3, 0.25, -0.25, 3, 0.005, "fp32"),
+    "spfc2d_64_fp64": ((64, 64), (8 * math.pi,) * 2, 0.25, -0.2, 1, 0.01, "fp64"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2012_15133_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload: str, steps: int):
+    """The oracle, as it is, on the first `steps` steps of the same run (host cores)."""
+    import numpy as np
+    from oracle import spfc_oracle as O
+    from paper_2012_15133_amd.inputs import noise_ic
+    n, L, eps, mean, seed, dt, _ = WORKLOADS[workload]
+    g = O.Grid(n, L)
+    phi0 = noise_ic(g.shape, mean, seed)
+    t0 = time.perf_counter()
+    O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
+    sec = time.perf_counter() - t0
+    npts = int(np.prod(n))
+    return {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps (first-order start + BDF2) of {workload} from the same seeded input, "
+                      f"{sec:.1f} s wall, numpy single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU (slab/pencil FFT) "
+                                   "decomposition is a design, not a build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2012_15133_amd import Solver
+    from paper_2012_15133_amd.inputs import noise_ic
+
+    n, L, eps, mean, seed, dt, prec = WORKLOADS[args.workload]
+    shape = tuple(reversed(n))
+    phi0 = noise_ic(shape, mean, seed)
+    s = Solver(n, L, phi0, eps, precision=prec, history=max(16, args.steps + args.warmup + args.profile_steps + 2))
+    stream = s.stream
+    npts = int(np.prod(n))
+
+    if args.warmup > 0:
+        s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.step(dt, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    flags = s.status()
+
+    # per-kernel times: HIP events around every step kernel on the solver stream
+    s.profile(True)
+    s.step(dt, args.profile_steps)
+    kt = s.kernel_times()
+    s.profile(False)
+    dom = max(kt, key=lambda k: k["avg_ms"] * k["launches"])
+    achieved = dom["bytes"] / (dom["avg_ms"] * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, dom["name"])
+    per_kernel = {k["name"]: {"avg_us": round(k["avg_ms"] * 1e3, 3), "GBps": round(k["bytes"] / (k["avg_ms"] * 1e-3) / 1e9, 1)}
+                  for k in kt}
+    s.close()
+
+    out = {
+        "metric": "grid-point-steps/s",
+        "value": npts * args.steps / (ms * 1e-3),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(n), "L": [round(v, 6) for v in L], "epsilon": eps,
+                   "dt": dt, "mean": mean, "seed": seed, "startup": "sav1"},
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "kernels": per_kernel,
+        "sticky_flags": flags,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
