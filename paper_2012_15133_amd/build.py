@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libspfc.so")
-SOURCES = ["kern_f64.hip", "kern_f32.hip", "finalize.hip", "solver.cpp"]
+SOURCES = [f"kern_{p}_{k}.hip" for p in ("f64", "f32") for k in ("inv", "real", "fwd", "aux")] + [
+    "finalize.hip", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPFC_OFFLOAD_ARCH", "gfx950")

@@ -158,7 +158,7 @@ struct UpdateArgs {
 
 enum { FWD_SOLVE = 0, FWD_GHOST = 1 };
 
-enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RESTART = 4 };
+enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RESTART = 4, FIN_STEP = 5 };
 
 struct FinalizeArgs {
     int mode;
@@ -166,6 +166,9 @@ struct FinalizeArgs {
     int nA;
     const double* partB;
     int nB;
+    const double* partC;    // FIN_STEP: 3 partials per workgroup of the forward pass
+    int nC;
+    double a0, a1, a2, dt;  // FIN_STEP: weights and dt of the step
     DevScalars* sc;
     Record* hist;
     long long hist_cap;

@@ -2,7 +2,7 @@
 // butterflies and a Stockham autosort schedule exchanging through LDS.
 //
 // A line of length N (power of two, 8..1024) is owned by P = N / E threads of
-// one workgroup; thread t keeps E complex values in registers.  On entry and on
+// one workgroup; thread t keeps E complex values in registers (E = 4, 8 or 16).  On entry and on
 // exit v[m] is element t + P*m of the line (natural order in both domains), so
 // the first pass can load straight from HBM with coalesced accesses and the last
 // pass result can be used in registers (pointwise work, spectral symbols) without
@@ -54,23 +54,34 @@ __host__ __device__ inline cpx<T> mul_si(cpx<T> a) {
 
 // ------------------------------------------------------------------ schedule
 
-// E values per thread: 16 for N >= 16, else N.  Radices: 16 while at least 16
-// remain, then the leftover factor (2, 4 or 8) as the last pass.
+// Plan<N, E>: E values per thread (E in {2, 4, 8, 16}, E <= N), P = N / E threads per
+// line.  Radices: E while at least E remain, then the leftover factor as the last pass.
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int default_E(int N) { return N >= 16 ? 16 : N; }
 
-template <int N>
+template <int N, int EE = default_E(N)>
 struct Plan {
     static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "line length must be a power of two >= 8");
-    static constexpr int E = N >= 16 ? 16 : N;
+    static_assert(EE == 2 || EE == 4 || EE == 8 || EE == 16, "values per thread must be 2, 4, 8 or 16");
+    static_assert(EE <= N, "values per thread exceed the line length");
+    static constexpr int Nl = N;
+    static constexpr int E = EE;
     static constexpr int P = N / E;
-    static constexpr int n16 = ilog2(N) / 4;          // radix-16 passes
-    static constexpr int rest = 1 << (ilog2(N) % 4);  // leftover radix (1 = none)
-    static constexpr int NP = n16 + (rest > 1 ? 1 : 0);
-    static constexpr int radix(int p) { return p < n16 ? 16 : rest; }
+    static constexpr int nE = ilog2(N) / ilog2(E);              // full radix-E passes
+    static constexpr int rest = 1 << (ilog2(N) - nE * ilog2(E));  // leftover radix (1 = none)
+    static constexpr int NP = nE + (rest > 1 ? 1 : 0);
+    static constexpr int radix(int p) { return p < nE ? E : rest; }
     static constexpr int span(int p) {
         int s = 1;
         for (int q = 0; q < p; ++q) s *= radix(q);
         return s;
+    }
+    // start of pass p in the pass-major twiddle table (entries Ns (R - 1) per pass,
+    // N - 1 in total)
+    static constexpr int tw_off(int p) {
+        int o = 0;
+        for (int q = 0; q < p; ++q) o += span(q) * (radix(q) - 1);
+        return o;
     }
 };
 
@@ -160,22 +171,40 @@ __host__ __device__ inline void dftR(cpx<T> (&a)[R]) {
 }
 
 // ------------------------------------------------------------------ passes
-// Twiddle table: tw[j] = exp(-2 pi i j / ntab) for j < ntab, ntab = N * tws.
+// Twiddles are read from a pass-major table: for pass p (span Ns, radix R) the
+// entry at tw_off(p) + k (R - 1) + (r - 1) is exp(-2 pi i r k / (Ns R)),
+// k < Ns, 1 <= r < R.  Lanes of one butterfly slot then read consecutive
+// entries (R - 1 apart), which keeps LDS reads free of bank conflicts; a table
+// in natural order would put every lane at a multiple of N / (Ns R).
+//
+// build_pass_twiddles fills it from a natural table tw[j] = exp(-2 pi i j / (N tws)).
+template <typename T, typename PL, int PASS = 0>
+__host__ __device__ inline void build_pass_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ tw, int tws, int tid,
+                                                    int nthreads) {
+    constexpr int N = PL::Nl, R = PL::radix(PASS), Ns = PL::span(PASS);
+    if constexpr (Ns > 1) {
+        constexpr int cnt = Ns * (R - 1);
+        for (int j = tid; j < cnt; j += nthreads) {
+            const int k = j / (R - 1), r = j - k * (R - 1) + 1;
+            dst[PL::tw_off(PASS) + j] = tw[(size_t)r * k * (N / (Ns * R)) * tws];
+        }
+    }
+    if constexpr (PASS + 1 < PL::NP) build_pass_twiddles<T, PL, PASS + 1>(dst, tw, tws, tid, nthreads);
+}
 
-template <typename T, int N, int DIR, int C, int PASS>
-__host__ __device__ inline void pass_compute(cpx<T> (&v)[C][Plan<N>::E], int t, const cpx<T>* __restrict__ tw,
-                                             int tws) {
-    constexpr int E = Plan<N>::E, P = Plan<N>::P;
-    constexpr int R = Plan<N>::radix(PASS), Ns = Plan<N>::span(PASS), NB = E / R;
+template <typename T, typename PL, int DIR, int C, int PASS>
+__host__ __device__ inline void pass_compute(cpx<T> (&v)[C][PL::E], int t, const cpx<T>* __restrict__ ptw) {
+    constexpr int E = PL::E, P = PL::P;
+    constexpr int R = PL::radix(PASS), Ns = PL::span(PASS), NB = E / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         cpx<T> w[R];
         if constexpr (Ns > 1) {
             const int k = (t + P * u) & (Ns - 1);
-            const int step = k * (N / (Ns * R)) * tws;
+            const cpx<T>* row = ptw + PL::tw_off(PASS) + k * (R - 1) - 1;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cpx<T> q = tw[r * step];
+                cpx<T> q = row[r];
                 w[r] = DIR > 0 ? conj(q) : q;
             }
         }
@@ -205,10 +234,10 @@ struct LdsLine {
     static constexpr int size = N + N / 16;
 };
 
-template <typename T, int N, int C, int PASS>
-__host__ __device__ inline void pass_store(const cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t) {
-    constexpr int E = Plan<N>::E, P = Plan<N>::P;
-    constexpr int R = Plan<N>::radix(PASS), Ns = Plan<N>::span(PASS), NB = E / R;
+template <typename T, typename PL, int C, int PASS>
+__host__ __device__ inline void pass_store(const cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t) {
+    constexpr int N = PL::Nl, E = PL::E, P = PL::P;
+    constexpr int R = PL::radix(PASS), Ns = PL::span(PASS), NB = E / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int b = t + P * u;
@@ -221,10 +250,10 @@ __host__ __device__ inline void pass_store(const cpx<T> (&v)[C][Plan<N>::E], cpx
     }
 }
 
-template <typename T, int N, int C, int PASS>
-__host__ __device__ inline void pass_load(cpx<T> (&v)[C][Plan<N>::E], const cpx<T>* lds, int t) {
-    constexpr int E = Plan<N>::E, P = Plan<N>::P;
-    constexpr int R = Plan<N>::radix(PASS), NB = E / R;
+template <typename T, typename PL, int C, int PASS>
+__host__ __device__ inline void pass_load(cpx<T> (&v)[C][PL::E], const cpx<T>* lds, int t) {
+    constexpr int N = PL::Nl, E = PL::E, P = PL::P;
+    constexpr int R = PL::radix(PASS), NB = E / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int b = t + P * u;
@@ -237,31 +266,47 @@ __host__ __device__ inline void pass_load(cpx<T> (&v)[C][Plan<N>::E], const cpx<
 }
 
 // natural-order store / load of the whole line (element t + P m)
-template <typename T, int N, int C>
-__host__ __device__ inline void line_store(const cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t) {
+template <typename T, typename PL, int C>
+__host__ __device__ inline void line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t) {
+    constexpr int N = PL::Nl;
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int m = 0; m < Plan<N>::E; ++m) lds[c * LdsLine<N>::size + lds_pad<N>(t + Plan<N>::P * m)] = v[c][m];
+        for (int m = 0; m < PL::E; ++m) lds[c * LdsLine<N>::size + lds_pad<N>(t + PL::P * m)] = v[c][m];
 }
 
 // Whole transform on the device: all threads of the workgroup must call it
 // (it contains workgroup barriers).  lds points at this thread group's
 // C * LdsLine<N>::size elements.
-template <typename T, int N, int DIR, int C, int PASS = 0>
-__device__ inline void fft_run(cpx<T> (&v)[C][Plan<N>::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ tw,
-                               int tws) {
+// ptw: the pass-major twiddle table of this plan (in LDS).
+template <typename T, typename PL, int DIR, int C, int PASS = 0>
+__device__ inline void fft_run(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ ptw) {
     if constexpr (PASS == 0) {
-        pass_compute<T, N, DIR, C, 0>(v, t, tw, tws);
-        if constexpr (Plan<N>::NP > 1) fft_run<T, N, DIR, C, 1>(v, lds, t, tw, tws);
+        pass_compute<T, PL, DIR, C, 0>(v, t, ptw);
+        if constexpr (PL::NP > 1) fft_run<T, PL, DIR, C, 1>(v, lds, t, ptw);
     } else {
         __syncthreads();
-        pass_store<T, N, C, PASS - 1>(v, lds, t);
+        pass_store<T, PL, C, PASS - 1>(v, lds, t);
         __syncthreads();
-        pass_load<T, N, C, PASS>(v, lds, t);
-        pass_compute<T, N, DIR, C, PASS>(v, t, tw, tws);
-        if constexpr (PASS + 1 < Plan<N>::NP) fft_run<T, N, DIR, C, PASS + 1>(v, lds, t, tw, tws);
+        pass_load<T, PL, C, PASS>(v, lds, t);
+        pass_compute<T, PL, DIR, C, PASS>(v, t, ptw);
+        if constexpr (PASS + 1 < PL::NP) fft_run<T, PL, DIR, C, PASS + 1>(v, lds, t, ptw);
     }
+}
+
+// Build this plan's pass-major twiddle table in LDS from the global natural table
+// (spacing tws); every thread of the workgroup takes part.  The first pass reads
+// no twiddles and the barrier before the second pass orders these writes.
+template <typename T, typename PL>
+__device__ inline void stage_twiddles(cpx<T>* lds_tw, const cpx<T>* __restrict__ tw, int tws) {
+    build_pass_twiddles<T, PL>(lds_tw, tw, tws, threadIdx.x, blockDim.x);
+}
+
+// Workgroup index remapped so that consecutive line blocks run on the same XCD
+// (workgroups are dealt to the 8 XCDs round-robin).  Bijective on [0, nblocks).
+__device__ inline int xcd_block(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 }  // namespace spfc

@@ -1,5 +1,8 @@
-// Single-workgroup reduction that closes the start-up, query and end-of-run
-// passes (the per-step reduction lives in the last workgroup of k_spec_fwd).
+// Single-workgroup reduction that closes every step (the SAV scalar solve) and
+// the start-up, query and end-of-run passes.  A separate launch, rather than the
+// last workgroup of the forward pass, because publishing the partial sums from
+// inside that kernel would need an agent-scope release per workgroup, which on a
+// multi-XCD part writes back the L2.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -7,11 +10,53 @@ namespace spfc {
 
 // ------------------------------------------------------------------ finalize (one workgroup)
 
-__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs p) {
-    double sA[4], sB[1];
-    block_sum_partials<4>(p.partA, p.nA, sA);
-    block_sum_partials<1>(p.partB, p.nB, sB);
+// Fixed-order sum of all partials of a step in one sweep: every thread reads its
+// fixed subset of the three partial arrays (all loads in flight together), then
+// one tree over the workgroup.
+__device__ inline void sum_all_partials(const FinalizeArgs& p, double (&sA)[4], double (&sB)[1], double (&sC)[3]) {
+    __shared__ double red[8][16];
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int nC = p.mode == FIN_STEP ? p.nC : 0;
+    const int n = max(p.nA, max(p.nB, nC));
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        if (j < p.nA) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] += p.partA[(size_t)4 * j + i];
+        }
+        if (j < p.nB) acc[4] += p.partB[j];
+        if (j < nC) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc[5 + i] += p.partC[(size_t)3 * j + i];
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[i][wave] = acc[i];
+    }
+    __syncthreads();
+    double s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        s[i] = 0.0;
+        for (int w = 0; w < nw; ++w) s[i] += red[i][w];
+    }
+    for (int i = 0; i < 4; ++i) sA[i] = s[i];
+    sB[0] = s[4];
+    for (int i = 0; i < 3; ++i) sC[i] = s[5 + i];
+}
+
+__global__ void __launch_bounds__(512) k_finalize(FinalizeArgs p) {
+    double sA[4], sB[1], sC[3];
+    sum_all_partials(p, sA, sB, sC);
     if (threadIdx.x != 0) return;
+    if (p.mode == FIN_STEP) {
+        finish_step(sB[0], sA, sC, p.sc, p.hist, p.hist_cap, p.step, p.a0, p.a1, p.a2, p.dt, p.check_rise,
+                    p.energy_tol, p.geo);
+        return;
+    }
     const Geo& geo = p.geo;
     DevScalars* sc = p.sc;
     const double E1 = geo.cell * sB[0] + geo.e1_const;
@@ -53,7 +98,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs p) {
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 

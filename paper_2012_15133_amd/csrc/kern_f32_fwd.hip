@@ -1,0 +1,7 @@
+// float instances: spectral forward pass (N, the two Fourier solves, inner products, SAV scalar).
+#include "kern_impl.hpp"
+
+namespace spfc {
+template hipError_t Kern<float>::spec_fwd(int, int, int, const SpecFwdArgs<float>&, const LaunchShape&,
+                                          hipStream_t);
+}  // namespace spfc

@@ -1,0 +1,9 @@
+// double instances: generic line passes, row transforms and the elementwise update.
+#include "kern_impl.hpp"
+
+namespace spfc {
+template hipError_t Kern<double>::pass(int, int, int, int, const PassArgs<double>&, const LaunchShape&, hipStream_t);
+template hipError_t Kern<double>::update(int, const UpdateArgs<double>&, int, int, hipStream_t);
+template hipError_t Kern<double>::r2c_rows(int, const RowArgs<double>&, const LaunchShape&, hipStream_t);
+template hipError_t Kern<double>::c2r_rows(int, bool, const RowArgs<double>&, const LaunchShape&, hipStream_t);
+}  // namespace spfc

@@ -1,0 +1,6 @@
+// double instances: spectral inverse pass (update + gradient + inverse transform).
+#include "kern_impl.hpp"
+
+namespace spfc {
+template hipError_t Kern<double>::spec_inv(int, int, const SpecInvArgs<double>&, const LaunchShape&, hipStream_t);
+}  // namespace spfc

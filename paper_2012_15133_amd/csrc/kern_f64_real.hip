@@ -1,0 +1,6 @@
+// double instances: real-space pass (C2R, pointwise SPFC flux, R2C).
+#include "kern_impl.hpp"
+
+namespace spfc {
+template hipError_t Kern<double>::real_pass(int, int, bool, const RealArgs<double>&, const LaunchShape&, hipStream_t);
+}  // namespace spfc

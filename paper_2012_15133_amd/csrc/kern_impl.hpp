@@ -5,62 +5,79 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
+#include <type_traits>
+
 namespace spfc {
 
-#define SPFC_SWITCH_N(n, BODY)            \
-    switch (n) {                          \
-        case 8: { constexpr int NN = 8; BODY; } \
-        case 16: { constexpr int NN = 16; BODY; } \
-        case 32: { constexpr int NN = 32; BODY; } \
-        case 64: { constexpr int NN = 64; BODY; } \
-        case 128: { constexpr int NN = 128; BODY; } \
-        case 256: { constexpr int NN = 256; BODY; } \
-        case 512: { constexpr int NN = 512; BODY; } \
-        case 1024: { constexpr int NN = 1024; BODY; } \
-        default: return hipErrorInvalidValue; \
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Call f(IC<n>, IC<e>) for the line length n and the values per thread e (8 or
+// 16; n itself for n = 8).
+template <typename F>
+hipError_t dispatch_ne(int n, int e, F&& f) {
+    const bool e8 = (e == 8);
+    switch (n) {
+        case 8: return f(IC<8>{}, IC<8>{});
+        case 16: return e8 ? f(IC<16>{}, IC<8>{}) : f(IC<16>{}, IC<16>{});
+        case 32: return e8 ? f(IC<32>{}, IC<8>{}) : f(IC<32>{}, IC<16>{});
+        case 64: return e8 ? f(IC<64>{}, IC<8>{}) : f(IC<64>{}, IC<16>{});
+        case 128: return e8 ? f(IC<128>{}, IC<8>{}) : f(IC<128>{}, IC<16>{});
+        case 256: return e8 ? f(IC<256>{}, IC<8>{}) : f(IC<256>{}, IC<16>{});
+        case 512: return e8 ? f(IC<512>{}, IC<8>{}) : f(IC<512>{}, IC<16>{});
+        case 1024: return e8 ? f(IC<1024>{}, IC<8>{}) : f(IC<1024>{}, IC<16>{});
+        default: return hipErrorInvalidValue;
     }
+}
+
+#define SPFC_NE_CONSTS               \
+    constexpr int NN = decltype(nn)::value; \
+    constexpr int EE = decltype(ee)::value;
 
 template <typename T>
 hipError_t Kern<T>::spec_inv(int nl, int dim, const SpecInvArgs<T>& a, const LaunchShape& s, hipStream_t st) {
-    SPFC_SWITCH_N(nl, {
-        if (dim == 2) hipLaunchKernelGGL((k_spec_inv<T, NN, 2>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-        else hipLaunchKernelGGL((k_spec_inv<T, NN, 3>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+    return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
+        if (dim == 2) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+        else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
-    })
+    });
 }
 
 template <typename T>
 hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, const LaunchShape& s,
                               hipStream_t st) {
-    SPFC_SWITCH_N(nx, {
+    return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
         if (dim == 2) {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, 2, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, 2, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         } else {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, 3, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, 3, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         }
         return hipGetLastError();
-    })
+    });
 }
 
 template <typename T>
 hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, const SpecFwdArgs<T>& a, const LaunchShape& s,
                              hipStream_t st) {
-    SPFC_SWITCH_N(nl, {
+    return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
         if (dim == 2) {
             if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, 2, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
             else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, 2, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         } else {
             if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, 3, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
             else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, 3, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         }
         return hipGetLastError();
-    })
+    });
 }
 
 template <typename T>
@@ -68,10 +85,11 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
                          hipStream_t st) {
 #define SPFC_PASS_CASE(D, OM, CC)                                                                      \
     if (dir == D && omode == OM && c == CC) {                                                        \
-        hipLaunchKernelGGL((k_pass<T, NN, D, OM, CC>), dim3(s.grid), dim3(s.block), s.shmem, st, a); \
+        hipLaunchKernelGGL((k_pass<T, NN, EE, D, OM, CC>), dim3(s.grid), dim3(s.block), s.shmem, st, a); \
         return hipGetLastError();                                                                    \
     }
-    SPFC_SWITCH_N(nl, {
+    return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
         SPFC_PASS_CASE(-1, OUT_KEEP, 1)
         SPFC_PASS_CASE(-1, OUT_SWAP, 1)
         SPFC_PASS_CASE(+1, OUT_ROTATE, 1)
@@ -79,7 +97,7 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
         SPFC_PASS_CASE(+1, OUT_SWAP, 3)
         SPFC_PASS_CASE(-1, OUT_SWAP, 3)
         return hipErrorInvalidValue;
-    })
+    });
 #undef SPFC_PASS_CASE
 }
 
@@ -92,21 +110,23 @@ hipError_t Kern<T>::update(int dim, const UpdateArgs<T>& a, int grid, int block,
 
 template <typename T>
 hipError_t Kern<T>::r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st) {
-    SPFC_SWITCH_N(nx, {
-        hipLaunchKernelGGL((k_r2c_rows<T, NN, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+    return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
+        hipLaunchKernelGGL((k_r2c_rows<T, NN, EE, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
-    })
+    });
 }
 
 template <typename T>
 hipError_t Kern<T>::c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st) {
-    SPFC_SWITCH_N(nx, {
-        if (out_fp32) hipLaunchKernelGGL((k_c2r_rows<T, NN, float>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-        else hipLaunchKernelGGL((k_c2r_rows<T, NN, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+    return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
+        if (out_fp32) hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, float>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+        else hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
-    })
+    });
 }
 
-#undef SPFC_SWITCH_N
+#undef SPFC_NE_CONSTS
 
 }  // namespace spfc

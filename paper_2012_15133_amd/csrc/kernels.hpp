@@ -129,41 +129,48 @@ __device__ inline void spec_symbols(const Geo& g, int kx, int ky, int kz, double
 // ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2 (modified energy,
 // eq. discrete energy; E_N, eq. energy-discrete-spectral).  Then
 // Z_j = i kappa1_j (e1 X + e2 Y) and the inverse transform along the line.
-template <typename T, int NL, int DIM>
+template <typename T, int NL, int EE, int DIM>
 __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
-    constexpr int E = Plan<NL>::E, P = Plan<NL>::P, C = DIM;
+    using PL = Plan<NL, EE>;
+    constexpr int E = PL::E, P = PL::P, C = DIM;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int line = blockIdx.x * p.G + g;
+    const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
     const Geo& geo = p.geo;
     const size_t lbase = (size_t)(act ? line : 0) * NL;
     const double xi = p.update ? p.xi[0] : 0.0;
 
+    // all loads first (the update writes in place over `prev`, so later loads
+    // must not wait behind earlier stores)
+    cpx<T> cur[E], prv[E], nh[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const size_t i = lbase + t + P * m;
+        cur[m] = act ? p.cur[i] : mk<T>(0, 0);
+        prv[m] = act ? p.prev[i] : mk<T>(0, 0);
+        nh[m] = (act && p.update) ? p.nhat[i] : mk<T>(0, 0);
+    }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     cpx<T> v[C][E];
+    const T h1 = T(p.e1), h2 = T(p.e2);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int e = t + P * m;
-        cpx<T> X = mk<T>(0, 0), Y = mk<T>(0, 0);
+        cpx<T> X = cur[m], Y = prv[m];
         int kx = 0, ky = 0, kz = 0;
         double k2 = 0.0, k1[3] = {0.0, 0.0, 0.0};
         if (act) {
             spec_index<DIM>(line, p.B, e, kx, ky, kz);
             spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
-            const cpx<T> cur = p.cur[lbase + e];
             if (p.update) {
-                const cpx<T> prv = p.prev[lbase + e];
-                const cpx<T> nh = p.nhat[lbase + e];
-                const double A = p.ua0 + p.udt * k2 * (geo.a + k2 * k2);
-                const T f1 = T(-p.udt * xi * k2 / A), f2 = T(p.ua1 / A), f3 = T(p.ua2 / A);
-                X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
-                Y = cur;
+                const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
+                const T f1 = T(-p.udt * xi * k2 * iA), f2 = T(p.ua1 * iA), f3 = T(p.ua2 * iA);
+                X = mk<T>(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x, f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y);
+                Y = cur[m];
                 p.out_new[lbase + e] = X;
-            } else {
-                X = cur;
-                Y = p.prev[lbase + e];
             }
             const double w = hweight(kx, geo.nx);
             const double Lk = geo.a + k2 * k2;
@@ -175,7 +182,6 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             acc[3] += w * k2 * k2 * xx;
             if (line == 0 && e == 0) p.mean_raw[0] = (double)X.x;
         }
-        const T h1 = T(p.e1), h2 = T(p.e2);
         const cpx<T> ph = mk<T>(h1 * X.x + h2 * Y.x, h1 * X.y + h2 * Y.y);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
@@ -184,7 +190,8 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
         }
     }
     if (p.want_grad) {
-        fft_run<T, NL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+        stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+        fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
         if (act) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -236,15 +243,17 @@ __device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e) 
 // Gradient rows (half spectra along x) -> C2R -> s = |grad phihat|^2,
 // E_1 partial sum (c4/4) s^2 - s, q = c4 s grad phihat (eq. nonlinear chem pot-1) ->
 // R2C -> flux spectra written rotated [kx][rows].  FWD = false: E_1 only.
-template <typename T, int NX, int DIM, bool FWD>
+template <typename T, int NX, int EE, int DIM, bool FWD>
 __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     using PK = RealPack<DIM>;
-    constexpr int E = Plan<NX>::E, P = Plan<NX>::P, C = PK::C, RPG = PK::RPG;
+    using PL = Plan<NX, EE>;
+    constexpr int E = PL::E, P = PL::P, C = PK::C, RPG = PK::RPG;
     constexpr int NXH = NX / 2 + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * C * LdsLine<NX>::size;
+    cpx<T>* ltw = reinterpret_cast<cpx<T>*>(smem_raw) + p.G * C * LdsLine<NX>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int row0 = (blockIdx.x * p.G + g) * RPG;
+    const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * RPG;
     const bool act = row0 < p.nrows;
     const Geo& geo = p.geo;
 
@@ -256,7 +265,8 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
 #pragma unroll
         for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
     }
-    fft_run<T, NX, +1, C>(v, lds, t, p.tw, p.tws);
+    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    fft_run<T, PL, +1, C>(v, lds, t, ltw);
 
     const T sc = T(geo.inv_npts), c4 = T(geo.c4);
     const double qc4 = 0.25 * geo.c4;
@@ -284,11 +294,11 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     if (!act) acc[0] = 0.0;
 
     if constexpr (FWD) {
-        fft_run<T, NX, -1, C>(v, lds, t, p.tw, p.tws);
+        fft_run<T, PL, -1, C>(v, lds, t, ltw);
         // split V = Q1 + i Q2 into the two half spectra: Q1(k) = (V(k) + conj V(-k)) / 2,
         // Q2(k) = (V(k) - conj V(-k)) / (2 i).
         __syncthreads();
-        line_store<T, NX, C>(v, lds, t);
+        line_store<T, PL, C>(v, lds, t);
         __syncthreads();
         if (act) {
             const T half = T(0.5);
@@ -316,13 +326,15 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
 
 // ------------------------------------------------------------------ generic line pass
 
-template <typename T, int NL, int DIR, int OMODE, int C>
+template <typename T, int NL, int EE, int DIR, int OMODE, int C>
 __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
-    constexpr int E = Plan<NL>::E, P = Plan<NL>::P;
+    using PL = Plan<NL, EE>;
+    constexpr int E = PL::E, P = PL::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int line = blockIdx.x * p.G + g;
+    const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
     const size_t lbase = (size_t)(act ? line : 0) * NL;
     cpx<T> v[C][E];
@@ -330,7 +342,8 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
     for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][lbase + t + P * m] : mk<T>(0, 0);
-    fft_run<T, NL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
     if (!act) return;
     const int a = line / p.B, b = line - a * p.B;
 #pragma unroll
@@ -402,13 +415,15 @@ __device__ inline void finish_step(double E1sum, const double (&nA)[4],
     sc->last_record = step;
 }
 
-template <typename T, int NL, int DIM, int MODE>
+template <typename T, int NL, int EE, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
-    constexpr int E = Plan<NL>::E, P = Plan<NL>::P, C = DIM;
+    using PL = Plan<NL, EE>;
+    constexpr int E = PL::E, P = PL::P, C = DIM;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int line = blockIdx.x * p.G + g;
+    const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
     const Geo& geo = p.geo;
     const size_t lbase = (size_t)(act ? line : 0) * NL;
@@ -418,8 +433,15 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     for (int j = 0; j < C; ++j)
 #pragma unroll
         for (int m = 0; m < E; ++m) v[j][m] = act ? p.in[j][lbase + t + P * m] : mk<T>(0, 0);
-    fft_run<T, NL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, p.tw, p.tws);
+    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    fft_run<T, PL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
 
+    cpx<T> Xs[E], Ys[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        Xs[m] = act ? p.X[lbase + t + P * m] : mk<T>(0, 0);
+        Ys[m] = act ? p.Y[lbase + t + P * m] : mk<T>(0, 0);
+    }
     double acc[3] = {0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
@@ -429,7 +451,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             double k2, k1[3];
             spec_index<DIM>(line, p.B, e, kx, ky, kz);
             spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
-            const cpx<T> X = p.X[lbase + e], Y = p.Y[lbase + e];
+            const cpx<T> X = Xs[m], Y = Ys[m];
             const double phx = p.e1 * X.x + p.e2 * Y.x, phy = p.e1 * X.y + p.e2 * Y.y;
             // div of the flux: sum_j i kappa1_j Q_j; N = -div - 2 |k|^2 phihat
             double dx = 0.0, dy = 0.0;
@@ -442,11 +464,11 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             const double Ny = -dx - 2.0 * k2 * phy;
             if constexpr (MODE == FWD_SOLVE) {
                 const double psx = p.a1 * X.x + p.a2 * Y.x, psy = p.a1 * X.y + p.a2 * Y.y;
-                const double A = p.a0 + p.dt * k2 * (geo.a + k2 * k2);
+                const double iA = 1.0 / (p.a0 + p.dt * k2 * (geo.a + k2 * k2));
                 const double w = hweight(kx, geo.nx);
                 const double re = Nx * psx + Ny * psy;
-                acc[0] += -w * k2 * (Nx * Nx + Ny * Ny) / A;
-                acc[1] += w * re / A;
+                acc[0] -= w * k2 * (Nx * Nx + Ny * Ny) * iA;
+                acc[1] += w * re * iA;
                 acc[2] += w * re;
                 p.nhat[lbase + e] = mk<T>(T(Nx), T(Ny));
             } else {
@@ -456,29 +478,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             }
         }
     }
-    if constexpr (MODE == FWD_SOLVE) {
-        block_sum_store<3>(acc, p.partC + 3 * blockIdx.x);
-        // last workgroup to arrive reduces every partial of the step and finishes it
-        __shared__ int is_last;
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            const unsigned int prev = atomicAdd(&p.sc->ticket, 1u);
-            is_last = (prev == gridDim.x - 1) ? 1 : 0;
-        }
-        __syncthreads();
-        if (!is_last) return;
-        __threadfence();
-        double sA[4], sB[1], sC[3];
-        block_sum_partials<4>(p.partA, p.nA, sA);
-        block_sum_partials<1>(p.partB, p.nB, sB);
-        block_sum_partials<3>(p.partC, gridDim.x, sC);
-        if (tid == 0) {
-            finish_step(sB[0], sA, sC, p.sc, p.hist, p.hist_cap, p.step, p.a0, p.a1, p.a2, p.dt,
-                        p.check_rise, p.energy_tol, geo);
-            p.sc->ticket = 0u;
-        }
-    }
+    if constexpr (MODE == FWD_SOLVE) block_sum_store<3>(acc, p.partC + 3 * blockIdx.x);
 }
 
 // ------------------------------------------------------------------ elementwise pending update
@@ -496,8 +496,8 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         spec_index<DIM>(line, p.B, e, kx, ky, kz);
         spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
         const cpx<T> cur = p.cur[i], prv = p.prev[i], nh = p.nhat[i];
-        const double A = p.ua0 + p.udt * k2 * (geo.a + k2 * k2);
-        const T f1 = T(-p.udt * xi * k2 / A), f2 = T(p.ua1 / A), f3 = T(p.ua2 / A);
+        const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
+        const T f1 = T(-p.udt * xi * k2 * iA), f2 = T(p.ua1 * iA), f3 = T(p.ua2 * iA);
         const cpx<T> X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
         p.out_new[i] = X;
         const double w = hweight(kx, geo.nx);
@@ -516,13 +516,15 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
 // ------------------------------------------------------------------ rows: real <-> half spectrum
 
 // Two real rows per complex line: W = row0 + i row1, forward transform, split.
-template <typename T, int NX, typename InT>
+template <typename T, int NX, int EE, typename InT>
 __global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
-    constexpr int E = Plan<NX>::E, P = Plan<NX>::P;
+    using PL = Plan<NX, EE>;
+    constexpr int E = PL::E, P = PL::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * LdsLine<NX>::size;
+    cpx<T>* ltw = reinterpret_cast<cpx<T>*>(smem_raw) + p.G * LdsLine<NX>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int row0 = (blockIdx.x * p.G + g) * 2;
+    const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * 2;
     const bool act = row0 < p.nrows;
     const InT* in = reinterpret_cast<const InT*>(p.in);
     cpx<T> v[1][E];
@@ -531,9 +533,10 @@ __global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
         const int x = t + P * m;
         v[0][m] = act ? mk<T>(T(in[(size_t)row0 * NX + x]), T(in[(size_t)(row0 + 1) * NX + x])) : mk<T>(0, 0);
     }
-    fft_run<T, NX, -1, 1>(v, lds, t, p.tw, p.tws);
+    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    fft_run<T, PL, -1, 1>(v, lds, t, ltw);
     __syncthreads();
-    line_store<T, NX, 1>(v, lds, t);
+    line_store<T, PL, 1>(v, lds, t);
     __syncthreads();
     if (!act) return;
     cpx<T>* out = reinterpret_cast<cpx<T>*>(p.out);
@@ -550,14 +553,16 @@ __global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
 }
 
 // Two half-spectrum rows -> one complex line -> inverse transform -> two real rows, scaled.
-template <typename T, int NX, typename OutT>
+template <typename T, int NX, int EE, typename OutT>
 __global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
-    constexpr int E = Plan<NX>::E, P = Plan<NX>::P;
+    using PL = Plan<NX, EE>;
+    constexpr int E = PL::E, P = PL::P;
     constexpr int NXH = NX / 2 + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw) + (threadIdx.x / P) * LdsLine<NX>::size;
+    cpx<T>* ltw = reinterpret_cast<cpx<T>*>(smem_raw) + p.G * LdsLine<NX>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
-    const int row0 = (blockIdx.x * p.G + g) * 2;
+    const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * 2;
     const bool act = row0 < p.nrows;
     const cpx<T>* in = reinterpret_cast<const cpx<T>*>(p.in);
     const cpx<T>* h1 = in + (size_t)(act ? row0 : 0) * NXH;
@@ -565,7 +570,8 @@ __global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
     cpx<T> v[1][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[0][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
-    fft_run<T, NX, +1, 1>(v, lds, t, p.tw, p.tws);
+    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    fft_run<T, PL, +1, 1>(v, lds, t, ltw);
     if (!act) return;
     OutT* out = reinterpret_cast<OutT*>(p.out);
 #pragma unroll

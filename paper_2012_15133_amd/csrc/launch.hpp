@@ -10,26 +10,32 @@ namespace spfc {
 
 // Shape of one launch of a line kernel.
 struct LaunchShape {
+    int E;          // values per thread (radix of the full passes)
     int G;          // line groups per workgroup
     int block;      // threads per workgroup
     int grid;       // workgroups
     size_t shmem;   // dynamic LDS bytes
 };
 
-// P threads per group, C complex lines per group, groups needed in total.
-inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int want_threads = 256,
+// E values per thread (clamped to the line length), P = N / E threads per group,
+// C complex lines per group, ngroups groups in total.  LDS: the groups' line
+// buffers plus the twiddle table of length N.
+inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int E = 16, int want_threads = 256,
                               size_t lds_cap = 65536) {
-    const int E = N >= 16 ? 16 : N;
+    E = std::min(E, N);
+    if (N < 16) E = N;
     const int P = N / E;
     const size_t per = (size_t)C * (size_t)(N + N / 16) * elem;
+    const size_t twb = (size_t)N * elem;
     int G = std::max(1, want_threads / P);
-    while (G > 1 && (size_t)G * per > lds_cap) --G;
+    while (G > 1 && (size_t)G * per + twb > lds_cap) --G;
     G = std::max(1, std::min(G, ngroups));
     LaunchShape s;
+    s.E = E;
     s.G = G;
     s.block = G * P;
     s.grid = (ngroups + G - 1) / G;
-    s.shmem = (size_t)G * per;
+    s.shmem = (size_t)G * per + twb;
     return s;
 }
 
@@ -44,6 +50,8 @@ struct Kern {
                            hipStream_t st);
     static hipError_t update(int dim, const UpdateArgs<T>& a, int grid, int block, hipStream_t st);
     static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
+    // values per thread available for line length n
+    static bool has_E(int n, int E) { return n < 16 ? E == n : (E == 8 || E == 16); }
     static hipError_t c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
 };
 

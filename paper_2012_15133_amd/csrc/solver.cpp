@@ -2,6 +2,8 @@
 // per-step launch sequence, start-up, queries and checkpoints.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -18,8 +20,9 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool pow2_ok(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
 
-enum Role { R_SPEC_INV = 0, R_MID_INV, R_REAL, R_MID_FWD, R_SPEC_FWD, R_COUNT };
-const char* const kRoleNames[R_COUNT] = {"spec_inv", "pass_y_inv", "real_pass", "pass_y_fwd", "spec_fwd"};
+enum Role { R_SPEC_INV = 0, R_MID_INV, R_REAL, R_MID_FWD, R_SPEC_FWD, R_FINAL, R_COUNT };
+const char* const kRoleNames[R_COUNT] = {"spec_inv", "pass_y_inv", "real_pass", "pass_y_fwd", "spec_fwd",
+                                         "step_finalize"};
 
 struct Sizes {
     int dim, nx, ny, nz, nxh;
@@ -50,18 +53,51 @@ Sizes sizes_of(const spfc_grid& g, int prec) {
     return s;
 }
 
+// Launch plan of the step kernels: values per thread (E) and target threads per
+// workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T".
+struct RolePlan {
+    int E = 16, T = 256;
+};
+struct TunePlan {
+    RolePlan inv, real, fwd, mid, misc;
+};
+
+void parse_role(const char* spec, const char* key, RolePlan& r) {
+    const char* p = std::strstr(spec, key);
+    if (!p) return;
+    p += std::strlen(key);
+    if (*p != '=') return;
+    int e = 0, t = 0;
+    if (std::sscanf(p + 1, "%d/%d", &e, &t) >= 1) {
+        if (e == 8 || e == 16) r.E = e;
+        if (t >= 64 && t <= 256) r.T = t;
+    }
+}
+
+TunePlan tune_plan() {
+    TunePlan tp;
+    if (const char* env = std::getenv("SPFC_PLAN")) {
+        parse_role(env, "inv", tp.inv);
+        parse_role(env, "real", tp.real);
+        parse_role(env, "fwd", tp.fwd);
+        parse_role(env, "mid", tp.mid);
+    }
+    return tp;
+}
+
 Shapes shapes_of(const Sizes& s) {
+    const TunePlan tp = tune_plan();
     Shapes h{};
     const int d = s.dim;
     const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
     const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines
-    h.A = line_shape(nl, d, s.elem, nlines);
-    h.Cf = line_shape(nl, d, s.elem, nlines);
+    h.A = line_shape(nl, d, s.elem, nlines, tp.inv.E, tp.inv.T);
+    h.Cf = line_shape(nl, d, s.elem, nlines, tp.fwd.E, tp.fwd.T);
     const int rowgroups = d == 2 ? s.ny : s.nz * s.ny / 2;
-    h.B = line_shape(s.nx, d == 2 ? 1 : 3, s.elem, rowgroups);
+    h.B = line_shape(s.nx, d == 2 ? 1 : 3, s.elem, rowgroups, tp.real.E, tp.real.T);
     if (d == 3) {
-        h.midI = line_shape(s.ny, 3, s.elem, s.nz * s.nxh);
-        h.midF = line_shape(s.ny, 3, s.elem, s.nxh * s.nz);
+        h.midI = line_shape(s.ny, 3, s.elem, s.nz * s.nxh, tp.mid.E, tp.mid.T);
+        h.midF = line_shape(s.ny, 3, s.elem, s.nxh * s.nz, tp.mid.E, tp.mid.T);
         h.swapInit = line_shape(s.ny, 1, s.elem, s.nxh * s.nz);
         h.swapGet = line_shape(s.ny, 1, s.elem, s.nz * s.nxh);
     }
@@ -331,13 +367,20 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    int finalize(int mode, int nA, int check_rise) {
+    int finalize(int mode, int nA, int check_rise, double a0 = 0, double a1 = 0, double a2 = 0, double dt = 0,
+                 bool timed = false) {
         FinalizeArgs f{};
         f.mode = mode;
         f.partA = ctx->partA();
         f.nA = nA;
         f.partB = ctx->partB();
         f.nB = ctx->sh.B.grid;
+        f.partC = ctx->partC();
+        f.nC = ctx->sh.Cf.grid;
+        f.a0 = a0;
+        f.a1 = a1;
+        f.a2 = a2;
+        f.dt = dt;
         f.sc = ctx->sc();
         f.hist = ctx->hist();
         f.hist_cap = ctx->prm.history;
@@ -345,6 +388,7 @@ struct Pipe {
         f.check_rise = check_rise;
         f.energy_tol = ctx->energy_tol;
         f.geo = ctx->geo;
+        Timed tm(ctx, R_FINAL, timed);
         CK(launch_finalize(f, ctx->stream));
         return SPFC_OK;
     }
@@ -442,6 +486,8 @@ struct Pipe {
             if ((rc = spec_fwd(flux, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt,
                                e1, e2, check, true)))
                 return rc;
+            // the SAV scalar: xi, r^{n+1}, the record of phi^n
+            if ((rc = finalize(FIN_STEP, ctx->sh.A.grid, check, a0, a1, a2, dt, true))) return rc;
             pa0 = a0;
             pa1 = a1;
             pa2 = a2;
@@ -857,7 +903,7 @@ int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms
     if (rc) return rc;
     const double F = (double)ctx->lay.F;
     const int d = ctx->sz.dim;
-    const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F};
+    const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F, 0.0};
     int k = 0;
     for (int i = 0; i < R_COUNT; ++i) {
         if (ctx->role_n[i] == 0) continue;

@@ -88,13 +88,14 @@ def _emu():
     if not os.path.exists(path):
         path = B.build_emulator()
     lib = ctypes.CDLL(path)
-    lib.emu_fft_lines.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 2
+    lib.emu_fft_lines.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p] * 2
     return lib
 
 
+@pytest.mark.parametrize("e", [16, 8, 4])
 @pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024])
-def test_line_fft_schedule_matches_dft(fp32, n):
+def test_line_fft_schedule_matches_dft(fp32, n, e):
     """The Stockham schedule of the kernels (fft_core.hpp), run thread by thread on the
     host, against the DFT definition evaluated by matrix product."""
     lib = _emu()
@@ -105,7 +106,8 @@ def test_line_fft_schedule_matches_dft(fp32, n):
         for c in (1, 3):
             x = rng.standard_normal((c, n)) + 1j * rng.standard_normal((c, n))
             out = np.zeros((c, n), complex)
-            assert lib.emu_fft_lines(fp32, n, sign, c, np.ascontiguousarray(x).ctypes.data, out.ctypes.data) == 0
+            assert lib.emu_fft_lines(fp32, n, e, sign, c, np.ascontiguousarray(x).ctypes.data,
+                                     out.ctypes.data) == 0
             ref = x @ W.T
             err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
             # FFT rounding grows like eps * log2(n)
