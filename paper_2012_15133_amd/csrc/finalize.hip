@@ -18,16 +18,22 @@ __device__ inline void sum_all_partials(const FinalizeArgs& p, double (&sA)[4], 
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int nC = p.mode == FIN_STEP ? p.nC : 0;
     const int n = max(p.nA, max(p.nB, nC));
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        if (j < p.nA) {
+    constexpr int U = 4;   // indices per thread per sweep, loaded before any is added
+    for (int j0 = threadIdx.x; j0 < n; j0 += U * blockDim.x) {
+        double v[U][8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] += p.partA[(size_t)4 * j + i];
-        }
-        if (j < p.nB) acc[4] += p.partB[j];
-        if (j < nC) {
+        for (int q = 0; q < U; ++q) {
+            const int j = j0 + q * blockDim.x;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) acc[5 + i] += p.partC[(size_t)3 * j + i];
+            for (int i = 0; i < 4; ++i) v[q][i] = j < p.nA ? p.partA[(size_t)4 * j + i] : 0.0;
+            v[q][4] = j < p.nB ? p.partB[j] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) v[q][5 + i] = j < nC ? p.partC[(size_t)3 * j + i] : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += v[q][i];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -48,7 +54,7 @@ __device__ inline void sum_all_partials(const FinalizeArgs& p, double (&sA)[4], 
     for (int i = 0; i < 3; ++i) sC[i] = s[5 + i];
 }
 
-__global__ void __launch_bounds__(512) k_finalize(FinalizeArgs p) {
+__global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
     double sA[4], sB[1], sC[3];
     sum_all_partials(p, sA, sB, sC);
     if (threadIdx.x != 0) return;
@@ -98,7 +104,7 @@ __global__ void __launch_bounds__(512) k_finalize(FinalizeArgs p) {
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(512), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 

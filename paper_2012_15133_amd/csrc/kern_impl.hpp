@@ -12,20 +12,25 @@ namespace spfc {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// Call f(IC<n>, IC<e>) for the line length n and the values per thread e (8 or
+// Call f(IC<n>, IC<e>) for the line length n and the values per thread e (4, 8 or
 // 16; n itself for n = 8).
 template <typename F>
 hipError_t dispatch_ne(int n, int e, F&& f) {
-    const bool e8 = (e == 8);
     switch (n) {
         case 8: return f(IC<8>{}, IC<8>{});
-        case 16: return e8 ? f(IC<16>{}, IC<8>{}) : f(IC<16>{}, IC<16>{});
-        case 32: return e8 ? f(IC<32>{}, IC<8>{}) : f(IC<32>{}, IC<16>{});
-        case 64: return e8 ? f(IC<64>{}, IC<8>{}) : f(IC<64>{}, IC<16>{});
-        case 128: return e8 ? f(IC<128>{}, IC<8>{}) : f(IC<128>{}, IC<16>{});
-        case 256: return e8 ? f(IC<256>{}, IC<8>{}) : f(IC<256>{}, IC<16>{});
-        case 512: return e8 ? f(IC<512>{}, IC<8>{}) : f(IC<512>{}, IC<16>{});
-        case 1024: return e8 ? f(IC<1024>{}, IC<8>{}) : f(IC<1024>{}, IC<16>{});
+#define SPFC_NE_CASE(NV)                               \
+    case NV:                                           \
+        if (e == 4) return f(IC<NV>{}, IC<4>{});       \
+        if (e == 8) return f(IC<NV>{}, IC<8>{});       \
+        return f(IC<NV>{}, IC<16>{});
+        SPFC_NE_CASE(16)
+        SPFC_NE_CASE(32)
+        SPFC_NE_CASE(64)
+        SPFC_NE_CASE(128)
+        SPFC_NE_CASE(256)
+        SPFC_NE_CASE(512)
+        SPFC_NE_CASE(1024)
+#undef SPFC_NE_CASE
         default: return hipErrorInvalidValue;
     }
 }

@@ -368,26 +368,26 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
 // b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
 //   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
 // p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1).
-__device__ inline void finish_step(double E1sum, const double (&nA)[4],
-                                   const double (&sC)[3], DevScalars* sc, Record* hist, long long cap,
-                                   long long step, double a0, double a1, double a2, double dt, int check_rise,
-                                   double tol, const Geo& geo) {
+__device__ inline void finish_step(double E1sum, const double (&nA)[4], const double (&sC)[3], DevScalars* sc,
+                                   Record* hist, long long cap, long long step, double a0, double a1, double a2,
+                                   double dt, int check_rise, double tol, const Geo& geo) {
+    // every read of the scalar block first, then the arithmetic, then the stores
+    const double rn = sc->r_n, rnm1 = sc->r_nm1, eprev = sc->energy_prev, mraw = sc->mean_raw;
+    unsigned int fl = sc->flags;
     const double E1 = geo.cell * E1sum + geo.e1_const;
     const double n0 = geo.pscale * nA[0], n1 = geo.pscale * nA[1];
     const double p1 = geo.pscale * sC[0], p2 = geo.pscale * sC[1], pp = geo.pscale * sC[2];
-    const double rn = sc->r_n, rnm1 = sc->r_nm1;
     const double S = sqrt(E1);
     const double rho = a1 * rn + a2 * rnm1;
     const double xi = (rho + (a0 * p2 - pp) / (2.0 * S)) / (a0 * (S - dt * p1 / (2.0 * S)));
     const double rnew = xi * S;
     const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
-    const double mean = sc->mean_raw * geo.inv_npts;
-    unsigned int fl = sc->flags;
+    const double mean = mraw * geo.inv_npts;
     if (!isfinite(E1) || !isfinite(p1) || !isfinite(p2) || !isfinite(pp) || !isfinite(xi) || !isfinite(energy))
         fl |= FLAG_NONFINITE;
     if (E1 < geo.volume * (1.0 - 1e-12)) fl |= FLAG_E1_BELOW_OMEGA;
     if (p1 > 0.0) fl |= FLAG_P1_POSITIVE;
-    if (check_rise && energy > sc->energy_prev * (1.0 + tol)) fl |= FLAG_ENERGY_RISE;
+    if (check_rise && energy > eprev * (1.0 + tol)) fl |= FLAG_ENERGY_RISE;
     Record* rc = hist + (step % cap);
     rc->energy = energy;
     rc->mean = mean;

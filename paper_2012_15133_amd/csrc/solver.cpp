@@ -56,7 +56,7 @@ Sizes sizes_of(const spfc_grid& g, int prec) {
 // Launch plan of the step kernels: values per thread (E) and target threads per
 // workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T".
 struct RolePlan {
-    int E = 16, T = 256;
+    int E = 8, T = 256;
 };
 struct TunePlan {
     RolePlan inv, real, fwd, mid, misc;
@@ -69,7 +69,7 @@ void parse_role(const char* spec, const char* key, RolePlan& r) {
     if (*p != '=') return;
     int e = 0, t = 0;
     if (std::sscanf(p + 1, "%d/%d", &e, &t) >= 1) {
-        if (e == 8 || e == 16) r.E = e;
+        if (e == 4 || e == 8 || e == 16) r.E = e;
         if (t >= 64 && t <= 256) r.T = t;
     }
 }
