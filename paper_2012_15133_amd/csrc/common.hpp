@@ -21,8 +21,10 @@ struct Geo {
     double e1_const;      // (1 + 1/c4) |Omega|
 };
 
-// Device-resident scalars of the run.  Written by single lanes of the finalize
-// code only (vector stores), read by the next launches.
+// Device-resident scalars of the run.  Written by one lane only (vector stores),
+// read by later launches.  Two copies: a step's finish reads one and writes the
+// other, so that the workgroups that still read the old values in the same
+// launch never see a half-written block.
 struct DevScalars {
     double xi;            // xi of the latest solved step (used by the pending update)
     double r_n;           // r of the newest state of the pair
@@ -32,9 +34,8 @@ struct DevScalars {
     double q_E1;          // E_1 of the latest query / start-up pass
     double q_norm[4];     // latest ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2
     double mean;          // mean of the newest state
-    double mean_raw;      // Re X(k = 0), written by the pass that forms X
     unsigned int flags;   // sticky SPFC_FLAG_* bits
-    unsigned int ticket;  // arrival counter of the solve pass (0 between launches)
+    unsigned int pad0;
     long long last_record;
     double pad[4];
 };
@@ -48,6 +49,30 @@ enum : unsigned int {
     FLAG_E1_BELOW_OMEGA = 2u,
     FLAG_P1_POSITIVE = 4u,
     FLAG_ENERGY_RISE = 8u,
+};
+
+// Partial sums per workgroup (FP64):
+//   P (forward pass): p1, p2, p_psi                                   3 per workgroup
+//   E (forward pass): ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2,
+//                     ||Delta X||^2, Re X(0) (only the owner adds it)  5 per workgroup
+//   B (real-space pass): E_1 density sum                              1 per workgroup
+//   Q (update / query passes): the same five as E for the pair they form
+constexpr int NPART_P = 3, NPART_E = 5;
+
+// What a launch needs to finish the previous step (the SAV scalar) itself.
+struct FinishIn {
+    const double* partP;
+    const double* partE;
+    int nPE;                 // workgroups of the forward pass that wrote P and E
+    const double* partB;
+    int nB;
+    const DevScalars* sc_in;
+    DevScalars* sc_out;
+    Record* hist;
+    long long hist_cap;
+    long long step;          // index of the state X of the finished step
+    int check_rise;
+    double energy_tol;
 };
 
 // ------------------------------------------------------------------ kernel arguments
@@ -67,11 +92,11 @@ struct SpecInvArgs {
     int G;                  // lines per workgroup
     int update;             // apply the pending update
     double ua0, ua1, ua2, udt;   // weights and dt of the step that produced nhat
-    const double* xi;       // its xi (device)
+    int fin;                // update: 1 = finish that step here (reduce its partials), 0 = read xi
+    FinishIn fi;            // fin = 1: partials and scalar blocks; fin = 0: fi.sc_in->xi
     double e1, e2;          // phihat = e1 X + e2 Y
-    int want_grad;          // 0: only the energy partials (no transform, no output)
-    double* part;           // 4 partials per workgroup
-    double* mean_raw;
+    int want_grad;          // 0: only the pair partials (no transform, no output)
+    double* part;           // no update: NPART_E partials of (X, Y) per workgroup
     Geo geo;
 };
 
@@ -102,17 +127,8 @@ struct SpecFwdArgs {
     int tws;
     int nlines, B, G;
     double a0, a1, a2, dt, e1, e2;
-    double* partC;          // 3 partials per workgroup (this pass)
-    const double* partA;    // 4 per workgroup of the spectral inverse pass
-    int nA;
-    const double* partB;    // 1 per workgroup of the real pass
-    int nB;
-    DevScalars* sc;
-    Record* hist;
-    long long hist_cap;
-    long long step;         // index of the state X
-    int check_rise;
-    double energy_tol;
+    double* partP;          // NPART_P per workgroup
+    double* partE;          // NPART_E per workgroup
     Geo geo;
 };
 
@@ -150,9 +166,9 @@ struct UpdateArgs {
     long long total;         // complex entries of one spectrum
     int NL, B;               // line length (last axis) and b extent
     double ua0, ua1, ua2, udt;
-    const double* xi;
-    double* part;            // 4 partials per workgroup
-    double* mean_raw;
+    int fin;
+    FinishIn fi;
+    double* part;            // NPART_E per workgroup
     Geo geo;
 };
 
@@ -162,14 +178,13 @@ enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RE
 
 struct FinalizeArgs {
     int mode;
-    const double* partA;
-    int nA;
+    const double* partQ;    // NPART_E per workgroup (state / query modes)
+    int nQ;
     const double* partB;
     int nB;
-    const double* partC;    // FIN_STEP: 3 partials per workgroup of the forward pass
-    int nC;
     double a0, a1, a2, dt;  // FIN_STEP: weights and dt of the step
-    DevScalars* sc;
+    FinishIn fi;            // FIN_STEP
+    DevScalars* sc;         // other modes: updated in place
     Record* hist;
     long long hist_cap;
     long long step;

@@ -46,6 +46,7 @@ __device__ inline void block_sum_store(double (&acc)[NV], double* dst) {
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
+    __syncthreads();   // an earlier use of `red` is finished
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) red[i][wave] = acc[i];
@@ -61,19 +62,11 @@ __device__ inline void block_sum_store(double (&acc)[NV], double* dst) {
     }
 }
 
-// Sum the NV-strided partials part[j*NV + i], j < n, over the workgroup: every
-// thread reads a fixed subset (vector loads), then a fixed-order tree.  Result
-// valid in thread 0.
+// Fixed-order tree over the workgroup of NV per-thread values; the result is
+// returned to every thread.
 template <int NV>
-__device__ inline void block_sum_partials(const double* part, int n, double (&out)[NV]) {
+__device__ inline void block_tree(double (&acc)[NV], double (&out)[NV]) {
     __shared__ double red[NV][16];
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += __builtin_nontemporal_load(part + (size_t)j * NV + i);
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -90,6 +83,45 @@ __device__ inline void block_sum_partials(const double* part, int n, double (&ou
         for (int w = 0; w < nw; ++w) s += red[i][w];
         out[i] = s;
     }
+}
+
+// Sum two arrays of per-workgroup partials, a[j*NA + i] (j < na) and
+// b[j*NB + i] (j < nb), over the workgroup.  Each thread reads a fixed subset,
+// U indices per sweep with every load issued before any is added; the order of
+// the sums depends only on the workgroup size, so every workgroup of a launch gets
+// the same bits.  Result (NA sums of a, then NB sums of b) in every thread.
+template <int NA, int NB>
+__device__ inline void block_sum_pair(const double* a, int na, const double* b, int nb,
+                                      double (&out)[NA + NB]) {
+    constexpr int U = 4;
+    double acc[NA + NB];
+#pragma unroll
+    for (int i = 0; i < NA + NB; ++i) acc[i] = 0.0;
+    const int n = na > nb ? na : nb;
+    for (int j0 = threadIdx.x; j0 < n; j0 += U * blockDim.x) {
+        double v[U][NA + NB];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int jj = j0 + q * blockDim.x;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) v[q][i] = jj < na ? a[(size_t)jj * NA + i] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) v[q][NA + i] = jj < nb ? b[(size_t)jj * NB + i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int i = 0; i < NA + NB; ++i) acc[i] += v[q][i];
+    }
+    block_tree<NA + NB>(acc, out);
+}
+
+template <int NV>
+__device__ inline void block_sum_partials(const double* part, int n, double (&out)[NV]) {
+    double o[NV + 1];
+    block_sum_pair<NV, 1>(part, n, part, 0, o);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = o[i];
 }
 
 // ------------------------------------------------------------------ index helpers
@@ -121,6 +153,111 @@ __device__ inline void spec_symbols(const Geo& g, int kx, int ky, int kz, double
     }
 }
 
+// Energy partials of the pair (X, Y) at one mode: ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2,
+// ||X||^2, ||Delta X||^2 with the Hermitian weight (modified energy, eq. discrete
+// energy; E_N, eq. energy-discrete-spectral), and Re X(0) for the mean.
+template <typename T>
+__device__ inline void pair_partials(cpx<T> X, cpx<T> Y, int kx, double k2, bool zero_mode, const Geo& geo,
+                                     double (&acc)[NPART_E]) {
+    const double w = hweight(kx, geo.nx);
+    const double Lk = geo.a + k2 * k2;
+    const double xx = (double)X.x * X.x + (double)X.y * X.y;
+    const double zx = 2.0 * X.x - Y.x, zy = 2.0 * X.y - Y.y;
+    acc[0] += w * Lk * xx;
+    acc[1] += w * Lk * (zx * zx + zy * zy);
+    acc[2] += w * xx;
+    acc[3] += w * k2 * k2 * xx;
+    if (zero_mode) acc[4] += (double)X.x;
+}
+
+// xi = r^{n+1} / sqrt(E_1) from the reduced sums (kept out of line so that every
+// caller evaluates it with the same instructions and gets the same bits).
+// Section 2.3 in this form: with phi^{n+1} = dt xi b1 + b2, b1 = A^-1 Delta N,
+// b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
+//   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
+// p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1),
+// rho = a1 r^n + a2 r^{n-1}.
+__device__ __noinline__ double sav_xi(double E1sum, double sP0, double sP1, double sP2, double rn, double rnm1,
+                                      double a0, double a1, double a2, double dt, double cell, double e1_const,
+                                      double pscale) {
+    const double E1 = cell * E1sum + e1_const;
+    const double p1 = pscale * sP0, p2 = pscale * sP1, pp = pscale * sP2;
+    const double S = sqrt(E1);
+    const double rho = a1 * rn + a2 * rnm1;
+    return (rho + (a0 * p2 - pp) / (2.0 * S)) / (a0 * (S - dt * p1 / (2.0 * S)));
+}
+
+// Close one step (one lane): copy the scalar block, then record the state X of the
+// step (modified energy, mean, r) and the next state's xi, E_1, p1, S, and shift
+// the r pair.  Reads fi.sc_in, writes fi.sc_out.
+__device__ inline void finish_step(const FinishIn& fi, double E1sum, const double (&sE)[NPART_E],
+                                   const double (&sP)[NPART_P], double a0, double a1, double a2, double dt,
+                                   const Geo& geo) {
+    DevScalars s = *fi.sc_in;
+    const double rn = s.r_n, rnm1 = s.r_nm1;
+    const double E1 = geo.cell * E1sum + geo.e1_const;
+    const double n0 = geo.pscale * sE[0], n1 = geo.pscale * sE[1];
+    const double p1 = geo.pscale * sP[0], p2 = geo.pscale * sP[1], pp = geo.pscale * sP[2];
+    const double S = sqrt(E1);
+    const double xi = sav_xi(E1sum, sP[0], sP[1], sP[2], rn, rnm1, a0, a1, a2, dt, geo.cell, geo.e1_const,
+                             geo.pscale);
+    const double rnew = xi * S;
+    const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
+    const double mean = sE[4] * geo.inv_npts;
+    unsigned int fl = s.flags;
+    if (!isfinite(E1) || !isfinite(p1) || !isfinite(p2) || !isfinite(pp) || !isfinite(xi) || !isfinite(energy))
+        fl |= FLAG_NONFINITE;
+    if (E1 < geo.volume * (1.0 - 1e-12)) fl |= FLAG_E1_BELOW_OMEGA;
+    if (p1 > 0.0) fl |= FLAG_P1_POSITIVE;
+    if (fi.check_rise && energy > s.energy_prev * (1.0 + fi.energy_tol)) fl |= FLAG_ENERGY_RISE;
+    Record* rc = fi.hist + (fi.step % fi.hist_cap);
+    rc->energy = energy;
+    rc->mean = mean;
+    rc->r = rn;
+    Record* rn1 = fi.hist + ((fi.step + 1) % fi.hist_cap);
+    rn1->energy = 0.0;
+    rn1->mean = 0.0;
+    rn1->r = rnew;
+    rn1->xi = xi;
+    rn1->E1 = E1;
+    rn1->p1 = p1;
+    rn1->S = S;
+    rn1->reserved = 0.0;
+    s.xi = xi;
+    s.r_nm1 = rn;
+    s.r_n = rnew;
+    s.energy_prev = energy;
+    s.E1 = E1;
+    s.p1 = p1;
+    s.p2 = p2;
+    s.ppsi = pp;
+    s.S = S;
+    s.mean = mean;
+    s.flags = fl;
+    s.last_record = fi.step;
+    *fi.sc_out = s;
+}
+
+// Every workgroup of a launch reduces the previous step's partial sums in the
+// same order and gets the same xi; workgroup 0 also closes the step (records,
+// new scalar block).  All threads of the workgroup must call it.
+__device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double a1, double a2, double dt,
+                                          const Geo& geo) {
+    double sBP[1 + NPART_P];
+    block_sum_pair<1, NPART_P>(fi.partB, fi.nB, fi.partP, fi.nPE, sBP);
+    const double xi = sav_xi(sBP[0], sBP[1], sBP[2], sBP[3], fi.sc_in->r_n, fi.sc_in->r_nm1, a0, a1, a2, dt,
+                             geo.cell, geo.e1_const, geo.pscale);
+    if (blockIdx.x == 0) {
+        double sE[NPART_E];
+        block_sum_partials<NPART_E>(fi.partE, fi.nPE, sE);
+        if (threadIdx.x == 0) {
+            const double sP[NPART_P] = {sBP[1], sBP[2], sBP[3]};
+            finish_step(fi, sBP[0], sE, sP, a0, a1, a2, dt, geo);
+        }
+    }
+    return xi;
+}
+
 // ------------------------------------------------------------------ spectral inverse pass
 
 // One group of P threads per spectral line.  Optional pending update
@@ -141,7 +278,6 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     const bool act = line < p.nlines;
     const Geo& geo = p.geo;
     const size_t lbase = (size_t)(act ? line : 0) * NL;
-    const double xi = p.update ? p.xi[0] : 0.0;
 
     // all loads first (the update writes in place over `prev`, so later loads
     // must not wait behind earlier stores)
@@ -153,7 +289,10 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
         prv[m] = act ? p.prev[i] : mk<T>(0, 0);
         nh[m] = (act && p.update) ? p.nhat[i] : mk<T>(0, 0);
     }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double xi = 0.0;
+    if (p.update) xi = p.fin ? finish_in_kernel(p.fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : p.fi.sc_in->xi;
+
+    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
     cpx<T> v[C][E];
     const T h1 = T(p.e1), h2 = T(p.e2);
 #pragma unroll
@@ -171,16 +310,9 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
                 X = mk<T>(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x, f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y);
                 Y = cur[m];
                 p.out_new[lbase + e] = X;
+            } else {
+                pair_partials<T>(X, Y, kx, k2, line == 0 && e == 0, geo, acc);
             }
-            const double w = hweight(kx, geo.nx);
-            const double Lk = geo.a + k2 * k2;
-            const double xx = (double)X.x * X.x + (double)X.y * X.y;
-            const double zx = 2.0 * X.x - Y.x, zy = 2.0 * X.y - Y.y;
-            acc[0] += w * Lk * xx;
-            acc[1] += w * Lk * (zx * zx + zy * zy);
-            acc[2] += w * xx;
-            acc[3] += w * k2 * k2 * xx;
-            if (line == 0 && e == 0) p.mean_raw[0] = (double)X.x;
         }
         const cpx<T> ph = mk<T>(h1 * X.x + h2 * Y.x, h1 * X.y + h2 * Y.y);
 #pragma unroll
@@ -189,6 +321,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             v[j][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1_j phihat
         }
     }
+    if (!p.update) block_sum_store<NPART_E>(acc, p.part + NPART_E * blockIdx.x);
     if (p.want_grad) {
         stage_twiddles<T, PL>(ltw, p.tw, p.tws);
         fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
@@ -201,7 +334,6 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             }
         }
     }
-    block_sum_store<4>(acc, p.part + 4 * blockIdx.x);
 }
 
 // ------------------------------------------------------------------ real-space pass
@@ -368,53 +500,6 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
 // b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
 //   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
 // p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1).
-__device__ inline void finish_step(double E1sum, const double (&nA)[4], const double (&sC)[3], DevScalars* sc,
-                                   Record* hist, long long cap, long long step, double a0, double a1, double a2,
-                                   double dt, int check_rise, double tol, const Geo& geo) {
-    // every read of the scalar block first, then the arithmetic, then the stores
-    const double rn = sc->r_n, rnm1 = sc->r_nm1, eprev = sc->energy_prev, mraw = sc->mean_raw;
-    unsigned int fl = sc->flags;
-    const double E1 = geo.cell * E1sum + geo.e1_const;
-    const double n0 = geo.pscale * nA[0], n1 = geo.pscale * nA[1];
-    const double p1 = geo.pscale * sC[0], p2 = geo.pscale * sC[1], pp = geo.pscale * sC[2];
-    const double S = sqrt(E1);
-    const double rho = a1 * rn + a2 * rnm1;
-    const double xi = (rho + (a0 * p2 - pp) / (2.0 * S)) / (a0 * (S - dt * p1 / (2.0 * S)));
-    const double rnew = xi * S;
-    const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
-    const double mean = mraw * geo.inv_npts;
-    if (!isfinite(E1) || !isfinite(p1) || !isfinite(p2) || !isfinite(pp) || !isfinite(xi) || !isfinite(energy))
-        fl |= FLAG_NONFINITE;
-    if (E1 < geo.volume * (1.0 - 1e-12)) fl |= FLAG_E1_BELOW_OMEGA;
-    if (p1 > 0.0) fl |= FLAG_P1_POSITIVE;
-    if (check_rise && energy > eprev * (1.0 + tol)) fl |= FLAG_ENERGY_RISE;
-    Record* rc = hist + (step % cap);
-    rc->energy = energy;
-    rc->mean = mean;
-    rc->r = rn;
-    Record* rn1 = hist + ((step + 1) % cap);
-    rn1->energy = 0.0;
-    rn1->mean = 0.0;
-    rn1->r = rnew;
-    rn1->xi = xi;
-    rn1->E1 = E1;
-    rn1->p1 = p1;
-    rn1->S = S;
-    rn1->reserved = 0.0;
-    sc->xi = xi;
-    sc->r_nm1 = rn;
-    sc->r_n = rnew;
-    sc->energy_prev = energy;
-    sc->E1 = E1;
-    sc->p1 = p1;
-    sc->p2 = p2;
-    sc->ppsi = pp;
-    sc->S = S;
-    sc->mean = mean;
-    sc->flags = fl;
-    sc->last_record = step;
-}
-
 template <typename T, int NL, int EE, int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     using PL = Plan<NL, EE>;
@@ -442,7 +527,8 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
         Xs[m] = act ? p.X[lbase + t + P * m] : mk<T>(0, 0);
         Ys[m] = act ? p.Y[lbase + t + P * m] : mk<T>(0, 0);
     }
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[NPART_P] = {0.0, 0.0, 0.0};
+    double accE[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -470,6 +556,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
                 acc[0] -= w * k2 * (Nx * Nx + Ny * Ny) * iA;
                 acc[1] += w * re * iA;
                 acc[2] += w * re;
+                pair_partials<T>(X, Y, kx, k2, line == 0 && e == 0, geo, accE);
                 p.nhat[lbase + e] = mk<T>(T(Nx), T(Ny));
             } else {
                 // phi^{-1} = phi^0 - dt Delta_N (N + L_N phi^0)  (eq. scheme-SAV-initial-1)
@@ -478,7 +565,10 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             }
         }
     }
-    if constexpr (MODE == FWD_SOLVE) block_sum_store<3>(acc, p.partC + 3 * blockIdx.x);
+    if constexpr (MODE == FWD_SOLVE) {
+        block_sum_store<NPART_P>(acc, p.partP + NPART_P * blockIdx.x);
+        block_sum_store<NPART_E>(accE, p.partE + NPART_E * blockIdx.x);
+    }
 }
 
 // ------------------------------------------------------------------ elementwise pending update
@@ -486,8 +576,8 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
     const Geo& geo = p.geo;
-    const double xi = p.xi[0];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double xi = p.fin ? finish_in_kernel(p.fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : p.fi.sc_in->xi;
+    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < p.total;
          i += (long long)gridDim.x * blockDim.x) {
         const int line = (int)(i / p.NL), e = (int)(i - (long long)line * p.NL);
@@ -500,17 +590,9 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         const T f1 = T(-p.udt * xi * k2 * iA), f2 = T(p.ua1 * iA), f3 = T(p.ua2 * iA);
         const cpx<T> X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
         p.out_new[i] = X;
-        const double w = hweight(kx, geo.nx);
-        const double Lk = geo.a + k2 * k2;
-        const double xx = (double)X.x * X.x + (double)X.y * X.y;
-        const double zx = 2.0 * X.x - cur.x, zy = 2.0 * X.y - cur.y;
-        acc[0] += w * Lk * xx;
-        acc[1] += w * Lk * (zx * zx + zy * zy);
-        acc[2] += w * xx;
-        acc[3] += w * k2 * k2 * xx;
-        if (i == 0) p.mean_raw[0] = (double)X.x;
+        pair_partials<T>(X, cur, kx, k2, i == 0, geo, acc);
     }
-    block_sum_store<4>(acc, p.part + 4 * blockIdx.x);
+    block_sum_store<NPART_E>(acc, p.part + NPART_E * blockIdx.x);
 }
 
 // ------------------------------------------------------------------ rows: real <-> half spectrum

@@ -36,9 +36,10 @@ struct Shapes {
 
 struct Layout {
     size_t F;  // bytes of one half-spectrum field
-    size_t off_slot[2], off_nhat, off_bufA, off_bufB, off_tw, off_partA, off_partB, off_partC, off_sc, off_hist;
+    size_t off_slot[2], off_nhat, off_bufA, off_bufB, off_tw, off_partP, off_partE, off_partB, off_partQ, off_sc,
+        off_hist;
     size_t total;
-    int nA, nB, nC;
+    int nPE, nB, nQ;
     int ntab;
 };
 
@@ -60,6 +61,7 @@ struct RolePlan {
 };
 struct TunePlan {
     RolePlan inv, real, fwd, mid, misc;
+    int fin_in_kernel = 1;   // allow closing each step inside the next update kernel
 };
 
 void parse_role(const char* spec, const char* key, RolePlan& r) {
@@ -81,6 +83,7 @@ TunePlan tune_plan() {
         parse_role(env, "real", tp.real);
         parse_role(env, "fwd", tp.fwd);
         parse_role(env, "mid", tp.mid);
+        if (std::strstr(env, "finsep")) tp.fin_in_kernel = 0;
     }
     return tp;
 }
@@ -122,13 +125,14 @@ Layout layout_of(const Sizes& s, const Shapes& h, int64_t hist_cap) {
     L.off_bufB = o; o += 3 * Fa;
     L.ntab = std::max(s.nx, std::max(s.ny, s.nz));
     L.off_tw = o; o += align_up((size_t)L.ntab * s.elem);
-    L.nA = std::max(h.A.grid, h.updGrid);
+    L.nPE = h.Cf.grid;
     L.nB = h.B.grid;
-    L.nC = h.Cf.grid;
-    L.off_partA = o; o += align_up((size_t)L.nA * 4 * sizeof(double));
+    L.nQ = std::max(h.A.grid, h.updGrid);
+    L.off_partP = o; o += align_up((size_t)L.nPE * NPART_P * sizeof(double));
+    L.off_partE = o; o += align_up((size_t)L.nPE * NPART_E * sizeof(double));
     L.off_partB = o; o += align_up((size_t)L.nB * sizeof(double));
-    L.off_partC = o; o += align_up((size_t)L.nC * 3 * sizeof(double));
-    L.off_sc = o; o += align_up(sizeof(DevScalars));
+    L.off_partQ = o; o += align_up((size_t)L.nQ * NPART_E * sizeof(double));
+    L.off_sc = o; o += 2 * align_up(sizeof(DevScalars));
     L.off_hist = o; o += align_up((size_t)hist_cap * sizeof(Record));
     L.total = o;
     return L;
@@ -178,6 +182,8 @@ struct spfc_ctx {
     bool started;
     bool broken;
     double energy_tol;
+    int cur_sc;            // which of the two scalar blocks holds the latest values
+    bool fin_in;           // close each step inside the next update kernel
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
@@ -189,10 +195,12 @@ struct spfc_ctx {
     char* bufA(int j) const { return ws + lay.off_bufA + j * align_up(lay.F); }
     char* bufB(int j) const { return ws + lay.off_bufB + j * align_up(lay.F); }
     char* tw() const { return ws + lay.off_tw; }
-    double* partA() const { return reinterpret_cast<double*>(ws + lay.off_partA); }
+    double* partP() const { return reinterpret_cast<double*>(ws + lay.off_partP); }
+    double* partE() const { return reinterpret_cast<double*>(ws + lay.off_partE); }
     double* partB() const { return reinterpret_cast<double*>(ws + lay.off_partB); }
-    double* partC() const { return reinterpret_cast<double*>(ws + lay.off_partC); }
-    DevScalars* sc() const { return reinterpret_cast<DevScalars*>(ws + lay.off_sc); }
+    double* partQ() const { return reinterpret_cast<double*>(ws + lay.off_partQ); }
+    DevScalars* scb(int i) const { return reinterpret_cast<DevScalars*>(ws + lay.off_sc + i * align_up(sizeof(DevScalars))); }
+    DevScalars* sc() const { return scb(cur_sc); }
     Record* hist() const { return reinterpret_cast<Record*>(ws + lay.off_hist); }
     int nl() const { return sz.dim == 2 ? sz.ny : sz.nz; }
     int nlines() const { return sz.dim == 2 ? sz.nxh : sz.nxh * sz.ny; }
@@ -264,9 +272,37 @@ struct Pipe {
     using C = cpx<T>;
     spfc_ctx* ctx;
 
-    // spectral state (cur, prev) -> gradient transforms along the last axis -> bufA
-    int spec_inv(const char* cur, const char* prev, char* out_new, bool update, double ua0, double ua1, double ua2,
-                 double udt, double e1, double e2, bool want_grad, bool timed) {
+    // What an update kernel needs to close the step whose N is pending.
+    FinishIn finish_in(long long step, int check_rise) {
+        FinishIn f{};
+        f.partP = ctx->partP();
+        f.partE = ctx->partE();
+        f.nPE = ctx->sh.Cf.grid;
+        f.partB = ctx->partB();
+        f.nB = ctx->sh.B.grid;
+        f.sc_in = ctx->scb(ctx->cur_sc);
+        f.sc_out = ctx->scb(1 - ctx->cur_sc);
+        f.hist = ctx->hist();
+        f.hist_cap = ctx->prm.history;
+        f.step = step;
+        f.check_rise = check_rise;
+        f.energy_tol = ctx->energy_tol;
+        return f;
+    }
+
+    // Pending step (weights, dt, index, rise check) whose scalar is still to be solved.
+    struct Pending {
+        bool open = false;
+        double a0 = 0, a1 = 0, a2 = 0, dt = 0;
+        long long step = 0;
+        int check = 0;
+    };
+
+    // spectral state (cur, prev) -> gradient transforms along the last axis -> bufA.
+    // With `pend.open` the kernel first applies the pending update (closing that
+    // step itself when ctx->fin_in).
+    int spec_inv(const char* cur, const char* prev, char* out_new, const Pending& pend, double e1, double e2,
+                 bool want_grad, bool timed) {
         SpecInvArgs<T> a{};
         a.cur = (const C*)cur;
         a.prev = (const C*)prev;
@@ -278,20 +314,23 @@ struct Pipe {
         a.nlines = ctx->nlines();
         a.B = ctx->lineB();
         a.G = ctx->sh.A.G;
-        a.update = update ? 1 : 0;
-        a.ua0 = ua0;
-        a.ua1 = ua1;
-        a.ua2 = ua2;
-        a.udt = udt;
-        a.xi = &ctx->sc()->xi;
+        a.update = pend.open ? 1 : 0;
+        a.ua0 = pend.a0;
+        a.ua1 = pend.a1;
+        a.ua2 = pend.a2;
+        a.udt = pend.dt;
+        a.fin = (pend.open && ctx->fin_in) ? 1 : 0;
+        a.fi = finish_in(pend.step, pend.check);
         a.e1 = e1;
         a.e2 = e2;
         a.want_grad = want_grad ? 1 : 0;
-        a.part = ctx->partA();
-        a.mean_raw = &ctx->sc()->mean_raw;
+        a.part = ctx->partQ();
         a.geo = ctx->geo;
-        Timed tm(ctx, R_SPEC_INV, timed);
-        CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, a, ctx->sh.A, ctx->stream));
+        {
+            Timed tm(ctx, R_SPEC_INV, timed);
+            CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, a, ctx->sh.A, ctx->stream));
+        }
+        if (a.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
     }
 
@@ -332,7 +371,7 @@ struct Pipe {
     }
 
     int spec_fwd(char* const* in, const char* X, const char* Y, int mode, char* ghost_out, double a0, double a1,
-                 double a2, double dt, double e1, double e2, int check_rise, bool timed) {
+                 double a2, double dt, double e1, double e2, bool timed) {
         SpecFwdArgs<T> a{};
         for (int j = 0; j < 3; ++j) a.in[j] = (const C*)in[j];
         a.X = (const C*)X;
@@ -350,37 +389,29 @@ struct Pipe {
         a.dt = dt;
         a.e1 = e1;
         a.e2 = e2;
-        a.partC = ctx->partC();
-        a.partA = ctx->partA();
-        a.nA = ctx->sh.A.grid;
-        a.partB = ctx->partB();
-        a.nB = ctx->sh.B.grid;
-        a.sc = ctx->sc();
-        a.hist = ctx->hist();
-        a.hist_cap = ctx->prm.history;
-        a.step = ctx->step;
-        a.check_rise = check_rise;
-        a.energy_tol = ctx->energy_tol;
+        a.partP = ctx->partP();
+        a.partE = ctx->partE();
         a.geo = ctx->geo;
         Timed tm(ctx, R_SPEC_FWD, timed);
         CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, a, ctx->sh.Cf, ctx->stream));
         return SPFC_OK;
     }
 
-    int finalize(int mode, int nA, int check_rise, double a0 = 0, double a1 = 0, double a2 = 0, double dt = 0,
-                 bool timed = false) {
+    // one-workgroup close of a step (FIN_STEP) or of a state / query pass
+    int finalize(int mode, int nQ, int check_rise, const Pending* pend = nullptr, bool timed = false) {
         FinalizeArgs f{};
         f.mode = mode;
-        f.partA = ctx->partA();
-        f.nA = nA;
+        f.partQ = ctx->partQ();
+        f.nQ = nQ;
         f.partB = ctx->partB();
         f.nB = ctx->sh.B.grid;
-        f.partC = ctx->partC();
-        f.nC = ctx->sh.Cf.grid;
-        f.a0 = a0;
-        f.a1 = a1;
-        f.a2 = a2;
-        f.dt = dt;
+        if (pend) {
+            f.a0 = pend->a0;
+            f.a1 = pend->a1;
+            f.a2 = pend->a2;
+            f.dt = pend->dt;
+            f.fi = finish_in(pend->step, pend->check);
+        }
         f.sc = ctx->sc();
         f.hist = ctx->hist();
         f.hist_cap = ctx->prm.history;
@@ -388,18 +419,18 @@ struct Pipe {
         f.check_rise = check_rise;
         f.energy_tol = ctx->energy_tol;
         f.geo = ctx->geo;
-        Timed tm(ctx, R_FINAL, timed);
-        CK(launch_finalize(f, ctx->stream));
+        {
+            Timed tm(ctx, R_FINAL, timed);
+            CK(launch_finalize(f, ctx->stream));
+        }
+        if (mode == FIN_STEP) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
     }
 
-    char* const* A3() { static thread_local char* p[3]; for (int j = 0; j < 3; ++j) p[j] = ctx->bufA(j); return p; }
-    char* const* B3() { static thread_local char* p[3]; for (int j = 0; j < 3; ++j) p[j] = ctx->bufB(j); return p; }
-
-    // E_1 of the state `field` (and the norms of (field, prev)) -> finalize(mode)
+    // E_1 of the state `field` (and the energy norms of (field, prev)) -> finalize(mode)
     int e1_pass(const char* field, const char* prev, int fin_mode) {
         int rc;
-        if ((rc = spec_inv(field, prev, nullptr, false, 0, 0, 0, 0, 1.0, 0.0, true, false))) return rc;
+        if ((rc = spec_inv(field, prev, nullptr, Pending{}, 1.0, 0.0, true, false))) return rc;
         char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
         char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
         if (ctx->sz.dim == 3) {
@@ -417,7 +448,7 @@ struct Pipe {
         int rc;
         const int o = 1 - ctx->slotX;
         char* X = ctx->slot(ctx->slotX);
-        if ((rc = spec_inv(X, X, nullptr, false, 0, 0, 0, 0, 1.0, 0.0, true, false))) return rc;
+        if ((rc = spec_inv(X, X, nullptr, Pending{}, 1.0, 0.0, true, false))) return rc;
         char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
         char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
         char** flux = bB;
@@ -430,7 +461,7 @@ struct Pipe {
         } else {
             if ((rc = real_pass(bA, bB, true, false))) return rc;
         }
-        if ((rc = spec_fwd(flux, X, X, FWD_GHOST, ctx->slot(o), 1.0, 0.0, 0.0, dt, 1.0, 0.0, 0, false))) return rc;
+        if ((rc = spec_fwd(flux, X, X, FWD_GHOST, ctx->slot(o), 1.0, 0.0, 0.0, dt, 1.0, 0.0, false))) return rc;
         if ((rc = finalize(FIN_GHOST_R0, ctx->sh.A.grid, 0))) return rc;
         if ((rc = e1_pass(ctx->slot(o), ctx->slot(o), FIN_GHOST_RM1))) return rc;
         ctx->slotY = o;
@@ -454,19 +485,18 @@ struct Pipe {
         char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
         char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
         const int d = ctx->sz.dim;
-        double pa0 = 0, pa1 = 0, pa2 = 0;
+        Pending pend;
         for (int64_t i = 0; i < n; ++i) {
             const bool sav1 = first_order && i == 0;
             const double a0 = sav1 ? 1.0 : 1.5, a1 = sav1 ? 1.0 : 2.0, a2 = sav1 ? 0.0 : -0.5;
             const double e1 = sav1 ? 1.0 : 2.0, e2 = sav1 ? 0.0 : -1.0;
-            if (i == 0) {
-                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, false, 0, 0, 0, 0, e1, e2,
-                                   true, true)))
+            if (!pend.open) {
+                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, pend, e1, e2, true, true)))
                     return rc;
             } else {
                 const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
-                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), ctx->slot(target), true, pa0, pa1,
-                                   pa2, dt, e1, e2, true, true)))
+                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), ctx->slot(target), pend, e1, e2,
+                                   true, true)))
                     return rc;
                 ctx->slotY = ctx->slotX;
                 ctx->slotX = target;
@@ -482,15 +512,20 @@ struct Pipe {
             } else {
                 if ((rc = real_pass(bA, bB, true, true))) return rc;
             }
-            const int check = (i == 0 && restart) ? 0 : 1;
             if ((rc = spec_fwd(flux, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt,
-                               e1, e2, check, true)))
+                               e1, e2, true)))
                 return rc;
-            // the SAV scalar: xi, r^{n+1}, the record of phi^n
-            if ((rc = finalize(FIN_STEP, ctx->sh.A.grid, check, a0, a1, a2, dt, true))) return rc;
-            pa0 = a0;
-            pa1 = a1;
-            pa2 = a2;
+            pend.open = true;
+            pend.a0 = a0;
+            pend.a1 = a1;
+            pend.a2 = a2;
+            pend.dt = dt;
+            pend.step = ctx->step;
+            pend.check = (i == 0 && restart) ? 0 : 1;
+            if (!ctx->fin_in) {
+                // the SAV scalar: xi, r^{n+1}, the record of phi^n
+                if ((rc = finalize(FIN_STEP, 0, 0, &pend, true))) return rc;
+            }
         }
         // apply the last update and record the state it reaches
         const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
@@ -502,15 +537,16 @@ struct Pipe {
         u.total = (long long)ctx->sz.nxh * ctx->sz.ny * ctx->sz.nz;
         u.NL = ctx->nl();
         u.B = ctx->lineB();
-        u.ua0 = pa0;
-        u.ua1 = pa1;
-        u.ua2 = pa2;
-        u.udt = dt;
-        u.xi = &ctx->sc()->xi;
-        u.part = ctx->partA();
-        u.mean_raw = &ctx->sc()->mean_raw;
+        u.ua0 = pend.a0;
+        u.ua1 = pend.a1;
+        u.ua2 = pend.a2;
+        u.udt = pend.dt;
+        u.fin = ctx->fin_in ? 1 : 0;
+        u.fi = finish_in(pend.step, pend.check);
+        u.part = ctx->partQ();
         u.geo = ctx->geo;
         CK(Kern<T>::update(d, u, ctx->sh.updGrid, 256, ctx->stream));
+        if (u.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         ctx->slotY = ctx->slotX;
         ctx->slotX = target;
         ctx->step += 1;
@@ -705,6 +741,13 @@ int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* ph
     ctx->broken = false;
     ctx->energy_tol = params->energy_tol > 0 ? params->energy_tol : (params->precision == SPFC_FP32 ? 1e-6 : 1e-12);
     ctx->profiling = false;
+    ctx->cur_sc = 0;
+    {
+        // closing each step inside the next update kernel makes every workgroup of
+        // that kernel read all partial sums: worth it while that re-read stays small
+        const double reread = (double)std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
+        ctx->fin_in = tune_plan().fin_in_kernel != 0 && reread <= 48.0e6;
+    }
     for (int i = 0; i < R_COUNT; ++i) {
         ctx->role_ms[i] = 0;
         ctx->role_n[i] = 0;
@@ -871,7 +914,7 @@ int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes) {
     if (!hd.slot_same)
         CK(hipMemcpyAsync(ctx->slot(1), in + off + align_up(ctx->lay.F), ctx->lay.F, hipMemcpyDeviceToDevice,
                           ctx->stream));
-    hd.sc.ticket = 0;
+    ctx->cur_sc = 0;
     CK(hipMemcpyAsync(ctx->sc(), &hd.sc, sizeof(DevScalars), hipMemcpyHostToDevice, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->slotX = 0;
