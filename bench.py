@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes 5 times (counter calibration)")

@@ -305,9 +305,12 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             spec_index<DIM>(line, p.B, e, kx, ky, kz);
             spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
             if (p.update) {
+                // in FP64 for both storage precisions: the k = 0 mode then keeps the mean
+                // (Theorem 2.1) to the rounding of one store per step
                 const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
-                const T f1 = T(-p.udt * xi * k2 * iA), f2 = T(p.ua1 * iA), f3 = T(p.ua2 * iA);
-                X = mk<T>(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x, f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y);
+                const double f1 = -p.udt * xi * k2 * iA, f2 = p.ua1 * iA, f3 = p.ua2 * iA;
+                X = mk<T>(T(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x),
+                          T(f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y));
                 Y = cur[m];
                 p.out_new[lbase + e] = X;
             } else {
@@ -587,8 +590,8 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
         const cpx<T> cur = p.cur[i], prv = p.prev[i], nh = p.nhat[i];
         const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
-        const T f1 = T(-p.udt * xi * k2 * iA), f2 = T(p.ua1 * iA), f3 = T(p.ua2 * iA);
-        const cpx<T> X = mk<T>(f1 * nh.x + f2 * cur.x + f3 * prv.x, f1 * nh.y + f2 * cur.y + f3 * prv.y);
+        const double f1 = -p.udt * xi * k2 * iA, f2 = p.ua1 * iA, f3 = p.ua2 * iA;
+        const cpx<T> X = mk<T>(T(f1 * nh.x + f2 * cur.x + f3 * prv.x), T(f1 * nh.y + f2 * cur.y + f3 * prv.y));
         p.out_new[i] = X;
         pair_partials<T>(X, cur, kx, k2, i == 0, geo, acc);
     }
