@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", type=int, default=0, help="1: replay the steady steps from a captured HIP graph")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -117,7 +118,8 @@ def main():
     n, L, eps, mean, seed, dt, prec = WORKLOADS[args.workload]
     shape = tuple(reversed(n))
     phi0 = noise_ic(shape, mean, seed)
-    s = Solver(n, L, phi0, eps, precision=prec, history=max(16, args.steps + args.warmup + args.profile_steps + 2))
+    s = Solver(n, L, phi0, eps, precision=prec, history=max(16, args.steps + args.warmup + args.profile_steps + 2),
+               graph=bool(args.graph))
     stream = s.stream
     npts = int(np.prod(n))
 
@@ -159,7 +161,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(n), "L": [round(v, 6) for v in L], "epsilon": eps,
-                   "dt": dt, "mean": mean, "seed": seed, "startup": "sav1"},
+                   "dt": dt, "mean": mean, "seed": seed, "startup": "sav1",
+                   "launch": "graph" if args.graph else "direct"},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "kernels": per_kernel,

@@ -61,6 +61,7 @@ enum {
 enum { SPFC_FP64 = 0, SPFC_FP32 = 1 };
 
 typedef struct spfc_ctx spfc_ctx;
+typedef struct spfc_batch spfc_batch;
 
 /* Grid (Section 2.1).  dim = 2 or 3; n[j] points along axis j (x, y, z), each a
  * power of two in [8, 1024]; L[j] > 0 the box side.  Unused entries ignored. */
@@ -171,6 +172,54 @@ int spfc_status(spfc_ctx* ctx, uint32_t* flags);
 int spfc_profile(spfc_ctx* ctx, int enable);
 int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms,
                       int64_t* launches, double* bytes_per_launch, int* count);
+
+/* Graph replay (enable = 1): spfc_step then captures two steady BDF2 steps (the
+ * launches of eq. scheme-SAV-1 with the weights 3/2, 2, -1/2 at one dt) into a HIP
+ * graph on first use and replays it for each further pair of steps, which removes
+ * the per-launch host cost.  Results are bit for bit those of direct launches.
+ * Needs a non-null stream (on the null stream steps run directly); steps run
+ * directly while profiling.  The graph is re-captured when dt changes.  Capture
+ * uses hipStreamCaptureModeThreadLocal on the context stream, so nothing else may
+ * be enqueued on that stream from another thread during spfc_step.  0 disables it
+ * (default) and frees the graph. */
+int spfc_set_graph(spfc_ctx* ctx, int enable);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances `count` independent runs ("members") together, e.g. a sweep
+ * over epsilon, mean density or box size of Section 5.  Members of the same grid
+ * sizes and precision form one class that shares every kernel launch (member m is
+ * grid dimension y of each launch), so many small grids fill the GPU as one large
+ * one would.  Members may differ in L and epsilon / c4; startup, history and
+ * energy_tol must be equal for all members (else SPFC_E_INVAL).  Every member
+ * follows exactly the arithmetic of a single run with its own grid and
+ * parameters (same kernels, same reduction order), so its results equal those of
+ * spfc_init + spfc_step on that member alone, bit for bit.
+ * grids, params: `count` entries each (host).  phi0_dev: `count` device pointers
+ * to the initial fields (N_total doubles of that member, x fastest), read during
+ * the call only.  Workspace and stream as for spfc_init (one workspace for the
+ * whole batch, from spfc_batch_workspace_bytes).  Member indices below are
+ * positions in the arrays given to spfc_batch_init. */
+int spfc_batch_workspace_bytes(int count, const spfc_grid* grids, const spfc_params* params,
+                               size_t* bytes);
+int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params,
+                    const double* const* phi0_dev, void* workspace_dev, size_t workspace_bytes,
+                    void* hip_stream, spfc_batch** out);
+/* Advance every member n steps of size dt (as spfc_step; asynchronous). */
+int spfc_batch_step(spfc_batch* b, double dt, int64_t n);
+/* Graph replay for every class (as spfc_set_graph). */
+int spfc_batch_set_graph(spfc_batch* b, int enable);
+int spfc_batch_step_count(spfc_batch* b, int64_t* n);
+/* Per-member queries, as their single-run counterparts; SPFC_E_INVAL for a member
+ * index out of range.  spfc_batch_energy runs the query pass of the member's
+ * whole class. */
+int spfc_batch_status(spfc_batch* b, int member, uint32_t* flags);
+int spfc_batch_mass(spfc_batch* b, int member, double* mean);
+int spfc_batch_energy(spfc_batch* b, int member, spfc_energy_t* out);
+int spfc_batch_history(spfc_batch* b, int member, int64_t first, int64_t count,
+                       spfc_record* out);
+int spfc_batch_get_phi(spfc_batch* b, int member, void* out_dev, int dtype);
+/* Free the host side of the batch.  Does not touch caller memory. */
+int spfc_batch_destroy(spfc_batch* b);
 
 /* Static description of a status code. */
 const char* spfc_strerror(int status);

@@ -6,8 +6,11 @@ wraps it.  `inputs` draws the seeded synthetic initial data.
 """
 
 from .binding import (  # noqa: F401
-    Solver, SpfcError, load_library, make_grid, make_params,
+    Batch, Solver, SpfcError, load_library, make_grid, make_params,
     spfc_workspace_bytes, spfc_init, spfc_step, spfc_mass, spfc_energy, spfc_history,
     spfc_step_count, spfc_get_phi, spfc_state_bytes, spfc_save_state, spfc_load_state,
-    spfc_status, spfc_profile, spfc_kernel_times, spfc_strerror, spfc_destroy,
+    spfc_status, spfc_profile, spfc_kernel_times, spfc_strerror, spfc_destroy, spfc_set_graph,
+    spfc_batch_workspace_bytes, spfc_batch_init, spfc_batch_step, spfc_batch_set_graph,
+    spfc_batch_step_count, spfc_batch_status, spfc_batch_mass, spfc_batch_energy, spfc_batch_history,
+    spfc_batch_get_phi, spfc_batch_destroy,
 )

@@ -23,7 +23,10 @@ PRECISIONS = {"fp64": SPFC_FP64, "fp32": SPFC_FP32}
 EXPORTS = [
     "spfc_workspace_bytes", "spfc_init", "spfc_step", "spfc_mass", "spfc_energy", "spfc_history",
     "spfc_step_count", "spfc_get_phi", "spfc_state_bytes", "spfc_save_state", "spfc_load_state",
-    "spfc_status", "spfc_profile", "spfc_kernel_times", "spfc_strerror", "spfc_destroy",
+    "spfc_status", "spfc_profile", "spfc_kernel_times", "spfc_strerror", "spfc_destroy", "spfc_set_graph",
+    "spfc_batch_workspace_bytes", "spfc_batch_init", "spfc_batch_step", "spfc_batch_set_graph",
+    "spfc_batch_step_count", "spfc_batch_status", "spfc_batch_mass", "spfc_batch_energy", "spfc_batch_history",
+    "spfc_batch_get_phi", "spfc_batch_destroy",
 ]
 
 
@@ -82,6 +85,18 @@ def load_library(path: str | None = None):
         "spfc_profile": [vp, i32],
         "spfc_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
         "spfc_destroy": [vp],
+        "spfc_set_graph": [vp, i32],
+        "spfc_batch_workspace_bytes": [i32, P(spfc_grid), P(spfc_params), P(sz)],
+        "spfc_batch_init": [i32, P(spfc_grid), P(spfc_params), P(vp), vp, sz, vp, P(vp)],
+        "spfc_batch_step": [vp, dbl, i64],
+        "spfc_batch_set_graph": [vp, i32],
+        "spfc_batch_step_count": [vp, P(i64)],
+        "spfc_batch_status": [vp, i32, P(ctypes.c_uint32)],
+        "spfc_batch_mass": [vp, i32, P(dbl)],
+        "spfc_batch_energy": [vp, i32, P(spfc_energy_t)],
+        "spfc_batch_history": [vp, i32, i64, i64, P(spfc_record)],
+        "spfc_batch_get_phi": [vp, i32, vp, i32],
+        "spfc_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -165,7 +180,7 @@ def spfc_energy(ctx, allow_nonfinite: bool = False) -> dict:
 def spfc_history(ctx, first: int, count: int) -> list:
     buf = (spfc_record * max(count, 1))()
     _check("spfc_history", load_library().spfc_history(ctx, int(first), int(count), buf))
-    return [{k: getattr(buf[i], k) for k, _ in spfc_record._fields_ if k != "reserved"} for i in range(count)]
+    return _records(buf, count)
 
 
 def spfc_step_count(ctx) -> int:
@@ -222,14 +237,113 @@ def spfc_destroy(ctx):
     _check("spfc_destroy", load_library().spfc_destroy(ctx))
 
 
+def spfc_set_graph(ctx, enable: bool):
+    _check("spfc_set_graph", load_library().spfc_set_graph(ctx, 1 if enable else 0))
+
+
+def _records(buf, count):
+    return [{k: getattr(buf[i], k) for k, _ in spfc_record._fields_ if k != "reserved"} for i in range(count)]
+
+
+def _arrays(grids, params):
+    ga = (spfc_grid * len(grids))(*grids)
+    pa = (spfc_params * len(params))(*params)
+    return ga, pa
+
+
+def spfc_batch_workspace_bytes(grids, params) -> int:
+    ga, pa = _arrays(grids, params)
+    out = ctypes.c_size_t(0)
+    _check("spfc_batch_workspace_bytes", load_library().spfc_batch_workspace_bytes(len(grids), ga, pa,
+                                                                                   ctypes.byref(out)))
+    return out.value
+
+
+def spfc_batch_init(grids, params, phi0_ptrs, workspace_ptr: int, workspace_bytes: int, stream_ptr: int):
+    ga, pa = _arrays(grids, params)
+    ptrs = (ctypes.c_void_p * len(phi0_ptrs))(*phi0_ptrs)
+    b = ctypes.c_void_p()
+    _check("spfc_batch_init", load_library().spfc_batch_init(len(grids), ga, pa, ptrs, workspace_ptr,
+                                                             workspace_bytes, stream_ptr, ctypes.byref(b)))
+    return b
+
+
+def spfc_batch_step(b, dt: float, n: int):
+    _check("spfc_batch_step", load_library().spfc_batch_step(b, float(dt), int(n)))
+
+
+def spfc_batch_set_graph(b, enable: bool):
+    _check("spfc_batch_set_graph", load_library().spfc_batch_set_graph(b, 1 if enable else 0))
+
+
+def spfc_batch_step_count(b) -> int:
+    n = ctypes.c_int64()
+    _check("spfc_batch_step_count", load_library().spfc_batch_step_count(b, ctypes.byref(n)))
+    return n.value
+
+
+def spfc_batch_status(b, member: int) -> int:
+    f = ctypes.c_uint32()
+    _check("spfc_batch_status", load_library().spfc_batch_status(b, int(member), ctypes.byref(f)))
+    return f.value
+
+
+def spfc_batch_mass(b, member: int) -> float:
+    m = ctypes.c_double()
+    _check("spfc_batch_mass", load_library().spfc_batch_mass(b, int(member), ctypes.byref(m)))
+    return m.value
+
+
+def spfc_batch_energy(b, member: int, allow_nonfinite: bool = False) -> dict:
+    e = spfc_energy_t()
+    st = load_library().spfc_batch_energy(b, int(member), ctypes.byref(e))
+    if not (st == SPFC_OK or (allow_nonfinite and st == SPFC_E_NONFINITE)):
+        _check("spfc_batch_energy", st)
+    return {k: getattr(e, k) for k, _ in spfc_energy_t._fields_}
+
+
+def spfc_batch_history(b, member: int, first: int, count: int) -> list:
+    buf = (spfc_record * max(count, 1))()
+    _check("spfc_batch_history", load_library().spfc_batch_history(b, int(member), int(first), int(count), buf))
+    return _records(buf, count)
+
+
+def spfc_batch_get_phi(b, member: int, out_ptr: int, dtype: int = SPFC_FP64):
+    _check("spfc_batch_get_phi", load_library().spfc_batch_get_phi(b, int(member), out_ptr, int(dtype)))
+
+
+def spfc_batch_destroy(b):
+    _check("spfc_batch_destroy", load_library().spfc_batch_destroy(b))
+
+
 # ------------------------------------------------------------------ convenience class (PyTorch memory + stream)
+
+def _stream_for(torch, stream, graph):
+    """The caller's stream, else a new one when graphs are wanted (they cannot be
+    captured on the null stream), else the current stream."""
+    if stream is not None:
+        return stream
+    if graph:
+        return torch.cuda.Stream()
+    return torch.cuda.current_stream()
+
+
+def _device_field(torch, np, phi0, shape):
+    if isinstance(phi0, torch.Tensor):
+        p0 = phi0.to(device="cuda", dtype=torch.float64).contiguous()
+    else:
+        p0 = torch.from_numpy(np.ascontiguousarray(np.asarray(phi0, dtype=np.float64))).to("cuda")
+    if tuple(p0.shape) != shape:
+        raise ValueError(f"phi0 shape {tuple(p0.shape)} != {shape}")
+    return p0
+
 
 class Solver:
     """One run on the current HIP device.  phi0: array of shape (n_y, n_x) or
     (n_z, n_y, n_x) (x fastest), copied to the device as float64."""
 
     def __init__(self, n, L, phi0, epsilon, c4=1.0, startup="sav1", precision="fp64", history=4096,
-                 energy_tol=0.0, stream=None):
+                 energy_tol=0.0, stream=None, graph=False):
         import numpy as np
         import torch
         if not torch.cuda.is_available():
@@ -239,21 +353,17 @@ class Solver:
         self.n = tuple(int(v) for v in n)
         self.grid = make_grid(n, L)
         self.params = make_params(epsilon, c4, startup, precision, history, energy_tol)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = _stream_for(torch, stream, graph)
         nbytes = spfc_workspace_bytes(self.grid, self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self._ws_bytes = nbytes
-        shape = tuple(reversed(self.n))
-        if isinstance(phi0, torch.Tensor):
-            p0 = phi0.to(device="cuda", dtype=torch.float64).contiguous()
-        else:
-            p0 = torch.from_numpy(np.ascontiguousarray(np.asarray(phi0, dtype=np.float64))).to("cuda")
-        if tuple(p0.shape) != shape:
-            raise ValueError(f"phi0 shape {tuple(p0.shape)} != {shape}")
+        p0 = _device_field(torch, np, phi0, tuple(reversed(self.n)))
         self.ctx = spfc_init(self.grid, self.params, p0.data_ptr(), self._ws_ptr, nbytes, self.stream.cuda_stream)
         del p0
+        if graph:
+            spfc_set_graph(self.ctx, True)
 
     def step(self, dt, n=1):
         spfc_step(self.ctx, dt, n)
@@ -301,6 +411,75 @@ class Solver:
         if getattr(self, "ctx", None) is not None:
             spfc_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent runs advanced together on the current HIP device.  members: list of
+    dicts with keys n, L, phi0, epsilon and optionally c4 and precision; startup,
+    history and energy_tol are shared."""
+
+    def __init__(self, members, startup="sav1", history=4096, energy_tol=0.0, stream=None, graph=False):
+        import numpy as np
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Batch needs a HIP device")
+        load_library()
+        self.torch = torch
+        self.ns = [tuple(int(v) for v in m["n"]) for m in members]
+        self.precisions = [m.get("precision", "fp64") for m in members]
+        grids = [make_grid(m["n"], m["L"]) for m in members]
+        params = [make_params(m["epsilon"], m.get("c4", 1.0), startup, m.get("precision", "fp64"), history,
+                              energy_tol) for m in members]
+        self.stream = _stream_for(torch, stream, graph)
+        nbytes = spfc_batch_workspace_bytes(grids, params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        fields = [_device_field(torch, np, m["phi0"], tuple(reversed(n))) for m, n in zip(members, self.ns)]
+        self.b = spfc_batch_init(grids, params, [f.data_ptr() for f in fields], ws, nbytes,
+                                 self.stream.cuda_stream)
+        del fields
+        if graph:
+            spfc_batch_set_graph(self.b, True)
+
+    def __len__(self):
+        return len(self.ns)
+
+    def step(self, dt, n=1):
+        spfc_batch_step(self.b, dt, n)
+
+    def step_count(self):
+        return spfc_batch_step_count(self.b)
+
+    def status(self, m):
+        return spfc_batch_status(self.b, m)
+
+    def mass(self, m):
+        return spfc_batch_mass(self.b, m)
+
+    def energy(self, m):
+        return spfc_batch_energy(self.b, m)
+
+    def history(self, m, first, count):
+        return spfc_batch_history(self.b, m, first, count)
+
+    def phi(self, m, dtype="fp64"):
+        torch = self.torch
+        out = torch.empty(tuple(reversed(self.ns[m])), dtype=torch.float64 if dtype == "fp64" else torch.float32,
+                          device="cuda")
+        spfc_batch_get_phi(self.b, m, out.data_ptr(), SPFC_FP64 if dtype == "fp64" else SPFC_FP32)
+        self.stream.synchronize()
+        return out
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            spfc_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

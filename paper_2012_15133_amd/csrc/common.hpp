@@ -37,7 +37,8 @@ struct DevScalars {
     unsigned int flags;   // sticky SPFC_FLAG_* bits
     unsigned int pad0;
     long long last_record;
-    double pad[4];
+    long long step_x;     // index of the newest state X of the pair (the record a finish writes)
+    double pad[3];
 };
 
 struct Record {
@@ -59,21 +60,27 @@ enum : unsigned int {
 //   Q (update / query passes): the same five as E for the pair they form
 constexpr int NPART_P = 3, NPART_E = 5;
 
-// What a launch needs to finish the previous step (the SAV scalar) itself.
+// What a launch needs to finish the previous step (the SAV scalar) itself.  All
+// arrays are those of member 0; member m's part starts m * (count per member)
+// further on (see member_finish).
 struct FinishIn {
     const double* partP;
     const double* partE;
-    int nPE;                 // workgroups of the forward pass that wrote P and E
+    int nPE;                 // workgroups per member of the forward pass that wrote P and E
     const double* partB;
-    int nB;
+    int nB;                  // workgroups per member of the real-space pass
     const DevScalars* sc_in;
     DevScalars* sc_out;
     Record* hist;
-    long long hist_cap;
-    long long step;          // index of the state X of the finished step
+    long long hist_cap;      // records per member
     int check_rise;
     double energy_tol;
 };
+
+// A batch of M independent runs of one grid size ("members") shares every launch:
+// member m is blockIdx.y (blockIdx.x for the one-workgroup kernels); its fields
+// start m * fs elements after member 0's, and its geometry and model constants are
+// geos[m].  A single run is a batch of one.
 
 // ------------------------------------------------------------------ kernel arguments
 
@@ -97,7 +104,8 @@ struct SpecInvArgs {
     double e1, e2;          // phihat = e1 X + e2 Y
     int want_grad;          // 0: only the pair partials (no transform, no output)
     double* part;           // no update: NPART_E partials of (X, Y) per workgroup
-    Geo geo;
+    size_t fs;              // member field stride (elements)
+    const Geo* geos;
 };
 
 // Rows of the half spectrum along x -> C2R (two real rows per complex line) ->
@@ -111,7 +119,8 @@ struct RealArgs {
     int nrows;              // rows (a, b) in the input, b fastest
     int G;                  // row groups per workgroup
     double* part;           // E_1 partial per workgroup
-    Geo geo;
+    size_t fs;
+    const Geo* geos;
 };
 
 // Flux spectra along the last axis -> forward transform -> N, the two solves
@@ -129,7 +138,8 @@ struct SpecFwdArgs {
     double a0, a1, a2, dt, e1, e2;
     double* partP;          // NPART_P per workgroup
     double* partE;          // NPART_E per workgroup
-    Geo geo;
+    size_t fs;
+    const Geo* geos;
 };
 
 // Generic batched line transform along the contiguous axis, with the output
@@ -143,6 +153,7 @@ struct PassArgs {
     const cpx<T>* tw;
     int tws;
     int nlines, B, G;
+    size_t fs;
 };
 
 // Real rows <-> half-spectrum rows (set-up and queries).
@@ -169,17 +180,19 @@ struct UpdateArgs {
     int fin;
     FinishIn fi;
     double* part;            // NPART_E per workgroup
-    Geo geo;
+    size_t fs;
+    const Geo* geos;
 };
 
 enum { FWD_SOLVE = 0, FWD_GHOST = 1 };
 
 enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RESTART = 4, FIN_STEP = 5 };
 
+// One workgroup per member (blockIdx.x = member).
 struct FinalizeArgs {
     int mode;
     const double* partQ;    // NPART_E per workgroup (state / query modes)
-    int nQ;
+    int nQ;                 // workgroups per member that wrote Q
     const double* partB;
     int nB;
     double a0, a1, a2, dt;  // FIN_STEP: weights and dt of the step
@@ -187,10 +200,9 @@ struct FinalizeArgs {
     DevScalars* sc;         // other modes: updated in place
     Record* hist;
     long long hist_cap;
-    long long step;
     int check_rise;
     double energy_tol;
-    Geo geo;
+    const Geo* geos;
 };
 
 }  // namespace spfc

@@ -9,22 +9,27 @@
 
 namespace spfc {
 
+// One workgroup per member of the batch (blockIdx.x).
 __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
-    const Geo& geo = p.geo;
+    const int mem = blockIdx.x;
+    const Geo geo = p.geos[mem];
     if (p.mode == FIN_STEP) {
+        const FinishIn fi = member_fin(p.fi, mem);
         double sBP[1 + NPART_P], sE[NPART_E];
-        block_sum_pair<1, NPART_P>(p.fi.partB, p.fi.nB, p.fi.partP, p.fi.nPE, sBP);
-        block_sum_partials<NPART_E>(p.fi.partE, p.fi.nPE, sE);
+        block_sum_pair<1, NPART_P>(fi.partB, fi.nB, fi.partP, fi.nPE, sBP);
+        block_sum_partials<NPART_E>(fi.partE, fi.nPE, sE);
         if (threadIdx.x == 0) {
             const double sP[NPART_P] = {sBP[1], sBP[2], sBP[3]};
-            finish_step(p.fi, sBP[0], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
+            finish_step(fi, sBP[0], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
         }
         return;
     }
     double sQB[NPART_E + 1];
-    block_sum_pair<NPART_E, 1>(p.partQ, p.nQ, p.partB, p.nB, sQB);
+    block_sum_pair<NPART_E, 1>(p.partQ + (size_t)mem * p.nQ * NPART_E, p.nQ, p.partB + (size_t)mem * p.nB, p.nB,
+                               sQB);
     if (threadIdx.x != 0) return;
-    DevScalars* sc = p.sc;
+    DevScalars* sc = p.sc + mem;
+    Record* hist = p.hist + (size_t)mem * p.hist_cap;
     const double n0 = geo.pscale * sQB[0], n1 = geo.pscale * sQB[1];
     const double mean = sQB[4] * geo.inv_npts;
     unsigned int fl = sc->flags;
@@ -34,13 +39,14 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
         const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
         if (!isfinite(energy)) fl |= FLAG_NONFINITE;
         if (p.check_rise && energy > sc->energy_prev * (1.0 + p.energy_tol)) fl |= FLAG_ENERGY_RISE;
-        Record* rc = p.hist + (p.step % p.hist_cap);
+        const long long step = sc->step_x;
+        Record* rc = hist + (step % p.hist_cap);
         rc->energy = energy;
         rc->mean = mean;
         rc->r = rn;
         sc->energy_prev = energy;
         sc->mean = mean;
-        sc->last_record = p.step;
+        sc->last_record = step;
     } else {
         const double E1 = geo.cell * sQB[NPART_E] + geo.e1_const;
         if (!isfinite(E1)) fl |= FLAG_NONFINITE;
@@ -63,8 +69,8 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
     sc->flags = fl;
 }
 
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, a);
+hipError_t launch_finalize(const FinalizeArgs& a, int members, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(members), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 

@@ -43,8 +43,8 @@ template <typename T>
 hipError_t Kern<T>::spec_inv(int nl, int dim, const SpecInvArgs<T>& a, const LaunchShape& s, hipStream_t st) {
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
-        if (dim == 2) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-        else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+        if (dim == 2) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+        else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
     });
 }
@@ -55,11 +55,11 @@ hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, c
     return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
         if (dim == 2) {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, true>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, false>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         } else {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, true>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, false>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, true>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, false>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         }
         return hipGetLastError();
     });
@@ -72,14 +72,14 @@ hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, const SpecFwdArgs<T>& a,
         SPFC_NE_CONSTS
         if (dim == 2) {
             if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
             else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         } else {
             if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
             else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         }
         return hipGetLastError();
     });
@@ -90,7 +90,7 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
                          hipStream_t st) {
 #define SPFC_PASS_CASE(D, OM, CC)                                                                      \
     if (dir == D && omode == OM && c == CC) {                                                        \
-        hipLaunchKernelGGL((k_pass<T, NN, EE, D, OM, CC>), dim3(s.grid), dim3(s.block), s.shmem, st, a); \
+        hipLaunchKernelGGL((k_pass<T, NN, EE, D, OM, CC>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a); \
         return hipGetLastError();                                                                    \
     }
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
@@ -107,9 +107,9 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
 }
 
 template <typename T>
-hipError_t Kern<T>::update(int dim, const UpdateArgs<T>& a, int grid, int block, hipStream_t st) {
-    if (dim == 2) hipLaunchKernelGGL((k_update<T, 2>), dim3(grid), dim3(block), 0, st, a);
-    else hipLaunchKernelGGL((k_update<T, 3>), dim3(grid), dim3(block), 0, st, a);
+hipError_t Kern<T>::update(int dim, const UpdateArgs<T>& a, int grid, int members, int block, hipStream_t st) {
+    if (dim == 2) hipLaunchKernelGGL((k_update<T, 2>), dim3(grid, members), dim3(block), 0, st, a);
+    else hipLaunchKernelGGL((k_update<T, 3>), dim3(grid, members), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
@@ -117,7 +117,7 @@ template <typename T>
 hipError_t Kern<T>::r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st) {
     return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
-        hipLaunchKernelGGL((k_r2c_rows<T, NN, EE, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+        hipLaunchKernelGGL((k_r2c_rows<T, NN, EE, double>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
     });
 }
@@ -126,8 +126,8 @@ template <typename T>
 hipError_t Kern<T>::c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st) {
     return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
-        if (out_fp32) hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, float>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
-        else hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, double>), dim3(s.grid), dim3(s.block), s.shmem, st, a);
+        if (out_fp32) hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, float>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+        else hipLaunchKernelGGL((k_c2r_rows<T, NN, EE, double>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
         return hipGetLastError();
     });
 }

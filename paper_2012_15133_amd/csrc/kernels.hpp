@@ -188,8 +188,9 @@ __device__ __noinline__ double sav_xi(double E1sum, double sP0, double sP1, doub
 }
 
 // Close one step (one lane): copy the scalar block, then record the state X of the
-// step (modified energy, mean, r) and the next state's xi, E_1, p1, S, and shift
-// the r pair.  Reads fi.sc_in, writes fi.sc_out.
+// step (record sc.step_x: modified energy, mean, r) and the next state's xi, E_1,
+// p1, S, and shift the r pair.  Reads fi.sc_in, writes fi.sc_out (already narrowed
+// to one member).
 __device__ inline void finish_step(const FinishIn& fi, double E1sum, const double (&sE)[NPART_E],
                                    const double (&sP)[NPART_P], double a0, double a1, double a2, double dt,
                                    const Geo& geo) {
@@ -210,11 +211,12 @@ __device__ inline void finish_step(const FinishIn& fi, double E1sum, const doubl
     if (E1 < geo.volume * (1.0 - 1e-12)) fl |= FLAG_E1_BELOW_OMEGA;
     if (p1 > 0.0) fl |= FLAG_P1_POSITIVE;
     if (fi.check_rise && energy > s.energy_prev * (1.0 + fi.energy_tol)) fl |= FLAG_ENERGY_RISE;
-    Record* rc = fi.hist + (fi.step % fi.hist_cap);
+    const long long step = s.step_x;
+    Record* rc = fi.hist + (step % fi.hist_cap);
     rc->energy = energy;
     rc->mean = mean;
     rc->r = rn;
-    Record* rn1 = fi.hist + ((fi.step + 1) % fi.hist_cap);
+    Record* rn1 = fi.hist + ((step + 1) % fi.hist_cap);
     rn1->energy = 0.0;
     rn1->mean = 0.0;
     rn1->r = rnew;
@@ -234,8 +236,21 @@ __device__ inline void finish_step(const FinishIn& fi, double E1sum, const doubl
     s.S = S;
     s.mean = mean;
     s.flags = fl;
-    s.last_record = fi.step;
+    s.last_record = step;
+    s.step_x = step + 1;
     *fi.sc_out = s;
+}
+
+// FinishIn narrowed to member m of the batch.
+__device__ inline FinishIn member_fin(const FinishIn& f, int m) {
+    FinishIn r = f;
+    r.partP = f.partP + (size_t)m * f.nPE * NPART_P;
+    r.partE = f.partE + (size_t)m * f.nPE * NPART_E;
+    r.partB = f.partB + (size_t)m * f.nB;
+    r.sc_in = f.sc_in + m;
+    r.sc_out = f.sc_out + m;
+    r.hist = f.hist + (size_t)m * f.hist_cap;
+    return r;
 }
 
 // Every workgroup of a launch reduces the previous step's partial sums in the
@@ -276,8 +291,10 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
-    const Geo& geo = p.geo;
-    const size_t lbase = (size_t)(act ? line : 0) * NL;
+    const int mem = blockIdx.y;
+    const Geo geo = p.geos[mem];
+    const size_t lbase = (size_t)mem * p.fs + (size_t)(act ? line : 0) * NL;
+    const size_t mbase = (size_t)mem * p.fs;
 
     // all loads first (the update writes in place over `prev`, so later loads
     // must not wait behind earlier stores)
@@ -290,7 +307,10 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
         nh[m] = (act && p.update) ? p.nhat[i] : mk<T>(0, 0);
     }
     double xi = 0.0;
-    if (p.update) xi = p.fin ? finish_in_kernel(p.fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : p.fi.sc_in->xi;
+    if (p.update) {
+        const FinishIn fi = member_fin(p.fi, mem);
+        xi = p.fin ? finish_in_kernel(fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : fi.sc_in->xi;
+    }
 
     double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
     cpx<T> v[C][E];
@@ -324,14 +344,14 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             v[j][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1_j phihat
         }
     }
-    if (!p.update) block_sum_store<NPART_E>(acc, p.part + NPART_E * blockIdx.x);
+    if (!p.update) block_sum_store<NPART_E>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
     if (p.want_grad) {
         stage_twiddles<T, PL>(ltw, p.tw, p.tws);
         fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
         if (act) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                cpx<T>* o = p.out[j];
+                cpx<T>* o = p.out[j] + mbase;
 #pragma unroll
                 for (int m = 0; m < E; ++m) o[(size_t)(t + P * m) * p.nlines + line] = v[j][m];
             }
@@ -390,13 +410,15 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * RPG;
     const bool act = row0 < p.nrows;
-    const Geo& geo = p.geo;
+    const int mem = blockIdx.y;
+    const Geo geo = p.geos[mem];
+    const size_t mbase = (size_t)mem * p.fs;
 
     cpx<T> v[C][E];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const cpx<T>* h1 = p.in[PK::fa(c)] + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
-        const cpx<T>* h2 = p.in[PK::fb(c)] + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
+        const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
+        const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
 #pragma unroll
         for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
     }
@@ -439,8 +461,8 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
             const T half = T(0.5);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                cpx<T>* o1 = p.out[PK::fa(c)];
-                cpx<T>* o2 = p.out[PK::fb(c)];
+                cpx<T>* o1 = p.out[PK::fa(c)] + mbase;
+                cpx<T>* o2 = p.out[PK::fb(c)] + mbase;
                 const int r1 = row0 + PK::ra(c), r2 = row0 + PK::rb(c);
 #pragma unroll
                 for (int m = 0; m <= E / 2; ++m) {
@@ -456,7 +478,7 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
             }
         }
     }
-    block_sum_store<1>(acc, p.part + blockIdx.x);
+    block_sum_store<1>(acc, p.part + (size_t)mem * gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------------------ generic line pass
@@ -471,19 +493,20 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
+    const size_t mbase = (size_t)blockIdx.y * p.fs;
     const size_t lbase = (size_t)(act ? line : 0) * NL;
     cpx<T> v[C][E];
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][lbase + t + P * m] : mk<T>(0, 0);
+        for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][mbase + lbase + t + P * m] : mk<T>(0, 0);
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
     fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
     if (!act) return;
     const int a = line / p.B, b = line - a * p.B;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        cpx<T>* o = p.out[c];
+        cpx<T>* o = p.out[c] + mbase;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int e = t + P * m;
@@ -513,8 +536,9 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
-    const Geo& geo = p.geo;
-    const size_t lbase = (size_t)(act ? line : 0) * NL;
+    const int mem = blockIdx.y;
+    const Geo geo = p.geos[mem];
+    const size_t lbase = (size_t)mem * p.fs + (size_t)(act ? line : 0) * NL;
 
     cpx<T> v[C][E];
 #pragma unroll
@@ -569,8 +593,9 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
         }
     }
     if constexpr (MODE == FWD_SOLVE) {
-        block_sum_store<NPART_P>(acc, p.partP + NPART_P * blockIdx.x);
-        block_sum_store<NPART_E>(accE, p.partE + NPART_E * blockIdx.x);
+        const size_t wg = (size_t)mem * gridDim.x + blockIdx.x;
+        block_sum_store<NPART_P>(acc, p.partP + NPART_P * wg);
+        block_sum_store<NPART_E>(accE, p.partE + NPART_E * wg);
     }
 }
 
@@ -578,8 +603,11 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
-    const Geo& geo = p.geo;
-    const double xi = p.fin ? finish_in_kernel(p.fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : p.fi.sc_in->xi;
+    const int mem = blockIdx.y;
+    const Geo geo = p.geos[mem];
+    const FinishIn fi = member_fin(p.fi, mem);
+    const double xi = p.fin ? finish_in_kernel(fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : fi.sc_in->xi;
+    const size_t mbase = (size_t)mem * p.fs;
     double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < p.total;
          i += (long long)gridDim.x * blockDim.x) {
@@ -588,14 +616,14 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         double k2, k1[3];
         spec_index<DIM>(line, p.B, e, kx, ky, kz);
         spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
-        const cpx<T> cur = p.cur[i], prv = p.prev[i], nh = p.nhat[i];
+        const cpx<T> cur = p.cur[mbase + i], prv = p.prev[mbase + i], nh = p.nhat[mbase + i];
         const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
         const double f1 = -p.udt * xi * k2 * iA, f2 = p.ua1 * iA, f3 = p.ua2 * iA;
         const cpx<T> X = mk<T>(T(f1 * nh.x + f2 * cur.x + f3 * prv.x), T(f1 * nh.y + f2 * cur.y + f3 * prv.y));
-        p.out_new[i] = X;
+        p.out_new[mbase + i] = X;
         pair_partials<T>(X, cur, kx, k2, i == 0, geo, acc);
     }
-    block_sum_store<NPART_E>(acc, p.part + NPART_E * blockIdx.x);
+    block_sum_store<NPART_E>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
 }
 
 // ------------------------------------------------------------------ rows: real <-> half spectrum

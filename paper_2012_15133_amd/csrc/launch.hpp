@@ -13,8 +13,9 @@ struct LaunchShape {
     int E;          // values per thread (radix of the full passes)
     int G;          // line groups per workgroup
     int block;      // threads per workgroup
-    int grid;       // workgroups
+    int grid;       // workgroups per member
     size_t shmem;   // dynamic LDS bytes
+    int members;    // batch members (grid y)
 };
 
 // E values per thread (clamped to the line length), P = N / E threads per group,
@@ -36,6 +37,7 @@ inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int E = 16
     s.block = G * P;
     s.grid = (ngroups + G - 1) / G;
     s.shmem = (size_t)G * per + twb;
+    s.members = 1;
     return s;
 }
 
@@ -48,13 +50,13 @@ struct Kern {
                                hipStream_t st);
     static hipError_t pass(int nl, int dir, int omode, int c, const PassArgs<T>& a, const LaunchShape& s,
                            hipStream_t st);
-    static hipError_t update(int dim, const UpdateArgs<T>& a, int grid, int block, hipStream_t st);
+    static hipError_t update(int dim, const UpdateArgs<T>& a, int grid, int members, int block, hipStream_t st);
     static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
     // values per thread available for line length n
     static bool has_E(int n, int E) { return n < 16 ? E == n : (E == 4 || E == 8 || E == 16); }
     static hipError_t c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
 };
 
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, int members, hipStream_t st);
 
 }  // namespace spfc

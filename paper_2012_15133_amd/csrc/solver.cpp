@@ -1,11 +1,16 @@
 // Host driver and C ABI (include/spfc.h): validation, workspace carving, the
-// per-step launch sequence, start-up, queries and checkpoints.
+// per-step launch sequence, start-up, queries, checkpoints, graph replay of the
+// steady steps, and batches of independent runs ("members") of one grid size
+// that share every launch.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "launch.hpp"
@@ -35,33 +40,25 @@ struct Shapes {
 };
 
 struct Layout {
-    size_t F;  // bytes of one half-spectrum field
-    size_t off_slot[2], off_nhat, off_bufA, off_bufB, off_tw, off_partP, off_partE, off_partB, off_partQ, off_sc,
-        off_hist;
+    size_t F;            // bytes of one half-spectrum field of one member
+    size_t fs;           // elements of one half-spectrum field of one member
+    size_t field_bytes;  // bytes of one field region (all members)
+    size_t sc_bytes;     // bytes of one copy of the scalar blocks (all members)
+    size_t off_slot[2], off_nhat, off_bufA, off_bufB, off_tw, off_partP, off_partE, off_partB, off_partQ, off_geo,
+        off_sc, off_hist;
     size_t total;
-    int nPE, nB, nQ;
     int ntab;
 };
 
-Sizes sizes_of(const spfc_grid& g, int prec) {
-    Sizes s;
-    s.dim = g.dim;
-    s.nx = g.n[0];
-    s.ny = g.n[1];
-    s.nz = g.dim == 3 ? g.n[2] : 1;
-    s.nxh = s.nx / 2 + 1;
-    s.elem = prec == SPFC_FP32 ? 2 * sizeof(float) : 2 * sizeof(double);
-    return s;
-}
-
 // Launch plan of the step kernels: values per thread (E) and target threads per
-// workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T".
+// workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T"
+// (and "finsep" to close every step in a separate kernel).
 struct RolePlan {
     int E = 8, T = 256;
 };
 struct TunePlan {
-    RolePlan inv, real, fwd, mid, misc;
-    int fin_in_kernel = 1;   // allow closing each step inside the next update kernel
+    RolePlan inv, real, fwd, mid;
+    int fin_in_kernel = 1;  // allow closing each step inside the next update kernel
 };
 
 void parse_role(const char* spec, const char* key, RolePlan& r) {
@@ -88,12 +85,23 @@ TunePlan tune_plan() {
     return tp;
 }
 
-Shapes shapes_of(const Sizes& s) {
+Sizes sizes_of(const spfc_grid& g, int prec) {
+    Sizes s;
+    s.dim = g.dim;
+    s.nx = g.n[0];
+    s.ny = g.n[1];
+    s.nz = g.dim == 3 ? g.n[2] : 1;
+    s.nxh = s.nx / 2 + 1;
+    s.elem = prec == SPFC_FP32 ? 2 * sizeof(float) : 2 * sizeof(double);
+    return s;
+}
+
+Shapes shapes_of(const Sizes& s, int M) {
     const TunePlan tp = tune_plan();
     Shapes h{};
     const int d = s.dim;
     const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
-    const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines
+    const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines per member
     h.A = line_shape(nl, d, s.elem, nlines, tp.inv.E, tp.inv.T);
     h.Cf = line_shape(nl, d, s.elem, nlines, tp.fwd.E, tp.fwd.T);
     const int rowgroups = d == 2 ? s.ny : s.nz * s.ny / 2;
@@ -108,32 +116,36 @@ Shapes shapes_of(const Sizes& s) {
     h.c2r = line_shape(s.nx, 1, s.elem, s.ny * s.nz / 2);
     h.keep = line_shape(nl, 1, s.elem, nlines);
     h.rot = line_shape(nl, 1, s.elem, nlines);
+    // the step kernels cover every member in one launch (grid y)
+    for (LaunchShape* x : {&h.A, &h.Cf, &h.B, &h.midI, &h.midF}) x->members = M;
     const long long total = (long long)s.nxh * s.ny * s.nz;
-    h.updGrid = (int)std::min<long long>((total + 255) / 256, 2048);
+    const long long cap = std::max(64, 2048 / M);
+    h.updGrid = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, cap));
     return h;
 }
 
-Layout layout_of(const Sizes& s, const Shapes& h, int64_t hist_cap) {
+Layout layout_of(const Sizes& s, const Shapes& h, int64_t hist_cap, int M) {
     Layout L{};
-    L.F = (size_t)s.nxh * s.ny * s.nz * s.elem;
-    const size_t Fa = align_up(L.F);
+    L.fs = (size_t)s.nxh * s.ny * s.nz;
+    L.F = L.fs * s.elem;
+    L.field_bytes = align_up(L.F * M);
     size_t o = 0;
-    L.off_slot[0] = o; o += Fa;
-    L.off_slot[1] = o; o += Fa;
-    L.off_nhat = o; o += Fa;
-    L.off_bufA = o; o += 3 * Fa;
-    L.off_bufB = o; o += 3 * Fa;
+    L.off_slot[0] = o; o += L.field_bytes;
+    L.off_slot[1] = o; o += L.field_bytes;
+    L.off_nhat = o; o += L.field_bytes;
+    L.off_bufA = o; o += 3 * L.field_bytes;
+    L.off_bufB = o; o += 3 * L.field_bytes;
     L.ntab = std::max(s.nx, std::max(s.ny, s.nz));
     L.off_tw = o; o += align_up((size_t)L.ntab * s.elem);
-    L.nPE = h.Cf.grid;
-    L.nB = h.B.grid;
-    L.nQ = std::max(h.A.grid, h.updGrid);
-    L.off_partP = o; o += align_up((size_t)L.nPE * NPART_P * sizeof(double));
-    L.off_partE = o; o += align_up((size_t)L.nPE * NPART_E * sizeof(double));
-    L.off_partB = o; o += align_up((size_t)L.nB * sizeof(double));
-    L.off_partQ = o; o += align_up((size_t)L.nQ * NPART_E * sizeof(double));
-    L.off_sc = o; o += 2 * align_up(sizeof(DevScalars));
-    L.off_hist = o; o += align_up((size_t)hist_cap * sizeof(Record));
+    const int nQ = std::max(h.A.grid, h.updGrid);
+    L.off_partP = o; o += align_up((size_t)M * h.Cf.grid * NPART_P * sizeof(double));
+    L.off_partE = o; o += align_up((size_t)M * h.Cf.grid * NPART_E * sizeof(double));
+    L.off_partB = o; o += align_up((size_t)M * h.B.grid * sizeof(double));
+    L.off_partQ = o; o += align_up((size_t)M * nQ * NPART_E * sizeof(double));
+    L.off_geo = o; o += align_up((size_t)M * sizeof(Geo));
+    L.sc_bytes = align_up((size_t)M * sizeof(DevScalars));
+    L.off_sc = o; o += 2 * L.sc_bytes;
+    L.off_hist = o; o += align_up((size_t)M * hist_cap * sizeof(Record));
     L.total = o;
     return L;
 }
@@ -154,6 +166,29 @@ int validate(const spfc_grid* g, const spfc_params* p) {
     return SPFC_OK;
 }
 
+Geo make_geo(const spfc_grid& g, const spfc_params& prm) {
+    Geo geo{};
+    geo.dim = g.dim;
+    geo.nx = g.n[0];
+    geo.ny = g.n[1];
+    geo.nz = g.dim == 3 ? g.n[2] : 1;
+    geo.nxh = geo.nx / 2 + 1;
+    const double twopi = 6.283185307179586476925286766559;
+    geo.k0x = twopi / g.L[0];
+    geo.k0y = twopi / g.L[1];
+    geo.k0z = g.dim == 3 ? twopi / g.L[2] : 0.0;
+    geo.a = 1.0 - prm.epsilon;
+    geo.c4 = prm.c4;
+    const double npts = (double)geo.nx * geo.ny * geo.nz;
+    geo.inv_npts = 1.0 / npts;
+    const double vol = g.L[0] * g.L[1] * (g.dim == 3 ? g.L[2] : 1.0);
+    geo.volume = vol;
+    geo.cell = vol / npts;
+    geo.pscale = vol / (npts * npts);
+    geo.e1_const = (1.0 + 1.0 / prm.c4) * vol;
+    return geo;
+}
+
 struct CkptHeader {
     uint64_t magic;
     int64_t step;
@@ -163,17 +198,18 @@ struct CkptHeader {
     int32_t pad;
     DevScalars sc;
 };
-constexpr uint64_t kMagic = 0x5350464353415631ull;
+constexpr uint64_t kMagic = 0x5350464353415632ull;
 
 }  // namespace
 
+// One grid size and precision; M members advance together (a single run is M = 1).
 struct spfc_ctx {
-    spfc_grid grid;
-    spfc_params prm;
+    spfc_params prm;        // shared by the members: startup, precision, history, energy_tol
+    int M;
+    std::vector<Geo> geos;  // per member (host copy of the device array)
     Sizes sz;
     Shapes sh;
     Layout lay;
-    Geo geo;
     hipStream_t stream;
     char* ws;
     int slotX, slotY;  // slots of the newest (X) and older (Y) state of the pair
@@ -182,8 +218,12 @@ struct spfc_ctx {
     bool started;
     bool broken;
     double energy_tol;
-    int cur_sc;            // which of the two scalar blocks holds the latest values
-    bool fin_in;           // close each step inside the next update kernel
+    int cur_sc;        // which of the two scalar-block copies holds the latest values
+    bool fin_in;       // close each step inside the next update kernel
+    // graph replay of two steady steps
+    bool use_graph;
+    std::vector<std::pair<std::tuple<double, int, int, int>, hipGraphExec_t>> graphs;  // newest last
+    // profiling
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
@@ -192,30 +232,38 @@ struct spfc_ctx {
 
     char* slot(int i) const { return ws + lay.off_slot[i]; }
     char* nhat() const { return ws + lay.off_nhat; }
-    char* bufA(int j) const { return ws + lay.off_bufA + j * align_up(lay.F); }
-    char* bufB(int j) const { return ws + lay.off_bufB + j * align_up(lay.F); }
+    char* bufA(int j) const { return ws + lay.off_bufA + j * lay.field_bytes; }
+    char* bufB(int j) const { return ws + lay.off_bufB + j * lay.field_bytes; }
     char* tw() const { return ws + lay.off_tw; }
     double* partP() const { return reinterpret_cast<double*>(ws + lay.off_partP); }
     double* partE() const { return reinterpret_cast<double*>(ws + lay.off_partE); }
     double* partB() const { return reinterpret_cast<double*>(ws + lay.off_partB); }
     double* partQ() const { return reinterpret_cast<double*>(ws + lay.off_partQ); }
-    DevScalars* scb(int i) const { return reinterpret_cast<DevScalars*>(ws + lay.off_sc + i * align_up(sizeof(DevScalars))); }
-    DevScalars* sc() const { return scb(cur_sc); }
-    Record* hist() const { return reinterpret_cast<Record*>(ws + lay.off_hist); }
+    const Geo* dgeos() const { return reinterpret_cast<const Geo*>(ws + lay.off_geo); }
+    DevScalars* scb(int i) const { return reinterpret_cast<DevScalars*>(ws + lay.off_sc + i * lay.sc_bytes); }
+    DevScalars* sc(int m = 0) const { return scb(cur_sc) + m; }
+    Record* hist(int m = 0) const { return reinterpret_cast<Record*>(ws + lay.off_hist) + (size_t)m * prm.history; }
+    size_t moff(int m) const { return (size_t)m * lay.F; }
     int nl() const { return sz.dim == 2 ? sz.ny : sz.nz; }
     int nlines() const { return sz.dim == 2 ? sz.nxh : sz.nxh * sz.ny; }
     int lineB() const { return sz.dim == 2 ? sz.nxh : sz.ny; }
 };
 
+// A batch: one context per (grid size, precision) class of members.
+struct spfc_batch {
+    std::vector<spfc_ctx*> cls;
+    std::vector<std::pair<int, int>> where;  // member -> (class, index within the class)
+};
+
 namespace {
 
-#define CK(x)                   \
-    do {                        \
-        hipError_t e_ = (x);    \
-        if (e_ != hipSuccess) { \
-            ctx->broken = true; \
+#define CK(x)                     \
+    do {                          \
+        hipError_t e_ = (x);      \
+        if (e_ != hipSuccess) {   \
+            ctx->broken = true;   \
             return SPFC_E_DEVICE; \
-        }                       \
+        }                         \
     } while (0)
 
 // ---------------------------------------------------------------- profiling
@@ -265,15 +313,30 @@ struct Timed {
     }
 };
 
+void drop_graph(spfc_ctx* ctx) {
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+}
+
 // ---------------------------------------------------------------- pipeline (one precision)
+
+// Weights of the steady BDF2 step (eq. scheme-SAV-1) and of the extrapolation 2X - Y.
+constexpr double kA0 = 1.5, kA1 = 2.0, kA2 = -0.5, kE1 = 2.0, kE2 = -1.0;
 
 template <typename T>
 struct Pipe {
     using C = cpx<T>;
     spfc_ctx* ctx;
 
-    // What an update kernel needs to close the step whose N is pending.
-    FinishIn finish_in(long long step, int check_rise) {
+    // Pending step (weights, dt, rise check) whose scalar is still to be solved.
+    struct Pending {
+        bool open = false;
+        double a0 = 0, a1 = 0, a2 = 0, dt = 0;
+        int check = 0;
+    };
+
+    // What a launch needs to close the step whose N is pending (all members).
+    FinishIn finish_in(int check_rise) {
         FinishIn f{};
         f.partP = ctx->partP();
         f.partE = ctx->partE();
@@ -284,19 +347,10 @@ struct Pipe {
         f.sc_out = ctx->scb(1 - ctx->cur_sc);
         f.hist = ctx->hist();
         f.hist_cap = ctx->prm.history;
-        f.step = step;
         f.check_rise = check_rise;
         f.energy_tol = ctx->energy_tol;
         return f;
     }
-
-    // Pending step (weights, dt, index, rise check) whose scalar is still to be solved.
-    struct Pending {
-        bool open = false;
-        double a0 = 0, a1 = 0, a2 = 0, dt = 0;
-        long long step = 0;
-        int check = 0;
-    };
 
     // spectral state (cur, prev) -> gradient transforms along the last axis -> bufA.
     // With `pend.open` the kernel first applies the pending update (closing that
@@ -320,12 +374,13 @@ struct Pipe {
         a.ua2 = pend.a2;
         a.udt = pend.dt;
         a.fin = (pend.open && ctx->fin_in) ? 1 : 0;
-        a.fi = finish_in(pend.step, pend.check);
+        a.fi = finish_in(pend.check);
         a.e1 = e1;
         a.e2 = e2;
         a.want_grad = want_grad ? 1 : 0;
         a.part = ctx->partQ();
-        a.geo = ctx->geo;
+        a.fs = ctx->lay.fs;
+        a.geos = ctx->dgeos();
         {
             Timed tm(ctx, R_SPEC_INV, timed);
             CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, a, ctx->sh.A, ctx->stream));
@@ -347,6 +402,7 @@ struct Pipe {
         a.nlines = nlines;
         a.B = B;
         a.G = s.G;
+        a.fs = ctx->lay.fs;
         Timed tm(ctx, role, timed);
         CK(Kern<T>::pass(ctx->sz.ny, dir, OUT_SWAP, 3, a, s, ctx->stream));
         return SPFC_OK;
@@ -364,7 +420,8 @@ struct Pipe {
         a.nrows = ctx->sz.ny * ctx->sz.nz;
         a.G = ctx->sh.B.G;
         a.part = ctx->partB();
-        a.geo = ctx->geo;
+        a.fs = ctx->lay.fs;
+        a.geos = ctx->dgeos();
         Timed tm(ctx, R_REAL, timed);
         CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, a, ctx->sh.B, ctx->stream));
         return SPFC_OK;
@@ -391,13 +448,14 @@ struct Pipe {
         a.e2 = e2;
         a.partP = ctx->partP();
         a.partE = ctx->partE();
-        a.geo = ctx->geo;
+        a.fs = ctx->lay.fs;
+        a.geos = ctx->dgeos();
         Timed tm(ctx, R_SPEC_FWD, timed);
         CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, a, ctx->sh.Cf, ctx->stream));
         return SPFC_OK;
     }
 
-    // one-workgroup close of a step (FIN_STEP) or of a state / query pass
+    // one workgroup per member: close a step (FIN_STEP) or a state / query pass
     int finalize(int mode, int nQ, int check_rise, const Pending* pend = nullptr, bool timed = false) {
         FinalizeArgs f{};
         f.mode = mode;
@@ -410,18 +468,17 @@ struct Pipe {
             f.a1 = pend->a1;
             f.a2 = pend->a2;
             f.dt = pend->dt;
-            f.fi = finish_in(pend->step, pend->check);
+            f.fi = finish_in(pend->check);
         }
         f.sc = ctx->sc();
         f.hist = ctx->hist();
         f.hist_cap = ctx->prm.history;
-        f.step = ctx->step;
         f.check_rise = check_rise;
         f.energy_tol = ctx->energy_tol;
-        f.geo = ctx->geo;
+        f.geos = ctx->dgeos();
         {
             Timed tm(ctx, R_FINAL, timed);
-            CK(launch_finalize(f, ctx->stream));
+            CK(launch_finalize(f, ctx->M, ctx->stream));
         }
         if (mode == FIN_STEP) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
@@ -443,28 +500,114 @@ struct Pipe {
         return finalize(fin_mode, ctx->sh.A.grid, 0);
     }
 
+    // gradient spectra in bufA -> flux spectra; returns where they are
+    int flux(bool timed, char** out) {
+        int rc;
+        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
+        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
+        if (ctx->sz.dim == 3) {
+            if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, timed)))
+                return rc;
+            if ((rc = real_pass(bB, bA, true, timed))) return rc;
+            if ((rc = mid(-1, bA, bB, ctx->sh.midF, ctx->sz.nxh * ctx->sz.nz, ctx->sz.nz, R_MID_FWD, timed)))
+                return rc;
+        } else {
+            if ((rc = real_pass(bA, bB, true, timed))) return rc;
+        }
+        for (int j = 0; j < 3; ++j) out[j] = bB[j];
+        return SPFC_OK;
+    }
+
     // Ghost start (eq. scheme-SAV-initial-1): phi^{-1} into the other slot, r^0 and r^{-1}.
     int ghost(double dt) {
         int rc;
         const int o = 1 - ctx->slotX;
         char* X = ctx->slot(ctx->slotX);
         if ((rc = spec_inv(X, X, nullptr, Pending{}, 1.0, 0.0, true, false))) return rc;
-        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
-        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
-        char** flux = bB;
-        if (ctx->sz.dim == 3) {
-            if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, false)))
-                return rc;
-            if ((rc = real_pass(bB, bA, true, false))) return rc;
-            if ((rc = mid(-1, bA, bB, ctx->sh.midF, ctx->sz.nxh * ctx->sz.nz, ctx->sz.nz, R_MID_FWD, false)))
-                return rc;
-        } else {
-            if ((rc = real_pass(bA, bB, true, false))) return rc;
-        }
-        if ((rc = spec_fwd(flux, X, X, FWD_GHOST, ctx->slot(o), 1.0, 0.0, 0.0, dt, 1.0, 0.0, false))) return rc;
+        char* fl[3];
+        if ((rc = flux(false, fl))) return rc;
+        if ((rc = spec_fwd(fl, X, X, FWD_GHOST, ctx->slot(o), 1.0, 0.0, 0.0, dt, 1.0, 0.0, false))) return rc;
         if ((rc = finalize(FIN_GHOST_R0, ctx->sh.A.grid, 0))) return rc;
         if ((rc = e1_pass(ctx->slot(o), ctx->slot(o), FIN_GHOST_RM1))) return rc;
         ctx->slotY = o;
+        return SPFC_OK;
+    }
+
+    // One step: (pending update, closing that step), gradient and inverse passes,
+    // real-space pass, forward pass + N + inner products; leaves this step pending.
+    int body(Pending& pend, double dt, double a0, double a1, double a2, double e1, double e2, int check,
+             bool timed) {
+        int rc;
+        if (!pend.open) {
+            if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, pend, e1, e2, true, timed)))
+                return rc;
+        } else {
+            const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
+            if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), ctx->slot(target), pend, e1, e2, true,
+                               timed)))
+                return rc;
+            ctx->slotY = ctx->slotX;
+            ctx->slotX = target;
+            ctx->step += 1;
+        }
+        char* fl[3];
+        if ((rc = flux(timed, fl))) return rc;
+        if ((rc = spec_fwd(fl, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt, e1,
+                           e2, timed)))
+            return rc;
+        pend.open = true;
+        pend.a0 = a0;
+        pend.a1 = a1;
+        pend.a2 = a2;
+        pend.dt = dt;
+        pend.check = check;
+        if (!ctx->fin_in) {
+            // the SAV scalar: xi, r^{n+1}, the record of phi^n
+            if ((rc = finalize(FIN_STEP, 0, 0, &pend, timed))) return rc;
+        }
+        return SPFC_OK;
+    }
+
+    // `pairs` replays of a graph of two steady steps.  The launches of two steps
+    // depend only on dt, the slot pair and the scalar-block parity, and two steps
+    // bring all three back; a graph is captured on first use of such a key and
+    // kept (the last few keys).
+    int graph_pairs(Pending& pend, double dt, int64_t pairs) {
+        const auto key = std::make_tuple(dt, ctx->slotX, ctx->slotY, ctx->cur_sc);
+        hipGraphExec_t exec = nullptr;
+        for (auto& g : ctx->graphs)
+            if (g.first == key) exec = g.second;
+        if (!exec) {
+            const int sx = ctx->slotX, sy = ctx->slotY, cs = ctx->cur_sc;
+            const int64_t st = ctx->step;
+            const Pending p0 = pend;
+            CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            int rc = SPFC_OK;
+            for (int k = 0; k < 2 && rc == SPFC_OK; ++k) rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, 1, false);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            CK(ec);
+            const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            CK(ei);
+            if (ctx->graphs.size() >= 4) {
+                (void)hipGraphExecDestroy(ctx->graphs.front().second);
+                ctx->graphs.erase(ctx->graphs.begin());
+            }
+            ctx->graphs.push_back({key, exec});
+            // capture only recorded the launches: back to the state before them
+            ctx->slotX = sx;
+            ctx->slotY = sy;
+            ctx->cur_sc = cs;
+            ctx->step = st;
+            pend = p0;
+        }
+        for (int64_t i = 0; i < pairs; ++i) CK(hipGraphLaunch(exec, ctx->stream));
+        ctx->step += 2 * pairs;
         return SPFC_OK;
     }
 
@@ -482,50 +625,25 @@ struct Pipe {
                 first_order = (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_SAV1);
             }
         }
-        char* bA[3] = {ctx->bufA(0), ctx->bufA(1), ctx->bufA(2)};
-        char* bB[3] = {ctx->bufB(0), ctx->bufB(1), ctx->bufB(2)};
-        const int d = ctx->sz.dim;
+        const bool graphs = ctx->use_graph && !ctx->profiling && ctx->stream != nullptr;
         Pending pend;
-        for (int64_t i = 0; i < n; ++i) {
+        int64_t i = 0;
+        while (i < n) {
+            // steady: a pending BDF2 step of this dt whose rise check is on, two distinct slots
+            const bool steady = pend.open && pend.a0 == kA0 && pend.check == 1 && pend.dt == dt &&
+                                ctx->slotX != ctx->slotY;
+            if (graphs && steady && n - i >= 2) {
+                const int64_t pairs = (n - i) / 2;
+                if ((rc = graph_pairs(pend, dt, pairs))) return rc;
+                i += 2 * pairs;
+                continue;
+            }
             const bool sav1 = first_order && i == 0;
-            const double a0 = sav1 ? 1.0 : 1.5, a1 = sav1 ? 1.0 : 2.0, a2 = sav1 ? 0.0 : -0.5;
-            const double e1 = sav1 ? 1.0 : 2.0, e2 = sav1 ? 0.0 : -1.0;
-            if (!pend.open) {
-                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, pend, e1, e2, true, true)))
-                    return rc;
-            } else {
-                const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
-                if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), ctx->slot(target), pend, e1, e2,
-                                   true, true)))
-                    return rc;
-                ctx->slotY = ctx->slotX;
-                ctx->slotX = target;
-                ctx->step += 1;
-            }
-            char** flux = bB;
-            if (d == 3) {
-                if ((rc = mid(+1, bA, bB, ctx->sh.midI, ctx->sz.nz * ctx->sz.nxh, ctx->sz.nxh, R_MID_INV, true)))
-                    return rc;
-                if ((rc = real_pass(bB, bA, true, true))) return rc;
-                if ((rc = mid(-1, bA, bB, ctx->sh.midF, ctx->sz.nxh * ctx->sz.nz, ctx->sz.nz, R_MID_FWD, true)))
-                    return rc;
-            } else {
-                if ((rc = real_pass(bA, bB, true, true))) return rc;
-            }
-            if ((rc = spec_fwd(flux, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt,
-                               e1, e2, true)))
-                return rc;
-            pend.open = true;
-            pend.a0 = a0;
-            pend.a1 = a1;
-            pend.a2 = a2;
-            pend.dt = dt;
-            pend.step = ctx->step;
-            pend.check = (i == 0 && restart) ? 0 : 1;
-            if (!ctx->fin_in) {
-                // the SAV scalar: xi, r^{n+1}, the record of phi^n
-                if ((rc = finalize(FIN_STEP, 0, 0, &pend, true))) return rc;
-            }
+            const int check = (i == 0 && restart) ? 0 : 1;
+            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, true);
+            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, true);
+            if (rc) return rc;
+            ++i;
         }
         // apply the last update and record the state it reaches
         const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
@@ -534,7 +652,7 @@ struct Pipe {
         u.prev = (const C*)ctx->slot(ctx->slotY);
         u.nhat = (const C*)ctx->nhat();
         u.out_new = (C*)ctx->slot(target);
-        u.total = (long long)ctx->sz.nxh * ctx->sz.ny * ctx->sz.nz;
+        u.total = (long long)ctx->lay.fs;
         u.NL = ctx->nl();
         u.B = ctx->lineB();
         u.ua0 = pend.a0;
@@ -542,10 +660,11 @@ struct Pipe {
         u.ua2 = pend.a2;
         u.udt = pend.dt;
         u.fin = ctx->fin_in ? 1 : 0;
-        u.fi = finish_in(pend.step, pend.check);
+        u.fi = finish_in(pend.check);
         u.part = ctx->partQ();
-        u.geo = ctx->geo;
-        CK(Kern<T>::update(d, u, ctx->sh.updGrid, 256, ctx->stream));
+        u.fs = ctx->lay.fs;
+        u.geos = ctx->dgeos();
+        CK(Kern<T>::update(ctx->sz.dim, u, ctx->sh.updGrid, ctx->M, 256, ctx->stream));
         if (u.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         ctx->slotY = ctx->slotX;
         ctx->slotX = target;
@@ -556,11 +675,12 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    // real field (doubles, x fastest) -> half spectrum in slot `s`
-    int forward_real(const double* phi, int s) {
+    // real field of member m (doubles, x fastest) -> its half spectrum in slot `s`
+    int forward_real(const double* phi, int s, int m) {
+        const size_t mo = ctx->moff(m);
         RowArgs<T> r{};
         r.in = phi;
-        r.out = ctx->bufA(0);
+        r.out = ctx->bufA(0) + mo;
         r.tw = (const C*)ctx->tw();
         r.tws = ctx->lay.ntab / ctx->sz.nx;
         r.nrows = ctx->sz.ny * ctx->sz.nz;
@@ -569,20 +689,21 @@ struct Pipe {
         CK(Kern<T>::r2c_rows(ctx->sz.nx, r, ctx->sh.r2c, ctx->stream));
         PassArgs<T> p{};
         p.tw = (const C*)ctx->tw();
+        p.fs = 0;
         if (ctx->sz.dim == 3) {
             // [X][Z][Y] -> transform y -> [X][Y][Z]
-            p.in[0] = (const C*)ctx->bufA(0);
-            p.out[0] = (C*)ctx->bufB(0);
+            p.in[0] = (const C*)(ctx->bufA(0) + mo);
+            p.out[0] = (C*)(ctx->bufB(0) + mo);
             p.tws = ctx->lay.ntab / ctx->sz.ny;
             p.nlines = ctx->sz.nxh * ctx->sz.nz;
             p.B = ctx->sz.nz;
             p.G = ctx->sh.swapInit.G;
             CK(Kern<T>::pass(ctx->sz.ny, -1, OUT_SWAP, 1, p, ctx->sh.swapInit, ctx->stream));
-            p.in[0] = (const C*)ctx->bufB(0);
+            p.in[0] = (const C*)(ctx->bufB(0) + mo);
         } else {
-            p.in[0] = (const C*)ctx->bufA(0);
+            p.in[0] = (const C*)(ctx->bufA(0) + mo);
         }
-        p.out[0] = (C*)ctx->slot(s);
+        p.out[0] = (C*)(ctx->slot(s) + mo);
         p.tws = ctx->lay.ntab / ctx->nl();
         p.nlines = ctx->nlines();
         p.B = ctx->lineB();
@@ -591,28 +712,30 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    // half spectrum of the newest state -> real field
-    int inverse_real(void* out, bool out_fp32) {
+    // half spectrum of member m's newest state -> real field
+    int inverse_real(int m, void* out, bool out_fp32) {
+        const size_t mo = ctx->moff(m);
         PassArgs<T> p{};
         p.tw = (const C*)ctx->tw();
-        p.in[0] = (const C*)ctx->slot(ctx->slotX);
-        p.out[0] = (C*)ctx->bufA(0);
+        p.fs = 0;
+        p.in[0] = (const C*)(ctx->slot(ctx->slotX) + mo);
+        p.out[0] = (C*)(ctx->bufA(0) + mo);
         p.tws = ctx->lay.ntab / ctx->nl();
         p.nlines = ctx->nlines();
         p.B = ctx->lineB();
         p.G = ctx->sh.rot.G;
         CK(Kern<T>::pass(ctx->nl(), +1, OUT_ROTATE, 1, p, ctx->sh.rot, ctx->stream));
-        const char* rows = ctx->bufA(0);
+        const char* rows = ctx->bufA(0) + mo;
         if (ctx->sz.dim == 3) {
             // [Z][X][Y] -> transform y -> [Z][Y][X]
-            p.in[0] = (const C*)ctx->bufA(0);
-            p.out[0] = (C*)ctx->bufB(0);
+            p.in[0] = (const C*)(ctx->bufA(0) + mo);
+            p.out[0] = (C*)(ctx->bufB(0) + mo);
             p.tws = ctx->lay.ntab / ctx->sz.ny;
             p.nlines = ctx->sz.nz * ctx->sz.nxh;
             p.B = ctx->sz.nxh;
             p.G = ctx->sh.swapGet.G;
             CK(Kern<T>::pass(ctx->sz.ny, +1, OUT_SWAP, 1, p, ctx->sh.swapGet, ctx->stream));
-            rows = ctx->bufB(0);
+            rows = ctx->bufB(0) + mo;
         }
         RowArgs<T> r{};
         r.in = rows;
@@ -621,12 +744,13 @@ struct Pipe {
         r.tws = ctx->lay.ntab / ctx->sz.nx;
         r.nrows = ctx->sz.ny * ctx->sz.nz;
         r.G = ctx->sh.c2r.G;
-        r.scale = ctx->geo.inv_npts;
+        r.scale = ctx->geos[m].inv_npts;
         CK(Kern<T>::c2r_rows(ctx->sz.nx, out_fp32, r, ctx->sh.c2r, ctx->stream));
         return SPFC_OK;
     }
 
-    int write_twiddles() {
+    // twiddle table and the members' geometry
+    int write_tables() {
         const int n = ctx->lay.ntab;
         std::vector<C> h(n);
         for (int j = 0; j < n; ++j) {
@@ -634,6 +758,8 @@ struct Pipe {
             h[j] = mk<T>(T(cosl(ang)), T(sinl(ang)));
         }
         CK(hipMemcpyAsync(ctx->tw(), h.data(), n * sizeof(C), hipMemcpyHostToDevice, ctx->stream));
+        CK(hipMemcpyAsync(ctx->ws + ctx->lay.off_geo, ctx->geos.data(), ctx->M * sizeof(Geo), hipMemcpyHostToDevice,
+                          ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         return SPFC_OK;
     }
@@ -649,28 +775,206 @@ int with_pipe(spfc_ctx* ctx, F&& f) {
     return f(p);
 }
 
-Geo make_geo(const spfc_grid& g, const spfc_params& prm) {
-    Geo geo{};
-    geo.dim = g.dim;
-    geo.nx = g.n[0];
-    geo.ny = g.n[1];
-    geo.nz = g.dim == 3 ? g.n[2] : 1;
-    geo.nxh = geo.nx / 2 + 1;
-    const double twopi = 6.283185307179586476925286766559;
-    geo.k0x = twopi / g.L[0];
-    geo.k0y = twopi / g.L[1];
-    geo.k0z = g.dim == 3 ? twopi / g.L[2] : 0.0;
-    geo.a = 1.0 - prm.epsilon;
-    geo.c4 = prm.c4;
-    const double npts = (double)geo.nx * geo.ny * geo.nz;
-    geo.inv_npts = 1.0 / npts;
-    double vol = g.L[0] * g.L[1] * (g.dim == 3 ? g.L[2] : 1.0);
-    geo.volume = vol;
-    geo.cell = vol / npts;
-    geo.pscale = vol / (npts * npts);
-    geo.e1_const = (1.0 + 1.0 / prm.c4) * vol;
-    return geo;
+// host copy of a device field; SPFC_E_INVAL if any value is not finite
+int check_finite_field(const double* dev, size_t n, hipStream_t stream) {
+    std::vector<double> host(n);
+    if (hipMemcpyAsync(host.data(), dev, n * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return SPFC_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return SPFC_E_DEVICE;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) return SPFC_E_INVAL;
+    return SPFC_OK;
 }
+
+size_t class_bytes(const spfc_grid& g, const spfc_params& p, int M) {
+    const Sizes s = sizes_of(g, p.precision);
+    return layout_of(s, shapes_of(s, M), p.history, M).total;
+}
+
+// Context over workspace `ws` for members idx[0..M) of (grids, params, phi0): same
+// sizes and precision.  Transforms the initial fields and computes r^0.
+int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, int M, const double* const* phi0,
+             char* ws, hipStream_t stream, spfc_ctx** out) {
+    const spfc_params& p0 = params[idx[0]];
+    spfc_ctx* ctx = new (std::nothrow) spfc_ctx();
+    if (!ctx) return SPFC_E_NOMEM;
+    ctx->prm = p0;
+    ctx->M = M;
+    for (int m = 0; m < M; ++m) ctx->geos.push_back(make_geo(grids[idx[m]], params[idx[m]]));
+    ctx->sz = sizes_of(grids[idx[0]], p0.precision);
+    ctx->sh = shapes_of(ctx->sz, M);
+    ctx->lay = layout_of(ctx->sz, ctx->sh, p0.history, M);
+    ctx->stream = stream;
+    ctx->ws = ws;
+    ctx->slotX = ctx->slotY = 0;
+    ctx->step = 0;
+    ctx->dt_prev = 0.0;
+    ctx->started = false;
+    ctx->broken = false;
+    ctx->energy_tol = p0.energy_tol > 0 ? p0.energy_tol : (p0.precision == SPFC_FP32 ? 1e-6 : 1e-12);
+    ctx->cur_sc = 0;
+    {
+        // closing each step inside the next update kernel makes every workgroup of
+        // that kernel read its member's partial sums: worth it while that re-read is small
+        const Shapes& h = ctx->sh;
+        const double reread = (double)M * std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
+        ctx->fin_in = tune_plan().fin_in_kernel != 0 && reread <= 48.0e6;
+    }
+    ctx->use_graph = false;
+    ctx->profiling = false;
+    for (int i = 0; i < R_COUNT; ++i) {
+        ctx->role_ms[i] = 0;
+        ctx->role_n[i] = 0;
+    }
+    const Layout& lay = ctx->lay;
+    int rc = SPFC_OK;
+    // scalar blocks (step_x = 0, flags clear) and history start at zero
+    if (hipMemsetAsync(ws + lay.off_sc, 0, lay.total - lay.off_sc, stream) != hipSuccess) rc = SPFC_E_DEVICE;
+    if (!rc)
+        rc = with_pipe(ctx, [&](auto& p) {
+            int r;
+            if ((r = p.write_tables())) return r;
+            for (int m = 0; m < M; ++m)
+                if ((r = p.forward_real(phi0[idx[m]], 0, m))) return r;
+            // r^0 = sqrt(E_1(phi^0)) (after eq. scheme-SAV-initial-1)
+            return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
+        });
+    if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = SPFC_E_DEVICE;
+    if (rc) {
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return SPFC_OK;
+}
+
+void free_ctx(spfc_ctx* ctx) {
+    if (!ctx->broken) (void)hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+    for (auto& u : ctx->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int ctx_step(spfc_ctx* ctx, double dt, int64_t n) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (n == 0) return SPFC_OK;
+    return with_pipe(ctx, [&](auto& p) { return p.steps(dt, n); });
+}
+
+int ctx_status(spfc_ctx* ctx, int m, uint32_t* flags) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    unsigned int f = 0;
+    CK(hipMemcpyAsync(&f, &ctx->sc(m)->flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    *flags = f;
+    return SPFC_OK;
+}
+
+int ctx_mass(spfc_ctx* ctx, int m, double* mean) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    const char* src = ctx->slot(ctx->slotX) + ctx->moff(m);
+    double re = 0.0;
+    if (ctx->prm.precision == SPFC_FP32) {
+        float v[2];
+        CK(hipMemcpyAsync(v, src, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        re = v[0];
+    } else {
+        double v[2];
+        CK(hipMemcpyAsync(v, src, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        re = v[0];
+    }
+    *mean = re * ctx->geos[m].inv_npts;
+    return SPFC_OK;
+}
+
+// the query pass covers every member of the context; member m's values are read back
+int ctx_energy(spfc_ctx* ctx, int m, spfc_energy_t* out) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    int rc = with_pipe(ctx, [&](auto& p) {
+        return p.e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FIN_QUERY);
+    });
+    if (rc) return rc;
+    DevScalars sc;
+    CK(hipMemcpyAsync(&sc, ctx->sc(m), sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    const Geo& g = ctx->geos[m];
+    const double rn = sc.r_n, rm = sc.r_nm1;
+    out->modified_energy = 0.25 * (sc.q_norm[0] + sc.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm));
+    out->E1 = sc.q_E1;
+    out->energy = sc.q_E1 - g.e1_const + 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3];
+    out->sav_energy = 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3] + rn * rn;
+    out->r = rn;
+    out->mean = sc.mean;
+    out->step = ctx->step;
+    return (sc.flags & SPFC_FLAG_NONFINITE) ? SPFC_E_NONFINITE : SPFC_OK;
+}
+
+int ctx_history(spfc_ctx* ctx, int m, int64_t first, int64_t count, spfc_record* out) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (count == 0) return SPFC_OK;
+    const int64_t cap = ctx->prm.history;
+    const int64_t last = first + count - 1;
+    if (last > ctx->step || first < ctx->step + 1 - cap) return SPFC_E_STATE;
+    static_assert(sizeof(Record) == sizeof(spfc_record), "record layout");
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int64_t i = first; i <= last;) {
+        const int64_t s = i % cap;
+        const int64_t run = std::min<int64_t>(last - i + 1, cap - s);
+        CK(hipMemcpy(out + (i - first), ctx->hist(m) + s, run * sizeof(Record), hipMemcpyDeviceToHost));
+        i += run;
+    }
+    return SPFC_OK;
+}
+
+int ctx_get_phi(spfc_ctx* ctx, int m, void* out_dev, int dtype) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    return with_pipe(ctx, [&](auto& p) { return p.inverse_real(m, out_dev, dtype == SPFC_FP32); });
+}
+
+// members grouped by (dim, n, precision), classes in order of first appearance
+std::vector<std::vector<int>> group_members(int count, const spfc_grid* grids, const spfc_params* params) {
+    std::map<std::tuple<int, int, int, int, int>, int> cls;
+    std::vector<std::vector<int>> out;
+    for (int i = 0; i < count; ++i) {
+        const auto key = std::make_tuple(grids[i].dim, grids[i].n[0], grids[i].n[1],
+                                         grids[i].dim == 3 ? grids[i].n[2] : 1, params[i].precision);
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            cls.emplace(key, (int)out.size());
+            out.push_back({i});
+        } else {
+            out[it->second].push_back(i);
+        }
+    }
+    return out;
+}
+
+int validate_batch(int count, const spfc_grid* grids, const spfc_params* params) {
+    if (count < 1 || !grids || !params) return SPFC_E_INVAL;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate(&grids[i], &params[i]);
+        if (rc) return rc;
+        if (params[i].startup != params[0].startup || params[i].history != params[0].history ||
+            params[i].energy_tol != params[0].energy_tol)
+            return SPFC_E_INVAL;
+    }
+    return SPFC_OK;
+}
+
+size_t batch_bytes(const std::vector<std::vector<int>>& classes, const spfc_grid* grids,
+                   const spfc_params* params) {
+    size_t total = 0;
+    for (const auto& c : classes) total += class_bytes(grids[c[0]], params[c[0]], (int)c.size());
+    return total;
+}
+
+bool member_ok(const spfc_batch* b, int member) { return b && member >= 0 && member < (int)b->where.size(); }
 
 }  // namespace
 
@@ -692,11 +996,9 @@ const char* spfc_strerror(int status) {
 
 int spfc_workspace_bytes(const spfc_grid* grid, const spfc_params* params, size_t* bytes) {
     if (!bytes) return SPFC_E_INVAL;
-    int rc = validate(grid, params);
+    const int rc = validate(grid, params);
     if (rc) return rc;
-    Sizes s = sizes_of(*grid, params->precision);
-    Shapes h = shapes_of(s);
-    *bytes = layout_of(s, h, params->history).total;
+    *bytes = class_bytes(*grid, *params, 1);
     return SPFC_OK;
 }
 
@@ -706,78 +1008,25 @@ int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* ph
     int rc = validate(grid, params);
     if (rc) return rc;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) return SPFC_E_INVAL;
-    Sizes s = sizes_of(*grid, params->precision);
-    Shapes h = shapes_of(s);
-    Layout lay = layout_of(s, h, params->history);
-    if (workspace_bytes < lay.total) return SPFC_E_NOMEM;
-
+    if (workspace_bytes < class_bytes(*grid, *params, 1)) return SPFC_E_NOMEM;
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    // reject non-finite initial data (host copy of phi0)
-    const size_t npts = (size_t)s.nx * s.ny * s.nz;
-    {
-        std::vector<double> host(npts);
-        if (hipMemcpyAsync(host.data(), phi0_dev, npts * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
-            return SPFC_E_DEVICE;
-        if (hipStreamSynchronize(stream) != hipSuccess) return SPFC_E_DEVICE;
-        for (size_t i = 0; i < npts; ++i)
-            if (!std::isfinite(host[i])) return SPFC_E_INVAL;
-    }
-
-    spfc_ctx* ctx = new (std::nothrow) spfc_ctx();
-    if (!ctx) return SPFC_E_NOMEM;
-    ctx->grid = *grid;
-    ctx->prm = *params;
-    ctx->sz = s;
-    ctx->sh = h;
-    ctx->lay = lay;
-    ctx->geo = make_geo(*grid, *params);
-    ctx->stream = stream;
-    ctx->ws = reinterpret_cast<char*>(workspace_dev);
-    ctx->slotX = 0;
-    ctx->slotY = 0;
-    ctx->step = 0;
-    ctx->dt_prev = 0.0;
-    ctx->started = false;
-    ctx->broken = false;
-    ctx->energy_tol = params->energy_tol > 0 ? params->energy_tol : (params->precision == SPFC_FP32 ? 1e-6 : 1e-12);
-    ctx->profiling = false;
-    ctx->cur_sc = 0;
-    {
-        // closing each step inside the next update kernel makes every workgroup of
-        // that kernel read all partial sums: worth it while that re-read stays small
-        const double reread = (double)std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
-        ctx->fin_in = tune_plan().fin_in_kernel != 0 && reread <= 48.0e6;
-    }
-    for (int i = 0; i < R_COUNT; ++i) {
-        ctx->role_ms[i] = 0;
-        ctx->role_n[i] = 0;
-    }
-
-    auto fail = [&](int code) {
-        delete ctx;
-        return code;
-    };
-    if (hipMemsetAsync(ctx->ws + lay.off_sc, 0, lay.total - lay.off_sc, stream) != hipSuccess)
-        return fail(SPFC_E_DEVICE);
-    rc = with_pipe(ctx, [&](auto& p) {
-        int r;
-        if ((r = p.write_twiddles())) return r;
-        if ((r = p.forward_real(phi0_dev, 0))) return r;
-        // r^0 = sqrt(E_1(phi^0)) (after eq. scheme-SAV-initial-1)
-        return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
-    });
-    if (rc) return fail(rc);
-    if (hipStreamSynchronize(stream) != hipSuccess) return fail(SPFC_E_DEVICE);
-    *out = ctx;
-    return SPFC_OK;
+    const Sizes s = sizes_of(*grid, params->precision);
+    if ((rc = check_finite_field(phi0_dev, (size_t)s.nx * s.ny * s.nz, stream))) return rc;
+    const int idx = 0;
+    return make_ctx(grid, params, &idx, 1, &phi0_dev, reinterpret_cast<char*>(workspace_dev), stream, out);
 }
 
 int spfc_step(spfc_ctx* ctx, double dt, int64_t n) {
     if (!ctx) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
-    if (n == 0) return SPFC_OK;
-    return with_pipe(ctx, [&](auto& p) { return p.steps(dt, n); });
+    return ctx_step(ctx, dt, n);
+}
+
+int spfc_set_graph(spfc_ctx* ctx, int enable) {
+    if (!ctx) return SPFC_E_INVAL;
+    ctx->use_graph = enable != 0;
+    if (!ctx->use_graph) drop_graph(ctx);
+    return SPFC_OK;
 }
 
 int spfc_step_count(spfc_ctx* ctx, int64_t* n) {
@@ -788,77 +1037,27 @@ int spfc_step_count(spfc_ctx* ctx, int64_t* n) {
 
 int spfc_status(spfc_ctx* ctx, uint32_t* flags) {
     if (!ctx || !flags) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
-    unsigned int f = 0;
-    CK(hipMemcpyAsync(&f, &ctx->sc()->flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
-    CK(hipStreamSynchronize(ctx->stream));
-    *flags = f;
-    return SPFC_OK;
+    return ctx_status(ctx, 0, flags);
 }
 
 int spfc_mass(spfc_ctx* ctx, double* mean) {
     if (!ctx || !mean) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
-    double re = 0.0;
-    if (ctx->prm.precision == SPFC_FP32) {
-        float v[2];
-        CK(hipMemcpyAsync(v, ctx->slot(ctx->slotX), sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
-        CK(hipStreamSynchronize(ctx->stream));
-        re = v[0];
-    } else {
-        double v[2];
-        CK(hipMemcpyAsync(v, ctx->slot(ctx->slotX), sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
-        CK(hipStreamSynchronize(ctx->stream));
-        re = v[0];
-    }
-    *mean = re * ctx->geo.inv_npts;
-    return SPFC_OK;
+    return ctx_mass(ctx, 0, mean);
 }
 
 int spfc_energy(spfc_ctx* ctx, spfc_energy_t* out) {
     if (!ctx || !out) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
-    int rc = with_pipe(ctx, [&](auto& p) {
-        return p.e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FIN_QUERY);
-    });
-    if (rc) return rc;
-    DevScalars sc;
-    CK(hipMemcpyAsync(&sc, ctx->sc(), sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
-    CK(hipStreamSynchronize(ctx->stream));
-    const Geo& g = ctx->geo;
-    const double rn = sc.r_n, rm = sc.r_nm1;
-    out->modified_energy = 0.25 * (sc.q_norm[0] + sc.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm));
-    out->E1 = sc.q_E1;
-    out->energy = sc.q_E1 - g.e1_const + 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3];
-    out->sav_energy = 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3] + rn * rn;
-    out->r = rn;
-    out->mean = sc.mean;
-    out->step = ctx->step;
-    return (sc.flags & SPFC_FLAG_NONFINITE) ? SPFC_E_NONFINITE : SPFC_OK;
+    return ctx_energy(ctx, 0, out);
 }
 
 int spfc_history(spfc_ctx* ctx, int64_t first, int64_t count, spfc_record* out) {
     if (!ctx || (!out && count > 0) || first < 0 || count < 0) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
-    if (count == 0) return SPFC_OK;
-    const int64_t cap = ctx->prm.history;
-    const int64_t last = first + count - 1;
-    if (last > ctx->step || first < ctx->step + 1 - cap) return SPFC_E_STATE;
-    static_assert(sizeof(Record) == sizeof(spfc_record), "record layout");
-    CK(hipStreamSynchronize(ctx->stream));
-    for (int64_t i = first; i <= last;) {
-        const int64_t s = i % cap;
-        const int64_t run = std::min<int64_t>(last - i + 1, cap - s);
-        CK(hipMemcpy(out + (i - first), ctx->hist() + s, run * sizeof(Record), hipMemcpyDeviceToHost));
-        i += run;
-    }
-    return SPFC_OK;
+    return ctx_history(ctx, 0, first, count, out);
 }
 
 int spfc_get_phi(spfc_ctx* ctx, void* out_dev, int dtype) {
     if (!ctx || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
-    if (ctx->broken) return SPFC_E_DEVICE;
-    return with_pipe(ctx, [&](auto& p) { return p.inverse_real(out_dev, dtype == SPFC_FP32); });
+    return ctx_get_phi(ctx, 0, out_dev, dtype);
 }
 
 int spfc_state_bytes(spfc_ctx* ctx, size_t* bytes) {
@@ -909,6 +1108,7 @@ int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes) {
     if (hd.magic != kMagic || hd.prec != ctx->prm.precision || hd.dim != ctx->sz.dim || hd.n[0] != ctx->sz.nx ||
         hd.n[1] != ctx->sz.ny || hd.n[2] != ctx->sz.nz)
         return SPFC_E_STATE;
+    drop_graph(ctx);
     const size_t off = align_up(sizeof(CkptHeader));
     CK(hipMemcpyAsync(ctx->slot(0), in + off, ctx->lay.F, hipMemcpyDeviceToDevice, ctx->stream));
     if (!hd.slot_same)
@@ -927,7 +1127,7 @@ int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes) {
 
 int spfc_profile(spfc_ctx* ctx, int enable) {
     if (!ctx) return SPFC_E_INVAL;
-    int rc = drain_events(ctx);
+    const int rc = drain_events(ctx);
     if (rc) return rc;
     ctx->profiling = enable != 0;
     if (enable) {
@@ -942,9 +1142,9 @@ int spfc_profile(spfc_ctx* ctx, int enable) {
 int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms, int64_t* launches,
                       double* bytes_per_launch, int* count) {
     if (!ctx || !count) return SPFC_E_INVAL;
-    int rc = drain_events(ctx);
+    const int rc = drain_events(ctx);
     if (rc) return rc;
-    const double F = (double)ctx->lay.F;
+    const double F = (double)ctx->lay.F * ctx->M;
     const int d = ctx->sz.dim;
     const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F, 0.0};
     int k = 0;
@@ -964,13 +1164,107 @@ int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms
 
 int spfc_destroy(spfc_ctx* ctx) {
     if (!ctx) return SPFC_E_INVAL;
-    if (!ctx->broken) (void)hipStreamSynchronize(ctx->stream);
-    for (auto& u : ctx->ev_used) {
-        (void)hipEventDestroy(u.second.first);
-        (void)hipEventDestroy(u.second.second);
+    free_ctx(ctx);
+    return SPFC_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+int spfc_batch_workspace_bytes(int count, const spfc_grid* grids, const spfc_params* params, size_t* bytes) {
+    if (!bytes) return SPFC_E_INVAL;
+    const int rc = validate_batch(count, grids, params);
+    if (rc) return rc;
+    *bytes = batch_bytes(group_members(count, grids, params), grids, params);
+    return SPFC_OK;
+}
+
+int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params, const double* const* phi0_dev,
+                    void* workspace_dev, size_t workspace_bytes, void* hip_stream, spfc_batch** out) {
+    if (!out || !phi0_dev || !workspace_dev) return SPFC_E_INVAL;
+    int rc = validate_batch(count, grids, params);
+    if (rc) return rc;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) return SPFC_E_INVAL;
+    const auto classes = group_members(count, grids, params);
+    if (workspace_bytes < batch_bytes(classes, grids, params)) return SPFC_E_NOMEM;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < count; ++i) {
+        if (!phi0_dev[i]) return SPFC_E_INVAL;
+        const Sizes s = sizes_of(grids[i], params[i].precision);
+        if ((rc = check_finite_field(phi0_dev[i], (size_t)s.nx * s.ny * s.nz, stream))) return rc;
     }
-    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
-    delete ctx;
+    spfc_batch* b = new (std::nothrow) spfc_batch();
+    if (!b) return SPFC_E_NOMEM;
+    b->where.assign(count, {0, 0});
+    char* ws = reinterpret_cast<char*>(workspace_dev);
+    for (size_t c = 0; c < classes.size(); ++c) {
+        const auto& idx = classes[c];
+        const int M = (int)idx.size();
+        spfc_ctx* ctx = nullptr;
+        rc = make_ctx(grids, params, idx.data(), M, phi0_dev, ws, stream, &ctx);
+        if (rc) {
+            for (auto* x : b->cls) free_ctx(x);
+            delete b;
+            return rc;
+        }
+        ws += class_bytes(grids[idx[0]], params[idx[0]], M);
+        for (int k = 0; k < M; ++k) b->where[idx[k]] = {(int)c, k};
+        b->cls.push_back(ctx);
+    }
+    *out = b;
+    return SPFC_OK;
+}
+
+int spfc_batch_set_graph(spfc_batch* b, int enable) {
+    if (!b) return SPFC_E_INVAL;
+    for (auto* c : b->cls) spfc_set_graph(c, enable);
+    return SPFC_OK;
+}
+
+int spfc_batch_step(spfc_batch* b, double dt, int64_t n) {
+    if (!b) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
+    for (auto* c : b->cls) {
+        const int rc = ctx_step(c, dt, n);
+        if (rc) return rc;
+    }
+    return SPFC_OK;
+}
+
+int spfc_batch_step_count(spfc_batch* b, int64_t* n) {
+    if (!b || !n) return SPFC_E_INVAL;
+    *n = b->cls[0]->step;
+    return SPFC_OK;
+}
+
+int spfc_batch_status(spfc_batch* b, int member, uint32_t* flags) {
+    if (!member_ok(b, member) || !flags) return SPFC_E_INVAL;
+    return ctx_status(b->cls[b->where[member].first], b->where[member].second, flags);
+}
+
+int spfc_batch_mass(spfc_batch* b, int member, double* mean) {
+    if (!member_ok(b, member) || !mean) return SPFC_E_INVAL;
+    return ctx_mass(b->cls[b->where[member].first], b->where[member].second, mean);
+}
+
+int spfc_batch_energy(spfc_batch* b, int member, spfc_energy_t* out) {
+    if (!member_ok(b, member) || !out) return SPFC_E_INVAL;
+    return ctx_energy(b->cls[b->where[member].first], b->where[member].second, out);
+}
+
+int spfc_batch_history(spfc_batch* b, int member, int64_t first, int64_t count, spfc_record* out) {
+    if (!member_ok(b, member) || (!out && count > 0) || first < 0 || count < 0) return SPFC_E_INVAL;
+    return ctx_history(b->cls[b->where[member].first], b->where[member].second, first, count, out);
+}
+
+int spfc_batch_get_phi(spfc_batch* b, int member, void* out_dev, int dtype) {
+    if (!member_ok(b, member) || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
+    return ctx_get_phi(b->cls[b->where[member].first], b->where[member].second, out_dev, dtype);
+}
+
+int spfc_batch_destroy(spfc_batch* b) {
+    if (!b) return SPFC_E_INVAL;
+    for (auto* c : b->cls) free_ctx(c);
+    delete b;
     return SPFC_OK;
 }
 

@@ -80,6 +80,48 @@ def test_init_rejects_null_pointers_without_touching_the_device():
         assert B.strerror(code)
 
 
+def test_batch_workspace_and_validation():
+    """Batch sizing: one class per (grid sizes, precision); a class of M members needs
+    M times the per-member fields plus one twiddle table; shared run settings only."""
+    B = _lib()
+    g = B.make_grid((256, 256), (64 * np.pi,) * 2)
+    g2 = B.make_grid((256, 256), (70.0, 60.0))
+    g3 = B.make_grid((128, 128), (32 * np.pi,) * 2)
+    p = B.make_params(0.25, history=64)
+    q = B.make_params(0.4, history=64)
+    one = B.spfc_workspace_bytes(g, p)
+    four = B.spfc_batch_workspace_bytes([g, g2, g, g2], [p, q, q, p])
+    F = 129 * 256 * 16
+    assert 4 * 9 * F <= four < 4 * one
+    assert B.spfc_batch_workspace_bytes([g], [p]) == one
+    mixed = B.spfc_batch_workspace_bytes([g, g3, g], [p, p, q])
+    assert mixed == B.spfc_batch_workspace_bytes([g, g], [p, q]) + B.spfc_workspace_bytes(g3, p)
+    # the fp32 members of the same size are a class of their own
+    p32 = B.make_params(0.25, precision="fp32", history=64)
+    assert B.spfc_batch_workspace_bytes([g, g], [p, p32]) == one + B.spfc_workspace_bytes(g, p32)
+    for grids, params in [([g, g], [p, B.make_params(0.25, startup="ghost", history=64)]),
+                          ([g, g], [p, B.make_params(0.25, history=65)]),
+                          ([g, B.make_grid((100, 64), (1, 1))], [p, p]),
+                          ([g], [B.make_params(1.5, history=64)])]:
+        with pytest.raises(B.SpfcError) as ei:
+            B.spfc_batch_workspace_bytes(grids, params)
+        assert ei.value.status == B.SPFC_E_INVAL
+    lib = B.load_library()
+    out = ctypes.c_size_t()
+    assert lib.spfc_batch_workspace_bytes(0, None, None, ctypes.byref(out)) == B.SPFC_E_INVAL
+    bh = ctypes.c_void_p()
+    ga, pa = B._arrays([g, g], [p, p])
+    assert lib.spfc_batch_init(2, ga, pa, None, 256, 1 << 30, None, ctypes.byref(bh)) == B.SPFC_E_INVAL
+    ptrs = (ctypes.c_void_p * 2)(256, 512)
+    assert lib.spfc_batch_init(2, ga, pa, ptrs, 257, 1 << 30, None, ctypes.byref(bh)) == B.SPFC_E_INVAL
+    assert lib.spfc_batch_init(2, ga, pa, ptrs, 256, 1024, None, ctypes.byref(bh)) == B.SPFC_E_NOMEM
+    assert lib.spfc_batch_step(None, 0.01, 1) == B.SPFC_E_INVAL
+    assert lib.spfc_batch_destroy(None) == B.SPFC_E_INVAL
+    assert lib.spfc_set_graph(None, 1) == B.SPFC_E_INVAL
+    rec = (B.spfc_record * 1)()
+    assert lib.spfc_batch_history(None, 0, 0, 1, rec) == B.SPFC_E_INVAL
+
+
 # ----------------------------------------------------------------- line FFT schedule on the host
 
 def _emu():

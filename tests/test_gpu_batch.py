@@ -1,0 +1,170 @@
+"""Batches of independent runs and graph replay, through the C ABI.
+
+A batch member runs the same kernels with the same reduction order as a single run
+of its own grid and parameters, so its field and records must equal the single
+run's bit for bit (where the end-of-call update uses the same workgroup count,
+i.e. small grids; otherwise the records of the state a call ends on differ by the
+summation order only).  Graph replay launches exactly what direct launches would,
+so it must reproduce them bit for bit over several calls, with synchronizing
+queries between the replays.  One member is also checked against the oracle.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spfc_oracle as O
+from paper_2012_15133_amd.inputs import noise_ic
+
+pytestmark = pytest.mark.gpu
+
+
+def _members(specs):
+    out = []
+    for n, L, eps, mean, seed, prec in specs:
+        out.append({"n": n, "L": L, "epsilon": eps, "precision": prec,
+                    "phi0": noise_ic(tuple(reversed(n)), mean, seed)})
+    return out
+
+
+SPECS = [
+    ((64, 64), (8 * math.pi,) * 2, 0.25, -0.2, 1, "fp64"),
+    ((64, 64), (9.0 * math.pi, 7.5 * math.pi), 0.1, -0.3, 2, "fp64"),
+    ((32, 32), (4 * math.pi,) * 2, 0.4, -0.1, 3, "fp64"),
+    ((64, 64), (8 * math.pi,) * 2, 0.3, 0.0, 4, "fp32"),
+    ((64, 64), (6 * math.pi,) * 2, 0.05, -0.35, 5, "fp64"),
+    ((16, 16, 16), (4 * math.pi,) * 3, 0.25, -0.25, 6, "fp64"),
+]
+
+
+def _single(m, dt_steps, history, graph=False):
+    from paper_2012_15133_amd import Solver
+    s = Solver(m["n"], m["L"], m["phi0"], m["epsilon"], precision=m["precision"], history=history, graph=graph)
+    for dt, k in dt_steps:
+        s.step(dt, k)
+    n = s.step_count()
+    out = (s.phi().cpu().numpy(), s.history(0, n + 1), s.status())
+    s.close()
+    return out
+
+
+def test_batch_members_equal_single_runs_bitwise():
+    from paper_2012_15133_amd import Batch
+    members = _members(SPECS)
+    plan = [(0.01, 12), (0.01, 9), (0.02, 6)]
+    b = Batch(members, history=64)
+    for dt, k in plan:
+        b.step(dt, k)
+    assert b.step_count() == 27
+    for i, m in enumerate(members):
+        print(f"member {i}: n={m['n']} eps={m['epsilon']} {m['precision']}", flush=True)
+        phi, hist, flags = _single(m, plan, 64)
+        assert np.array_equal(b.phi(i).cpu().numpy(), phi)
+        assert b.history(i, 0, 28) == hist
+        assert b.status(i) == flags
+    b.close()
+
+
+def test_batch_member_matches_oracle():
+    from paper_2012_15133_amd import Batch
+    members = _members(SPECS[:3])
+    b = Batch(members, history=32)
+    b.step(0.01, 20)
+    for i in (1, 2):
+        m = members[i]
+        g = O.Grid(m["n"], m["L"])
+        ref = O.run(g, O.Params(m["epsilon"]), m["phi0"], 0.01, 20)
+        phi = b.phi(i).cpu().numpy()
+        assert np.max(np.abs(phi - ref["phi"])) <= 1e-11 * np.max(np.abs(ref["phi"]))
+        for h, r in zip(b.history(i, 0, 21), ref["records"]):
+            assert abs(h["energy"] - r["energy"]) <= 1e-12 * abs(r["energy"])
+            assert abs(h["mean"] - r["mean"]) <= 1e-14
+        e = b.energy(i)
+        assert abs(e["modified_energy"] - ref["records"][-1]["energy"]) <= 1e-12 * abs(ref["records"][-1]["energy"])
+        assert abs(b.mass(i) - np.mean(m["phi0"])) <= 1e-14
+    b.close()
+
+
+def test_batch_large_members_fields_bitwise():
+    """64 members of 128^2 and 4 of 512^2 in one batch: fields equal the single runs bit
+    for bit; records to summation-order rounding."""
+    from paper_2012_15133_amd import Batch
+    rng = np.random.default_rng(7)
+    specs = []
+    for k in range(64):
+        specs.append(((128, 128), (32 * math.pi,) * 2, float(rng.uniform(0.05, 0.5)),
+                      float(rng.uniform(-0.4, 0.0)), 100 + k, "fp64"))
+    for k in range(4):
+        specs.append(((512, 512), (128 * math.pi,) * 2, 0.25, -0.2, 200 + k, "fp64"))
+    members = _members(specs)
+    b = Batch(members, history=64)
+    b.step(0.01, 30)
+    for i in (0, 37, 63, 64, 67):
+        print(f"member {i}", flush=True)
+        phi, hist, flags = _single(members[i], [(0.01, 30)], 64)
+        assert np.array_equal(b.phi(i).cpu().numpy(), phi)
+        for x, y in zip(b.history(i, 0, 31), hist):
+            for key in x:
+                assert abs(x[key] - y[key]) <= 1e-13 * max(1.0, abs(y[key])), (i, key)
+        assert b.status(i) == flags
+    b.close()
+
+
+def test_batch_member_index_errors():
+    from paper_2012_15133_amd import Batch, SpfcError
+    b = Batch(_members(SPECS[:2]), history=8)
+    with pytest.raises(SpfcError):
+        b.status(2)
+    with pytest.raises(SpfcError):
+        b.history(-1, 0, 1)
+    b.close()
+
+
+# ----------------------------------------------------------------- graph replay
+
+@pytest.mark.parametrize("n,startup", [((64, 64), "sav1"), ((64, 32), "ghost"), ((16, 16, 16), "sav1"),
+                                       ((256, 256), "copy")])
+def test_graph_replay_equals_direct_launches(n, startup):
+    from paper_2012_15133_amd import Solver
+    L = tuple(2 * math.pi * v / 8 for v in n)
+    phi0 = noise_ic(tuple(reversed(n)), -0.2, 9)
+    plan = [(0.01, 1), (0.01, 8), (0.01, 7), (0.02, 11), (0.02, 2), (0.01, 4)]
+    runs = []
+    for graph in (False, True):
+        s = Solver(n, L, phi0, 0.25, startup=startup, history=64, graph=graph)
+        snaps = []
+        for dt, k in plan:
+            s.step(dt, k)
+            # eager work and a synchronization between the replays
+            snaps.append((s.phi().cpu().numpy(), s.energy()["modified_energy"], s.mass()))
+        runs.append((snaps, s.history(0, s.step_count() + 1), s.status()))
+        s.close()
+    (a, ha, fa), (b, hb, fb) = runs
+    for (pa, ea, ma), (pb, eb, mb) in zip(a, b):
+        assert np.array_equal(pa, pb)
+        assert ea == eb and ma == mb
+    assert ha == hb and fa == fb
+
+
+def test_graph_replay_batch_and_checkpoint():
+    from paper_2012_15133_amd import Batch, Solver
+    members = _members(SPECS[:4])
+    b = Batch(members, history=64, graph=True)
+    b.step(0.01, 10)
+    b.step(0.01, 13)
+    for i in (0, 3):
+        phi, hist, _ = _single(members[i], [(0.01, 10), (0.01, 13)], 64)
+        assert np.array_equal(b.phi(i).cpu().numpy(), phi)
+        assert b.history(i, 0, 24) == hist
+    b.close()
+    m = members[1]
+    s = Solver(m["n"], m["L"], m["phi0"], m["epsilon"], history=64, graph=True)
+    s.step(0.01, 10)
+    ck = s.save_state()
+    s.step(0.01, 10)
+    ref = s.phi().cpu().numpy()
+    s.load_state(ck)
+    s.step(0.01, 10)
+    assert np.array_equal(s.phi().cpu().numpy(), ref)
+    s.close()
