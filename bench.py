@@ -80,12 +80,110 @@ def cpu_baseline(workload: str, steps: int):
                       f"{sec:.1f} s wall, numpy single thread"}
 
 
+ENSEMBLES = {
+    # name: (members, sizes, dt, precision)
+    "ensemble64_fp64": (64, (128, 256, 512), 0.01, "fp64"),
+}
+
+
+def run_ensemble(args):
+    """64 independent 2-D runs (n in {128, 256, 512}, h = pi/4, epsilon ~ U[0.05, 0.5),
+    mean ~ U[-0.4, 0)) advanced as one batch, against the same runs one after another
+    on the single-run path (same steps, same call pattern); fields compared bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2012_15133_amd import Batch, Solver
+    from paper_2012_15133_amd.inputs import ensemble_members, noise_ic
+
+    count, sizes, dt, prec = ENSEMBLES[args.workload]
+    specs = ensemble_members(count, sizes)
+    members = [{"n": m["n"], "L": m["L"], "epsilon": m["epsilon"], "precision": prec,
+                "phi0": noise_ic(tuple(reversed(m["n"])), m["mean"], m["seed"])} for m in specs]
+    npts = sum(int(np.prod(m["n"])) for m in members)
+    hist = max(16, args.steps + args.warmup + args.profile_steps + 2)
+    b = Batch(members, history=hist, graph=bool(args.graph))
+    if args.warmup > 0:
+        b.step(dt, args.warmup)
+    plans = None
+    if args.tune:
+        b.tune(dt, trial_steps=args.tune)
+        plans = {str(members[i]["n"][0]): b.plan(i) for i in range(min(count, len(sizes)))}
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    b.step(dt, args.steps)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    flags = [b.status(i) for i in range(count)]
+    fields = [b.phi(i) for i in range(count)]
+    b.profile(True)
+    b.step(dt, args.profile_steps)
+    kt = b.kernel_times()
+    b.profile(False)
+    b.close()
+
+    seq_ms = 0.0
+    equal = 0
+    worst = 0.0
+    if not args.no_seq:
+        for i, m in enumerate(members):
+            s = Solver(m["n"], m["L"], m["phi0"], m["epsilon"], precision=prec, history=16)
+            if args.warmup > 0:
+                s.step(dt, args.warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.step(dt, args.steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            seq_ms += e0.elapsed_time(e1)
+            p = s.phi()
+            equal += int(torch.equal(p, fields[i]))
+            worst = max(worst, float((p - fields[i]).abs().max() / p.abs().max()))
+            s.close()
+
+    dom = max(kt, key=lambda k: k["avg_ms"])
+    achieved = dom["bytes"] / (dom["avg_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "grid-point-steps/s",
+        "value": npts * args.steps / (ms * 1e-3),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "members": count, "sizes": list(sizes), "h": "pi/4", "dt": dt,
+                   "epsilon": "U[0.05,0.5)", "mean": "U[-0.4,0)", "launch": "graph" if args.graph else "direct",
+                   "plans": plans or "default"},
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "kernels": {k["name"]: {"us_per_step": round(k["avg_ms"] * 1e3, 3),
+                                "GBps": round(k["bytes"] / (k["avg_ms"] * 1e-3) / 1e9, 1)} for k in kt},
+        "sticky_flags_or": int(np.bitwise_or.reduce(flags)),
+    }
+    if not args.no_seq:
+        out["sequential"] = {"ms_per_step": seq_ms / args.steps, "speedup": seq_ms / ms,
+                             "bitwise_equal_members": equal, "max_rel_diff": worst}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS) + sorted(ENSEMBLES))
+    ap.add_argument("--no-seq", action="store_true", help="ensembles: skip the one-after-another comparison")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="ensembles: tune the launch plan of each size class with this many trial steps first")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
@@ -109,6 +207,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU (slab/pencil FFT) "
                                    "decomposition is a design, not a build", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload in ENSEMBLES:
+        run_ensemble(args)
+        return
 
     import numpy as np
     import torch

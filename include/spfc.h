@@ -124,7 +124,9 @@ int spfc_workspace_bytes(const spfc_grid* grid, const spfc_params* params, size_
  * 256-byte aligned, owned by the caller.  hip_stream: the hipStream_t every
  * later call enqueues on (0 = null stream).  Computes r^0 = sqrt(E_1(phi^0))
  * (after eq. scheme-SAV-initial-1).  Errors: SPFC_E_INVAL (bad grid/params,
- * null pointer, non-finite phi0), SPFC_E_NOMEM, SPFC_E_DEVICE. */
+ * null pointer, non-finite phi0, or a grid whose line transforms need more LDS
+ * per workgroup than the device has, e.g. 3-D FP64 with n_x = 1024),
+ * SPFC_E_NOMEM, SPFC_E_DEVICE. */
 int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev,
               void* workspace_dev, size_t workspace_bytes, void* hip_stream, spfc_ctx** out);
 
@@ -184,6 +186,23 @@ int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms
  * (default) and frees the graph. */
 int spfc_set_graph(spfc_ctx* ctx, int enable);
 
+/* Launch-plan tuner.  The step kernels run with a plan: for each of them the
+ * values per thread (4, 8 or 16; the radix of the line transforms) and the
+ * workgroup size.  spfc_tune times `trial_steps` steps of size dt > 0 for
+ * candidate plans (a coordinate search over the kernels, 4/8/16 values per thread
+ * x 128/256 threads) and keeps the fastest.  It starts every trial from a
+ * snapshot of the run state (both states, scalars, history ring) that it keeps in
+ * caller device memory scratch_dev of at least spfc_tune_bytes bytes, and
+ * restores that state at the end, so the run continues from where it was; the
+ * plan only changes the rounding of the transforms.  Synchronizes.  Errors:
+ * SPFC_E_INVAL, SPFC_E_NOMEM (scratch too small), SPFC_E_DEVICE.
+ * spfc_get_plan writes 8 ints: (values per thread, threads per workgroup) of the
+ * gradient/inverse, real-space, forward and (3-D) middle-axis kernels, 0 where
+ * unused. */
+int spfc_tune_bytes(spfc_ctx* ctx, size_t* bytes);
+int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes);
+int spfc_get_plan(spfc_ctx* ctx, int* plan8);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances `count` independent runs ("members") together, e.g. a sweep
  * over epsilon, mean density or box size of Section 5.  Members of the same grid
@@ -218,6 +237,19 @@ int spfc_batch_energy(spfc_batch* b, int member, spfc_energy_t* out);
 int spfc_batch_history(spfc_batch* b, int member, int64_t first, int64_t count,
                        spfc_record* out);
 int spfc_batch_get_phi(spfc_batch* b, int member, void* out_dev, int dtype);
+/* Tune the plan of every class in turn (as spfc_tune; one scratch buffer of
+ * spfc_batch_tune_bytes bytes serves all classes); read the plan of a member's class. */
+int spfc_batch_tune_bytes(spfc_batch* b, size_t* bytes);
+int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch_dev,
+                    size_t scratch_bytes);
+int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8);
+/* Kernel timing as spfc_profile / spfc_kernel_times, summed over the classes: for
+ * each step kernel, avg_ms is the sum over classes of its average launch time
+ * (the time that kernel takes per step for the whole batch), bytes_per_launch the
+ * algorithmic bytes of those launches together, launches the count per class. */
+int spfc_batch_profile(spfc_batch* b, int enable);
+int spfc_batch_kernel_times(spfc_batch* b, int cap, const char** names, double* avg_ms,
+                            int64_t* launches, double* bytes_per_launch, int* count);
 /* Free the host side of the batch.  Does not touch caller memory. */
 int spfc_batch_destroy(spfc_batch* b);
 

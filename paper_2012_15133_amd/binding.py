@@ -26,7 +26,9 @@ EXPORTS = [
     "spfc_status", "spfc_profile", "spfc_kernel_times", "spfc_strerror", "spfc_destroy", "spfc_set_graph",
     "spfc_batch_workspace_bytes", "spfc_batch_init", "spfc_batch_step", "spfc_batch_set_graph",
     "spfc_batch_step_count", "spfc_batch_status", "spfc_batch_mass", "spfc_batch_energy", "spfc_batch_history",
-    "spfc_batch_get_phi", "spfc_batch_destroy",
+    "spfc_batch_get_phi", "spfc_batch_destroy", "spfc_batch_profile", "spfc_batch_kernel_times",
+    "spfc_tune_bytes", "spfc_tune", "spfc_get_plan", "spfc_batch_tune_bytes", "spfc_batch_tune",
+    "spfc_batch_get_plan",
 ]
 
 
@@ -97,6 +99,14 @@ def load_library(path: str | None = None):
         "spfc_batch_history": [vp, i32, i64, i64, P(spfc_record)],
         "spfc_batch_get_phi": [vp, i32, vp, i32],
         "spfc_batch_destroy": [vp],
+        "spfc_batch_profile": [vp, i32],
+        "spfc_tune_bytes": [vp, P(sz)],
+        "spfc_tune": [vp, dbl, i64, vp, sz],
+        "spfc_get_plan": [vp, P(i32)],
+        "spfc_batch_tune_bytes": [vp, P(sz)],
+        "spfc_batch_tune": [vp, dbl, i64, vp, sz],
+        "spfc_batch_get_plan": [vp, i32, P(i32)],
+        "spfc_batch_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -217,16 +227,20 @@ def spfc_profile(ctx, enable: bool):
     _check("spfc_profile", load_library().spfc_profile(ctx, 1 if enable else 0))
 
 
-def spfc_kernel_times(ctx) -> list:
+def _kernel_times(call, handle) -> list:
     cap = 8
     names = (ctypes.c_char_p * cap)()
     avg = (ctypes.c_double * cap)()
     nl = (ctypes.c_int64 * cap)()
     by = (ctypes.c_double * cap)()
     cnt = ctypes.c_int()
-    _check("spfc_kernel_times", load_library().spfc_kernel_times(ctx, cap, names, avg, nl, by, ctypes.byref(cnt)))
+    _check(call, getattr(load_library(), call)(handle, cap, names, avg, nl, by, ctypes.byref(cnt)))
     return [{"name": names[i].decode(), "avg_ms": avg[i], "launches": nl[i], "bytes": by[i]}
             for i in range(min(cnt.value, cap))]
+
+
+def spfc_kernel_times(ctx) -> list:
+    return _kernel_times("spfc_kernel_times", ctx)
 
 
 def spfc_strerror(status: int) -> str:
@@ -310,6 +324,52 @@ def spfc_batch_history(b, member: int, first: int, count: int) -> list:
 
 def spfc_batch_get_phi(b, member: int, out_ptr: int, dtype: int = SPFC_FP64):
     _check("spfc_batch_get_phi", load_library().spfc_batch_get_phi(b, int(member), out_ptr, int(dtype)))
+
+
+def spfc_tune_bytes(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check("spfc_tune_bytes", load_library().spfc_tune_bytes(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def spfc_tune(ctx, dt: float, trial_steps: int, scratch_ptr: int, scratch_bytes: int):
+    _check("spfc_tune", load_library().spfc_tune(ctx, float(dt), int(trial_steps), scratch_ptr, int(scratch_bytes)))
+
+
+def _plan(arr):
+    keys = ("inv", "real", "fwd", "mid")
+    return {k: (arr[2 * i], arr[2 * i + 1]) for i, k in enumerate(keys) if arr[2 * i]}
+
+
+def spfc_get_plan(ctx) -> dict:
+    arr = (ctypes.c_int * 8)()
+    _check("spfc_get_plan", load_library().spfc_get_plan(ctx, arr))
+    return _plan(arr)
+
+
+def spfc_batch_tune_bytes(b) -> int:
+    n = ctypes.c_size_t()
+    _check("spfc_batch_tune_bytes", load_library().spfc_batch_tune_bytes(b, ctypes.byref(n)))
+    return n.value
+
+
+def spfc_batch_tune(b, dt: float, trial_steps: int, scratch_ptr: int, scratch_bytes: int):
+    _check("spfc_batch_tune", load_library().spfc_batch_tune(b, float(dt), int(trial_steps), scratch_ptr,
+                                                             int(scratch_bytes)))
+
+
+def spfc_batch_get_plan(b, member: int) -> dict:
+    arr = (ctypes.c_int * 8)()
+    _check("spfc_batch_get_plan", load_library().spfc_batch_get_plan(b, int(member), arr))
+    return _plan(arr)
+
+
+def spfc_batch_profile(b, enable: bool):
+    _check("spfc_batch_profile", load_library().spfc_batch_profile(b, 1 if enable else 0))
+
+
+def spfc_batch_kernel_times(b) -> list:
+    return _kernel_times("spfc_batch_kernel_times", b)
 
 
 def spfc_batch_destroy(b):
@@ -401,6 +461,17 @@ class Solver:
     def load_state(self, buf):
         spfc_load_state(self.ctx, buf.data_ptr(), buf.numel())
 
+    def tune(self, dt, trial_steps=20):
+        """Choose the fastest launch plan for steps of size dt (the run state is kept)."""
+        nb = spfc_tune_bytes(self.ctx)
+        scratch = self.torch.empty(nb, dtype=self.torch.uint8, device="cuda")
+        spfc_tune(self.ctx, dt, trial_steps, scratch.data_ptr(), nb)
+        del scratch
+        return spfc_get_plan(self.ctx)
+
+    def plan(self):
+        return spfc_get_plan(self.ctx)
+
     def profile(self, enable=True):
         spfc_profile(self.ctx, enable)
 
@@ -475,6 +546,22 @@ class Batch:
         spfc_batch_get_phi(self.b, m, out.data_ptr(), SPFC_FP64 if dtype == "fp64" else SPFC_FP32)
         self.stream.synchronize()
         return out
+
+    def tune(self, dt, trial_steps=20):
+        """Choose the fastest launch plan of every size class (the run state is kept)."""
+        nb = spfc_batch_tune_bytes(self.b)
+        scratch = self.torch.empty(nb, dtype=self.torch.uint8, device="cuda")
+        spfc_batch_tune(self.b, dt, trial_steps, scratch.data_ptr(), nb)
+        del scratch
+
+    def plan(self, m):
+        return spfc_batch_get_plan(self.b, m)
+
+    def profile(self, enable=True):
+        spfc_batch_profile(self.b, enable)
+
+    def kernel_times(self):
+        return spfc_batch_kernel_times(self.b)
 
     def close(self):
         if getattr(self, "b", None) is not None:

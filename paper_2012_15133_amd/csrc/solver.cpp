@@ -96,8 +96,7 @@ Sizes sizes_of(const spfc_grid& g, int prec) {
     return s;
 }
 
-Shapes shapes_of(const Sizes& s, int M) {
-    const TunePlan tp = tune_plan();
+Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
     Shapes h{};
     const int d = s.dim;
     const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
@@ -124,7 +123,12 @@ Shapes shapes_of(const Sizes& s, int M) {
     return h;
 }
 
-Layout layout_of(const Sizes& s, const Shapes& h, int64_t hist_cap, int M) {
+// Partial-sum buffers are sized for any launch plan (one line group per workgroup
+// gives the most workgroups), so that a context can change its plan in place.
+Layout layout_of(const Sizes& s, int64_t hist_cap, int M) {
+    TunePlan widest;
+    widest.inv.T = widest.real.T = widest.fwd.T = widest.mid.T = 1;
+    const Shapes h = shapes_of(s, M, widest);
     Layout L{};
     L.fs = (size_t)s.nxh * s.ny * s.nz;
     L.F = L.fs * s.elem;
@@ -208,6 +212,7 @@ struct spfc_ctx {
     int M;
     std::vector<Geo> geos;  // per member (host copy of the device array)
     Sizes sz;
+    TunePlan plan;
     Shapes sh;
     Layout lay;
     hipStream_t stream;
@@ -316,6 +321,35 @@ struct Timed {
 void drop_graph(spfc_ctx* ctx) {
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
+}
+
+// Dynamic LDS of every launch shape of the plan within the device limit.
+bool plan_fits(const Sizes& sz, int M, const TunePlan& tp, size_t lds_max) {
+    const Shapes h = shapes_of(sz, M, tp);
+    for (const LaunchShape* x : {&h.A, &h.B, &h.Cf, &h.midI, &h.midF, &h.r2c, &h.keep, &h.swapInit, &h.rot,
+                                 &h.swapGet, &h.c2r})
+        if (x->shmem > lds_max) return false;
+    return true;
+}
+
+size_t device_lds_max() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return (size_t)v;
+}
+
+// Launch plan of a context: shapes of the step kernels and whether each step is
+// closed inside the next update kernel.  That makes every workgroup of the update
+// kernel read its member's partial sums: worth it while that re-read is small.
+void set_plan(spfc_ctx* ctx, const TunePlan& tp) {
+    drop_graph(ctx);
+    ctx->plan = tp;
+    ctx->sh = shapes_of(ctx->sz, ctx->M, tp);
+    const Shapes& h = ctx->sh;
+    const double reread = (double)ctx->M * std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
+    ctx->fin_in = tp.fin_in_kernel != 0 && reread <= 48.0e6;
 }
 
 // ---------------------------------------------------------------- pipeline (one precision)
@@ -788,7 +822,7 @@ int check_finite_field(const double* dev, size_t n, hipStream_t stream) {
 
 size_t class_bytes(const spfc_grid& g, const spfc_params& p, int M) {
     const Sizes s = sizes_of(g, p.precision);
-    return layout_of(s, shapes_of(s, M), p.history, M).total;
+    return layout_of(s, p.history, M).total;
 }
 
 // Context over workspace `ws` for members idx[0..M) of (grids, params, phi0): same
@@ -802,8 +836,13 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     ctx->M = M;
     for (int m = 0; m < M; ++m) ctx->geos.push_back(make_geo(grids[idx[m]], params[idx[m]]));
     ctx->sz = sizes_of(grids[idx[0]], p0.precision);
-    ctx->sh = shapes_of(ctx->sz, M);
-    ctx->lay = layout_of(ctx->sz, ctx->sh, p0.history, M);
+    ctx->plan = tune_plan();
+    if (!plan_fits(ctx->sz, M, ctx->plan, device_lds_max())) {
+        delete ctx;
+        return SPFC_E_INVAL;
+    }
+    ctx->sh = shapes_of(ctx->sz, M, ctx->plan);
+    ctx->lay = layout_of(ctx->sz, p0.history, M);
     ctx->stream = stream;
     ctx->ws = ws;
     ctx->slotX = ctx->slotY = 0;
@@ -813,13 +852,7 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     ctx->broken = false;
     ctx->energy_tol = p0.energy_tol > 0 ? p0.energy_tol : (p0.precision == SPFC_FP32 ? 1e-6 : 1e-12);
     ctx->cur_sc = 0;
-    {
-        // closing each step inside the next update kernel makes every workgroup of
-        // that kernel read its member's partial sums: worth it while that re-read is small
-        const Shapes& h = ctx->sh;
-        const double reread = (double)M * std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
-        ctx->fin_in = tune_plan().fin_in_kernel != 0 && reread <= 48.0e6;
-    }
+    set_plan(ctx, ctx->plan);
     ctx->use_graph = false;
     ctx->profiling = false;
     for (int i = 0; i < R_COUNT; ++i) {
@@ -975,6 +1008,116 @@ size_t batch_bytes(const std::vector<std::vector<int>>& classes, const spfc_grid
 }
 
 bool member_ok(const spfc_batch* b, int member) { return b && member >= 0 && member < (int)b->where.size(); }
+
+// ---------------------------------------------------------------- launch-plan tuner
+
+// Run state of a context between calls: both state slots, both scalar-block copies
+// and the history ring on the device (two contiguous ranges of the workspace),
+// slot / step bookkeeping on the host.
+struct HostState {
+    int slotX, slotY, cur_sc;
+    int64_t step;
+    double dt_prev;
+    bool started;
+};
+
+size_t snapshot_bytes(const spfc_ctx* ctx) {
+    return 2 * ctx->lay.field_bytes + (ctx->lay.total - ctx->lay.off_sc);
+}
+
+int snapshot(spfc_ctx* ctx, char* dst, HostState& hs) {
+    hs = {ctx->slotX, ctx->slotY, ctx->cur_sc, ctx->step, ctx->dt_prev, ctx->started};
+    const size_t a = 2 * ctx->lay.field_bytes, b = ctx->lay.total - ctx->lay.off_sc;
+    CK(hipMemcpyAsync(dst, ctx->slot(0), a, hipMemcpyDeviceToDevice, ctx->stream));
+    CK(hipMemcpyAsync(dst + a, ctx->ws + ctx->lay.off_sc, b, hipMemcpyDeviceToDevice, ctx->stream));
+    return SPFC_OK;
+}
+
+int restore(spfc_ctx* ctx, const char* src, const HostState& hs) {
+    const size_t a = 2 * ctx->lay.field_bytes, b = ctx->lay.total - ctx->lay.off_sc;
+    CK(hipMemcpyAsync(ctx->slot(0), src, a, hipMemcpyDeviceToDevice, ctx->stream));
+    CK(hipMemcpyAsync(ctx->ws + ctx->lay.off_sc, src + a, b, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->slotX = hs.slotX;
+    ctx->slotY = hs.slotY;
+    ctx->cur_sc = hs.cur_sc;
+    ctx->step = hs.step;
+    ctx->dt_prev = hs.dt_prev;
+    ctx->started = hs.started;
+    return SPFC_OK;
+}
+
+// Milliseconds of `trial` steps of size dt under plan tp, from the snapshot (after
+// two untimed steps that absorb any restart).
+int time_plan(spfc_ctx* ctx, const TunePlan& tp, double dt, int64_t trial, const char* snap, const HostState& hs,
+              hipEvent_t e0, hipEvent_t e1, float* ms) {
+    set_plan(ctx, tp);
+    int rc;
+    if ((rc = restore(ctx, snap, hs))) return rc;
+    if ((rc = ctx_step(ctx, dt, 2))) return rc;
+    CK(hipEventRecord(e0, ctx->stream));
+    if ((rc = ctx_step(ctx, dt, trial))) return rc;
+    CK(hipEventRecord(e1, ctx->stream));
+    CK(hipEventSynchronize(e1));
+    CK(hipEventElapsedTime(ms, e0, e1));
+    return SPFC_OK;
+}
+
+// Coordinate search over the values per thread (4, 8, 16) and workgroup size (128,
+// 256 threads) of each step kernel, one kernel at a time, keeping a change only if
+// it saves at least 1 %.  The run state is restored afterwards: tuning changes
+// nothing but the plan (and with it the rounding of the transforms).
+int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
+    HostState hs;
+    int rc;
+    if ((rc = snapshot(ctx, snap, hs))) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        ctx->broken = true;
+        return SPFC_E_DEVICE;
+    }
+    TunePlan best = ctx->plan;
+    float best_ms = 0.f;
+    rc = time_plan(ctx, best, dt, trial, snap, hs, e0, e1, &best_ms);
+    const size_t lds_max = device_lds_max();
+    RolePlan TunePlan::*roles[4] = {&TunePlan::inv, &TunePlan::real, &TunePlan::fwd, &TunePlan::mid};
+    const int nroles = ctx->sz.dim == 3 ? 4 : 3;
+    for (int r = 0; r < nroles && !rc; ++r) {
+        for (int E : {4, 8, 16}) {
+            for (int T : {128, 256}) {
+                TunePlan cand = best;
+                if ((cand.*roles[r]).E == E && (cand.*roles[r]).T == T) continue;
+                (cand.*roles[r]).E = E;
+                (cand.*roles[r]).T = T;
+                if (!plan_fits(ctx->sz, ctx->M, cand, lds_max)) continue;
+                float ms = 0.f;
+                if ((rc = time_plan(ctx, cand, dt, trial, snap, hs, e0, e1, &ms))) break;
+                if (ms < 0.99f * best_ms) {
+                    best = cand;
+                    best_ms = ms;
+                }
+            }
+            if (rc) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    set_plan(ctx, best);
+    if ((rc = restore(ctx, snap, hs))) return rc;
+    CK(hipStreamSynchronize(ctx->stream));
+    return SPFC_OK;
+}
+
+// values per thread and threads per workgroup the step kernels actually use
+void get_plan(const spfc_ctx* ctx, int* out) {
+    const LaunchShape* sh[4] = {&ctx->sh.A, &ctx->sh.B, &ctx->sh.Cf, &ctx->sh.midI};
+    for (int i = 0; i < 4; ++i) {
+        const bool used = i < 3 || ctx->sz.dim == 3;
+        out[2 * i] = used ? sh[i]->E : 0;
+        out[2 * i + 1] = used ? sh[i]->block : 0;
+    }
+}
 
 }  // namespace
 
@@ -1162,6 +1305,26 @@ int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms
     return SPFC_OK;
 }
 
+int spfc_tune_bytes(spfc_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return SPFC_E_INVAL;
+    *bytes = snapshot_bytes(ctx);
+    return SPFC_OK;
+}
+
+int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes) {
+    if (!ctx || !scratch_dev) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || trial_steps < 1) return SPFC_E_INVAL;
+    if (scratch_bytes < snapshot_bytes(ctx)) return SPFC_E_NOMEM;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    return tune_ctx(ctx, dt, trial_steps, reinterpret_cast<char*>(scratch_dev));
+}
+
+int spfc_get_plan(spfc_ctx* ctx, int* plan8) {
+    if (!ctx || !plan8) return SPFC_E_INVAL;
+    get_plan(ctx, plan8);
+    return SPFC_OK;
+}
+
 int spfc_destroy(spfc_ctx* ctx) {
     if (!ctx) return SPFC_E_INVAL;
     free_ctx(ctx);
@@ -1259,6 +1422,72 @@ int spfc_batch_history(spfc_batch* b, int member, int64_t first, int64_t count, 
 int spfc_batch_get_phi(spfc_batch* b, int member, void* out_dev, int dtype) {
     if (!member_ok(b, member) || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
     return ctx_get_phi(b->cls[b->where[member].first], b->where[member].second, out_dev, dtype);
+}
+
+int spfc_batch_profile(spfc_batch* b, int enable) {
+    if (!b) return SPFC_E_INVAL;
+    for (auto* c : b->cls) {
+        const int rc = spfc_profile(c, enable);
+        if (rc) return rc;
+    }
+    return SPFC_OK;
+}
+
+int spfc_batch_kernel_times(spfc_batch* b, int cap, const char** names, double* avg_ms, int64_t* launches,
+                            double* bytes_per_launch, int* count) {
+    if (!b || !count) return SPFC_E_INVAL;
+    double ms[R_COUNT] = {0}, by[R_COUNT] = {0};
+    int64_t nl[R_COUNT] = {0};
+    for (auto* ctx : b->cls) {
+        const int rc = drain_events(ctx);
+        if (rc) return rc;
+        const double F = (double)ctx->lay.F * ctx->M;
+        const int d = ctx->sz.dim;
+        const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F, 0.0};
+        for (int i = 0; i < R_COUNT; ++i) {
+            if (ctx->role_n[i] == 0) continue;
+            ms[i] += ctx->role_ms[i] / (double)ctx->role_n[i];
+            by[i] += bytes[i];
+            nl[i] = std::max(nl[i], ctx->role_n[i]);
+        }
+    }
+    int k = 0;
+    for (int i = 0; i < R_COUNT; ++i) {
+        if (nl[i] == 0) continue;
+        if (k < cap) {
+            if (names) names[k] = kRoleNames[i];
+            if (avg_ms) avg_ms[k] = ms[i];
+            if (launches) launches[k] = nl[i];
+            if (bytes_per_launch) bytes_per_launch[k] = by[i];
+        }
+        ++k;
+    }
+    *count = k;
+    return SPFC_OK;
+}
+
+int spfc_batch_tune_bytes(spfc_batch* b, size_t* bytes) {
+    if (!b || !bytes) return SPFC_E_INVAL;
+    size_t m = 0;
+    for (auto* c : b->cls) m = std::max(m, snapshot_bytes(c));
+    *bytes = m;
+    return SPFC_OK;
+}
+
+int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes) {
+    if (!b || !scratch_dev) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || trial_steps < 1) return SPFC_E_INVAL;
+    for (auto* c : b->cls) {
+        const int rc = spfc_tune(c, dt, trial_steps, scratch_dev, scratch_bytes);
+        if (rc) return rc;
+    }
+    return SPFC_OK;
+}
+
+int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8) {
+    if (!member_ok(b, member) || !plan8) return SPFC_E_INVAL;
+    get_plan(b->cls[b->where[member].first], plan8);
+    return SPFC_OK;
 }
 
 int spfc_batch_destroy(spfc_batch* b) {

@@ -56,3 +56,19 @@ def noise_ic(shape, mean: float, seed: int, amplitude: float = 0.05) -> np.ndarr
 def uniform_range(seed: int, count: int, lo: float, hi: float) -> np.ndarray:
     """`count` draws from U[lo, hi) (for parameter ensembles)."""
     return lo + (hi - lo) * uniform01(seed, count)
+
+
+def ensemble_members(count: int = 64, sizes=(128, 256, 512), seed: int = 2024):
+    """Parameter ensemble of independent 2-D runs: member k has n = sizes[k % len(sizes)]
+    points per axis on a box of side n pi / 4 (h = pi / 4), epsilon ~ U[0.05, 0.5),
+    mean density ~ U[-0.4, 0) and the noise initial data of `noise_ic` with seed
+    seed + 1 + k.  Returns a list of dicts with keys n, L, epsilon, mean, seed."""
+    eps = uniform_range(seed, count, 0.05, 0.5)
+    means = uniform_range(seed + 7919, count, -0.4, 0.0)
+    out = []
+    for k in range(count):
+        n = int(sizes[k % len(sizes)])
+        side = n * np.pi / 4.0
+        out.append({"n": (n, n), "L": (side, side), "epsilon": float(eps[k]), "mean": float(means[k]),
+                    "seed": seed + 1 + k})
+    return out

@@ -168,3 +168,51 @@ def test_graph_replay_batch_and_checkpoint():
     s.step(0.01, 10)
     assert np.array_equal(s.phi().cpu().numpy(), ref)
     s.close()
+
+
+# ----------------------------------------------------------------- launch-plan tuner
+
+def test_tune_keeps_the_run_state():
+    """Tuning mid-run restores the state: records so far unchanged, the step count
+    unchanged, and the continuation equal to an untuned run up to the rounding of the
+    different transform radices."""
+    from paper_2012_15133_amd import Solver
+    n, L = (128, 64), (16 * math.pi, 8 * math.pi)
+    phi0 = noise_ic((64, 128), -0.2, 12)
+    a = Solver(n, L, phi0, 0.25, history=128)
+    b = Solver(n, L, phi0, 0.25, history=128)
+    a.step(0.01, 30)
+    b.step(0.01, 30)
+    before = a.history(0, 31)
+    plan = a.tune(0.01, trial_steps=6)
+    print("plan", plan, flush=True)
+    assert set(plan) == {"inv", "real", "fwd"}
+    assert all(e in (4, 8, 16) and 32 <= t <= 256 for e, t in plan.values())
+    assert a.step_count() == 30 and a.history(0, 31) == before
+    a.step(0.01, 40)
+    b.step(0.01, 40)
+    pa, pb = a.phi().cpu().numpy(), b.phi().cpu().numpy()
+    assert np.max(np.abs(pa - pb)) <= 1e-12 * np.max(np.abs(pb))
+    for x, y in zip(a.history(0, 71), b.history(0, 71)):
+        assert abs(x["energy"] - y["energy"]) <= 1e-13 * abs(y["energy"])
+    a.close()
+    b.close()
+
+
+def test_batch_tune_then_step_matches_untuned_members():
+    from paper_2012_15133_amd import Batch
+    members = _members(SPECS)
+    b = Batch(members, history=64)
+    b.step(0.01, 5)
+    b.tune(0.01, trial_steps=4)
+    for i in range(len(members)):
+        assert set(b.plan(i)) >= {"inv", "real", "fwd"}
+    assert b.step_count() == 5
+    b.step(0.01, 20)
+    for i in (0, 2, 5):
+        phi, hist, _ = _single(members[i], [(0.01, 5), (0.01, 20)], 64)
+        got = b.phi(i).cpu().numpy()
+        assert np.max(np.abs(got - phi)) <= 1e-12 * np.max(np.abs(phi))
+        for x, y in zip(b.history(i, 0, 26), hist):
+            assert abs(x["energy"] - y["energy"]) <= 1e-13 * abs(y["energy"])
+    b.close()
