@@ -156,9 +156,14 @@ class Grid:
 
 @dataclass(frozen=True)
 class Params:
-    """Model parameters: a = 1 - epsilon > 0 (Section 1), c4 > 0 (paper: 1)."""
+    """Model parameters: a = 1 - epsilon > 0 (Section 1), c4 > 0 (paper: 1).
+
+    stab = A >= 0 selects the stabilized scheme of the closing remarks of Section 5:
+    the regularization -A dt Delta_N (phi^{n+1} - phi^n) is added to the chemical
+    potential of the step (A = 0: the scheme eq. scheme-SAV-1 itself)."""
     epsilon: float
     c4: float = 1.0
+    stab: float = 0.0
 
     @property
     def a(self) -> float:
@@ -246,16 +251,33 @@ def modified_energy(g: Grid, prm: Params, phi1, phi0, r1: float, r0: float) -> f
             + 0.5 * (r1 * r1 + (2.0 * r1 - r0) ** 2))
 
 
+def grad_sq_norm(g: Grid, f: np.ndarray) -> float:
+    """<f, -Delta_N f>: the squared gradient norm with the even-order symbol of Delta_N."""
+    return -inner(g, f, lap(g, f))
+
+
+def stabilized_energy(g: Grid, prm: Params, dt: float, phi1, phi0, r1: float, r0: float) -> float:
+    """Modified energy of the stabilized scheme: the energy of Theorem 3.1 plus
+    (A dt / 4) <phi1 - phi0, -Delta_N (phi1 - phi0)>.  Derived here from the algebra of
+    Theorem 3.1 with the regularization term in mu; it equals modified_energy at A = 0."""
+    d = phi1 - phi0
+    return modified_energy(g, prm, phi1, phi0, r1, r0) + 0.25 * prm.stab * dt * grad_sq_norm(g, d)
+
+
 def sav_energy(g: Grid, prm: Params, phi: np.ndarray, r: float) -> float:
     """SAV energy plotted against E_N in Section 5.2: a/2 ||phi||^2 + 1/2 ||Delta_N phi||^2 + r^2."""
     lp = lap(g, phi)
     return 0.5 * prm.a * inner(g, phi, phi) + 0.5 * inner(g, lp, lp) + r * r
 
 
-def mu_of(g: Grid, prm: Params, phi_new, phihat, r_new: float) -> np.ndarray:
+def mu_of(g: Grid, prm: Params, phi_new, phihat, r_new: float, phi_old=None, dt: float = 0.0) -> np.ndarray:
     """Chemical potential of the step, mu = L_N phi^{n+1} + r^{n+1}/sqrt(E_1(phihat)) N_N(phihat)
-    (Section 3.1, eq. eng stab-1, second line)."""
-    return L_op(g, prm, phi_new) + (r_new / math.sqrt(E1(g, prm, phihat))) * N_nl(g, prm, phihat)
+    (Section 3.1, eq. eng stab-1, second line), plus -A dt Delta_N (phi^{n+1} - phi^n) for the
+    stabilized scheme (phi_old = phi^n)."""
+    mu = L_op(g, prm, phi_new) + (r_new / math.sqrt(E1(g, prm, phihat))) * N_nl(g, prm, phihat)
+    if prm.stab != 0.0:
+        mu = mu - prm.stab * dt * lap(g, phi_new - phi_old)
+    return mu
 
 
 # ----------------------------------------------------------------- one time step (Section 2.3)
@@ -281,6 +303,10 @@ def sav_step(g: Grid, prm: Params, dt: float, phi_n, phi_nm1, r_n: float, r_nm1:
       3. g = dt Delta_N N (rho/a0 - <N, psi>/(2 a0 sqrt E)) / sqrt E + psi + dt f,
          psi = a1 phi^n + a2 phi^{n-1}, rho = a1 r^n + a2 r^{n-1}
          (for BDF2 this is the right-hand side g_N^n printed before eq. solver-3).
+    Stabilized scheme (prm.stab = A > 0): mu gains -A dt Delta_N (phi^{n+1} - phi^n), so
+    dt Delta_N mu gains -A dt^2 Delta_N^2 (phi^{n+1} - phi^n): A_N gains + A dt^2 Delta_N^2 and
+    the right-hand side of step 3 gains + A dt^2 Delta_N^2 phi^n.  The r equation (eq.
+    solver-2) keeps a0 phi^{n+1} - psi, so steps 3 (the constant c) and 6 use psi itself.
       4. LHS = <N, phi^{n+1}> from eq. solver-4:
          (1 - dt/(2E) <N, v>) LHS = <N, A_N^{-1} g>.
       5. phi^{n+1} = dt/(2E) LHS v + A_N^{-1} g   (eq. solver-6).
@@ -298,6 +324,8 @@ def sav_step(g: Grid, prm: Params, dt: float, phi_n, phi_nm1, r_n: float, r_nm1:
 
     k2 = g.ksq()
     A = a0 + dt * k2 * (prm.a + k2 * k2)          # symbol of A_N = a0 I - dt Delta_N L_N
+    if prm.stab != 0.0:
+        A = A + prm.stab * dt * dt * k2 * k2      # + A dt^2 Delta_N^2
 
     def A_inv(f):
         return ifftn(fftn(f) / A).real
@@ -305,6 +333,8 @@ def sav_step(g: Grid, prm: Params, dt: float, phi_n, phi_nm1, r_n: float, r_nm1:
     lapN = lap(g, Nh)
     v = A_inv(lapN)
     rhs = psi if forcing is None else psi + dt * forcing
+    if prm.stab != 0.0:
+        rhs = rhs + prm.stab * dt * dt * lap(g, lap(g, phi_n))
     c = rho / a0 - inner(g, Nh, psi) / (2.0 * a0 * sqE)
     gN = dt * lapN * (c / sqE) + rhs
     Ag = A_inv(gN)
@@ -354,7 +384,8 @@ def run(g: Grid, prm: Params, phi0, dt: float, nsteps: int, startup: str = "sav1
     """Advance `nsteps` steps from phi0 and record per-step diagnostics.
 
     records[n] (n = 0..nsteps) holds the modified energy E_n = E(phi^n, phi^{n-1},
-    r^n, r^{n-1}) (eq. discrete energy; for n = 0 the start-up pair), the mean
+    r^n, r^{n-1}) (eq. discrete energy; for n = 0 the start-up pair; for the stabilized
+    scheme the energy of `stabilized_energy`), the mean
     of phi^n, r^n, and for n >= 1 xi = r^n / sqrt(E_1(phihat)), E_1(phihat) and
     p1 = <N, A_N^{-1} Delta_N N> of the step that produced phi^n.
     `forcing(t)` returns f at time t; it is evaluated at t^{n+1}.
@@ -371,7 +402,7 @@ def run(g: Grid, prm: Params, phi0, dt: float, nsteps: int, startup: str = "sav1
     def record(info=None):
         rec = {"mean": float(np.mean(phi_n)), "r": r_n}
         if energies:
-            rec["energy"] = modified_energy(g, prm, phi_n, phi_nm1, r_n, r_nm1)
+            rec["energy"] = stabilized_energy(g, prm, dt, phi_n, phi_nm1, r_n, r_nm1)
         if info is not None:
             rec.update({"xi": info["xi"], "E1": info["E1"], "p1": info["p1"]})
         records.append(rec)
