@@ -79,7 +79,13 @@ typedef struct {
  *  precision: SPFC_FP64 or SPFC_FP32.
  *  history  : capacity of the per-step record ring (>= 1).
  *  energy_tol: relative rise of the modified energy that sets SPFC_FLAG_ENERGY_RISE
- *             (<= 0 picks 1e-12 for FP64, 1e-6 for FP32). */
+ *             (<= 0 picks 1e-12 for FP64, 1e-6 for FP32).
+ *  stab     : A >= 0.  A > 0 selects the stabilized scheme of the closing remarks of
+ *             Section 5: the regularization -A dt Delta_N (phi^{n+1} - phi^n) is added to
+ *             the chemical potential of every step (the step operator gains A dt^2 |k|^4,
+ *             its right-hand side A dt^2 |k|^4 phi^n), and the modified energy gains
+ *             (A dt / 4) <phi^n - phi^{n-1}, -Delta_N (phi^n - phi^{n-1})>, with which it
+ *             is again non-increasing.  0 = the scheme eq. scheme-SAV-1. */
 typedef struct {
     double epsilon;
     double c4;
@@ -87,10 +93,12 @@ typedef struct {
     int precision;
     int64_t history;
     double energy_tol;
+    double stab;
 } spfc_params;
 
 /* Per-step record (index n = state phi^n).  energy is the modified energy
- * E(phi^n, phi^{n-1}, r^n, r^{n-1}) of Theorem 3.1 (eq. discrete energy), mean the
+ * E(phi^n, phi^{n-1}, r^n, r^{n-1}) of Theorem 3.1 (eq. discrete energy; with the
+ * stabilization term of spfc_params.stab when that is > 0), mean the
  * mean of phi^n, r = r^n.  xi = r^n / sqrt(E_1(phihat)), E1 = E_1(phihat) and
  * p1 = <N, A_N^-1 Delta_N N> belong to the step that produced phi^n (0 for n = 0). */
 typedef struct {
@@ -106,7 +114,7 @@ typedef struct {
 
 /* Energies of the current state phi^n (spfc_energy). */
 typedef struct {
-    double modified_energy;  /* E(phi^n, phi^{n-1}, r^n, r^{n-1}), Theorem 3.1 */
+    double modified_energy;  /* E(phi^n, phi^{n-1}, r^n, r^{n-1}), Theorem 3.1 (+ stab term) */
     double energy;           /* E_N(phi^n), eq. energy-discrete-spectral (with c4) */
     double sav_energy;       /* a/2||phi||^2 + 1/2||Delta_N phi||^2 + r^2 (Section 5.2) */
     double r;                /* r^n */

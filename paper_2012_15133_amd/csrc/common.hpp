@@ -19,6 +19,7 @@ struct Geo {
     double volume;        // |Omega|
     double pscale;        // |Omega| / N_total^2: inner product from two spectra (Parseval)
     double e1_const;      // (1 + 1/c4) |Omega|
+    double stab;          // A of the stabilized scheme (0: plain scheme)
 };
 
 // Device-resident scalars of the run.  Written by one lane only (vector stores),
@@ -32,13 +33,14 @@ struct DevScalars {
     double energy_prev;   // modified energy of the newest finalized record
     double E1, p1, p2, ppsi, S;   // latest step
     double q_E1;          // E_1 of the latest query / start-up pass
-    double q_norm[4];     // latest ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2
+    double q_norm[5];     // latest ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2,
+                          // <X - Y, -Delta_N (X - Y)>
     double mean;          // mean of the newest state
     unsigned int flags;   // sticky SPFC_FLAG_* bits
     unsigned int pad0;
     long long last_record;
     long long step_x;     // index of the newest state X of the pair (the record a finish writes)
-    double pad[3];
+    double pad[2];
 };
 
 struct Record {
@@ -55,10 +57,11 @@ enum : unsigned int {
 // Partial sums per workgroup (FP64):
 //   P (forward pass): p1, p2, p_psi                                   3 per workgroup
 //   E (forward pass): ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2,
-//                     ||Delta X||^2, Re X(0) (only the owner adds it)  5 per workgroup
+//                     ||Delta X||^2, Re X(0) (only the owner adds it),
+//                     <X - Y, -Delta_N (X - Y)>                         6 per workgroup
 //   B (real-space pass): E_1 density sum                              1 per workgroup
 //   Q (update / query passes): the same five as E for the pair they form
-constexpr int NPART_P = 3, NPART_E = 5;
+constexpr int NPART_P = 3, NPART_E = 6;
 
 // What a launch needs to finish the previous step (the SAV scalar) itself.  All
 // arrays are those of member 0; member m's part starts m * (count per member)
@@ -195,7 +198,7 @@ struct FinalizeArgs {
     int nQ;                 // workgroups per member that wrote Q
     const double* partB;
     int nB;
-    double a0, a1, a2, dt;  // FIN_STEP: weights and dt of the step
+    double a0, a1, a2, dt;  // FIN_STEP: weights and dt of the step; FIN_STATE: dt of the last step
     FinishIn fi;            // FIN_STEP
     DevScalars* sc;         // other modes: updated in place
     Record* hist;

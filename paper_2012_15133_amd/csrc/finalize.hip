@@ -15,12 +15,13 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
     const Geo geo = p.geos[mem];
     if (p.mode == FIN_STEP) {
         const FinishIn fi = member_fin(p.fi, mem);
-        double sBP[1 + NPART_P], sE[NPART_E];
-        block_sum_pair<1, NPART_P>(fi.partB, fi.nB, fi.partP, fi.nPE, sBP);
-        block_sum_partials<NPART_E>(fi.partE, fi.nPE, sE);
+        double sBPE[1 + NPART_P + NPART_E];
+        block_sum_trio<1, NPART_P, NPART_E>(fi.partB, fi.nB, fi.partP, fi.nPE, fi.partE, fi.nPE, sBPE);
         if (threadIdx.x == 0) {
-            const double sP[NPART_P] = {sBP[1], sBP[2], sBP[3]};
-            finish_step(fi, sBP[0], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
+            const double sP[NPART_P] = {sBPE[1], sBPE[2], sBPE[3]};
+            double sE[NPART_E];
+            for (int i = 0; i < NPART_E; ++i) sE[i] = sBPE[1 + NPART_P + i];
+            finish_step(fi, sBPE[0], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
         }
         return;
     }
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
     if (p.mode == FIN_STATE) {
         // record of the state reached by the last update: energy of (X, Y, r^n, r^{n-1})
         const double rn = sc->r_n, rnm1 = sc->r_nm1;
-        const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
+        const double energy = pair_energy(n0, n1, rn, rnm1, geo.pscale * sQB[5], p.dt, geo);
         if (!isfinite(energy)) fl |= FLAG_NONFINITE;
         if (p.check_rise && energy > sc->energy_prev * (1.0 + p.energy_tol)) fl |= FLAG_ENERGY_RISE;
         const long long step = sc->step_x;
@@ -55,6 +56,7 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
         sc->q_norm[1] = n1;
         sc->q_norm[2] = geo.pscale * sQB[2];
         sc->q_norm[3] = geo.pscale * sQB[3];
+        sc->q_norm[4] = geo.pscale * sQB[5];
         sc->mean = mean;
         const double r = sqrt(E1);
         if (p.mode == FIN_GHOST_R0) {

@@ -40,11 +40,18 @@ hipError_t dispatch_ne(int n, int e, F&& f) {
     constexpr int EE = decltype(ee)::value;
 
 template <typename T>
-hipError_t Kern<T>::spec_inv(int nl, int dim, const SpecInvArgs<T>& a, const LaunchShape& s, hipStream_t st) {
+hipError_t Kern<T>::spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a, const LaunchShape& s,
+                             hipStream_t st) {
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
-        if (dim == 2) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
-        else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+        const dim3 g(s.grid, s.members), b(s.block);
+        if (dim == 2) {
+            if (stab) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2, true>), g, b, s.shmem, st, a);
+            else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2, false>), g, b, s.shmem, st, a);
+        } else {
+            if (stab) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3, true>), g, b, s.shmem, st, a);
+            else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3, false>), g, b, s.shmem, st, a);
+        }
         return hipGetLastError();
     });
 }
@@ -66,20 +73,19 @@ hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, c
 }
 
 template <typename T>
-hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, const SpecFwdArgs<T>& a, const LaunchShape& s,
+hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwdArgs<T>& a, const LaunchShape& s,
                              hipStream_t st) {
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
+        const dim3 g(s.grid, s.members), b(s.block);
         if (dim == 2) {
-            if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
-            else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST, false>), g, b, s.shmem, st, a);
+            else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, true>), g, b, s.shmem, st, a);
+            else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, false>), g, b, s.shmem, st, a);
         } else {
-            if (mode == FWD_SOLVE)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
-            else
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST, false>), g, b, s.shmem, st, a);
+            else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, true>), g, b, s.shmem, st, a);
+            else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, false>), g, b, s.shmem, st, a);
         }
         return hipGetLastError();
     });
@@ -107,9 +113,16 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
 }
 
 template <typename T>
-hipError_t Kern<T>::update(int dim, const UpdateArgs<T>& a, int grid, int members, int block, hipStream_t st) {
-    if (dim == 2) hipLaunchKernelGGL((k_update<T, 2>), dim3(grid, members), dim3(block), 0, st, a);
-    else hipLaunchKernelGGL((k_update<T, 3>), dim3(grid, members), dim3(block), 0, st, a);
+hipError_t Kern<T>::update(int dim, bool stab, const UpdateArgs<T>& a, int grid, int members, int block,
+                           hipStream_t st) {
+    const dim3 g(grid, members), b(block);
+    if (dim == 2) {
+        if (stab) hipLaunchKernelGGL((k_update<T, 2, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_update<T, 2, false>), g, b, 0, st, a);
+    } else {
+        if (stab) hipLaunchKernelGGL((k_update<T, 3, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_update<T, 3, false>), g, b, 0, st, a);
+    }
     return hipGetLastError();
 }
 

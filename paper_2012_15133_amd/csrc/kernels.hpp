@@ -116,6 +116,37 @@ __device__ inline void block_sum_pair(const double* a, int na, const double* b, 
     block_tree<NA + NB>(acc, out);
 }
 
+// Three arrays of per-workgroup partials in one sweep (as block_sum_pair), result
+// NA + NB + NC sums in every thread.
+template <int NA, int NB, int NC>
+__device__ inline void block_sum_trio(const double* a, int na, const double* b, int nb, const double* c, int nc,
+                                      double (&out)[NA + NB + NC]) {
+    constexpr int U = 4, NV = NA + NB + NC;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    int n = na > nb ? na : nb;
+    n = n > nc ? n : nc;
+    for (int j0 = threadIdx.x; j0 < n; j0 += U * blockDim.x) {
+        double v[U][NV];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int jj = j0 + q * blockDim.x;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) v[q][i] = jj < na ? a[(size_t)jj * NA + i] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) v[q][NA + i] = jj < nb ? b[(size_t)jj * NB + i] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) v[q][NA + NB + i] = jj < nc ? c[(size_t)jj * NC + i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] += v[q][i];
+    }
+    block_tree<NV>(acc, out);
+}
+
 template <int NV>
 __device__ inline void block_sum_partials(const double* part, int n, double (&out)[NV]) {
     double o[NV + 1];
@@ -155,8 +186,9 @@ __device__ inline void spec_symbols(const Geo& g, int kx, int ky, int kz, double
 
 // Energy partials of the pair (X, Y) at one mode: ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2,
 // ||X||^2, ||Delta X||^2 with the Hermitian weight (modified energy, eq. discrete
-// energy; E_N, eq. energy-discrete-spectral), and Re X(0) for the mean.
-template <typename T>
+// energy; E_N, eq. energy-discrete-spectral), Re X(0) for the mean, and
+// <X - Y, -Delta_N (X - Y)> for the extra term of the stabilized scheme's energy.
+template <typename T, bool STAB>
 __device__ inline void pair_partials(cpx<T> X, cpx<T> Y, int kx, double k2, bool zero_mode, const Geo& geo,
                                      double (&acc)[NPART_E]) {
     const double w = hweight(kx, geo.nx);
@@ -168,6 +200,41 @@ __device__ inline void pair_partials(cpx<T> X, cpx<T> Y, int kx, double k2, bool
     acc[2] += w * xx;
     acc[3] += w * k2 * k2 * xx;
     if (zero_mode) acc[4] += (double)X.x;
+    if constexpr (STAB) {
+        const double dx = (double)X.x - Y.x, dy = (double)X.y - Y.y;
+        acc[5] += w * k2 * (dx * dx + dy * dy);
+    }
+}
+
+// Store the energy partials of a workgroup: all NPART_E sums for the stabilized
+// kernels, else the first five and a zero (the same layout, without the work).
+template <bool STAB>
+__device__ inline void store_energy_partials(double (&acc)[NPART_E], double* dst) {
+    if constexpr (STAB) {
+        block_sum_store<NPART_E>(acc, dst);
+    } else {
+        double a5[NPART_E - 1];
+#pragma unroll
+        for (int i = 0; i < NPART_E - 1; ++i) a5[i] = acc[i];
+        block_sum_store<NPART_E - 1>(a5, dst);
+        if (threadIdx.x == 0) dst[NPART_E - 1] = 0.0;
+    }
+}
+
+// Symbol of the step operator, A(k) = a0 + dt |k|^2 (a + |k|^4) (eq. solver-1), plus
+// stab dt^2 |k|^4 for the stabilized scheme, whose regularization -A dt Delta_N
+// (phi^{n+1} - phi^n) in mu also adds stab dt^2 |k|^4 phi^n to the right-hand side.
+template <bool STAB>
+__device__ inline double stab_sym(const Geo& g, double dt, double k2) {
+    if constexpr (STAB) return g.stab * dt * dt * k2 * k2;
+    return 0.0;
+}
+
+// Stabilized modified energy: the energy of Theorem 3.1 plus (A dt / 4) <X - Y, -Delta_N (X - Y)>.
+__device__ inline double pair_energy(double n0, double n1, double rn, double rnm1, double dgrad, double dt,
+                                     const Geo& g) {
+    return 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1)) +
+           0.25 * g.stab * dt * dgrad;
 }
 
 // xi = r^{n+1} / sqrt(E_1) from the reduced sums (kept out of line so that every
@@ -203,7 +270,7 @@ __device__ inline void finish_step(const FinishIn& fi, double E1sum, const doubl
     const double xi = sav_xi(E1sum, sP[0], sP[1], sP[2], rn, rnm1, a0, a1, a2, dt, geo.cell, geo.e1_const,
                              geo.pscale);
     const double rnew = xi * S;
-    const double energy = 0.25 * (n0 + n1) + 0.5 * (rn * rn + (2.0 * rn - rnm1) * (2.0 * rn - rnm1));
+    const double energy = pair_energy(n0, n1, rn, rnm1, geo.pscale * sE[5], dt, geo);
     const double mean = sE[4] * geo.inv_npts;
     unsigned int fl = s.flags;
     if (!isfinite(E1) || !isfinite(p1) || !isfinite(p2) || !isfinite(pp) || !isfinite(xi) || !isfinite(energy))
@@ -281,7 +348,7 @@ __device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double 
 // ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2 (modified energy,
 // eq. discrete energy; E_N, eq. energy-discrete-spectral).  Then
 // Z_j = i kappa1_j (e1 X + e2 Y) and the inverse transform along the line.
-template <typename T, int NL, int EE, int DIM>
+template <typename T, int NL, int EE, int DIM, bool STAB>
 __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     using PL = Plan<NL, EE>;
     constexpr int E = PL::E, P = PL::P, C = DIM;
@@ -312,7 +379,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
         xi = p.fin ? finish_in_kernel(fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : fi.sc_in->xi;
     }
 
-    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     cpx<T> v[C][E];
     const T h1 = T(p.e1), h2 = T(p.e2);
 #pragma unroll
@@ -327,14 +394,15 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             if (p.update) {
                 // in FP64 for both storage precisions: the k = 0 mode then keeps the mean
                 // (Theorem 2.1) to the rounding of one store per step
-                const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
-                const double f1 = -p.udt * xi * k2 * iA, f2 = p.ua1 * iA, f3 = p.ua2 * iA;
+                const double st = stab_sym<STAB>(geo, p.udt, k2);
+                const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2) + st);
+                const double f1 = -p.udt * xi * k2 * iA, f2 = (p.ua1 + st) * iA, f3 = p.ua2 * iA;
                 X = mk<T>(T(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x),
                           T(f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y));
                 Y = cur[m];
                 p.out_new[lbase + e] = X;
             } else {
-                pair_partials<T>(X, Y, kx, k2, line == 0 && e == 0, geo, acc);
+                pair_partials<T, STAB>(X, Y, kx, k2, line == 0 && e == 0, geo, acc);
             }
         }
         const cpx<T> ph = mk<T>(h1 * X.x + h2 * Y.x, h1 * X.y + h2 * Y.y);
@@ -344,7 +412,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             v[j][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1_j phihat
         }
     }
-    if (!p.update) block_sum_store<NPART_E>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
+    if (!p.update) store_energy_partials<STAB>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
     if (p.want_grad) {
         stage_twiddles<T, PL>(ltw, p.tw, p.tws);
         fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
@@ -526,7 +594,9 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
 // b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
 //   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
 // p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1).
-template <typename T, int NL, int EE, int DIM, int MODE>
+// Stabilized scheme: A gains stab dt^2 |k|^4 and b2 = A^-1 (psi + stab dt^2 |k|^4 phi^n);
+// the r equation, and so p_psi, keeps psi.
+template <typename T, int NL, int EE, int DIM, int MODE, bool STAB>
 __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     using PL = Plan<NL, EE>;
     constexpr int E = PL::E, P = PL::P, C = DIM;
@@ -555,7 +625,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
         Ys[m] = act ? p.Y[lbase + t + P * m] : mk<T>(0, 0);
     }
     double acc[NPART_P] = {0.0, 0.0, 0.0};
-    double accE[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double accE[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -577,13 +647,15 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             const double Ny = -dx - 2.0 * k2 * phy;
             if constexpr (MODE == FWD_SOLVE) {
                 const double psx = p.a1 * X.x + p.a2 * Y.x, psy = p.a1 * X.y + p.a2 * Y.y;
-                const double iA = 1.0 / (p.a0 + p.dt * k2 * (geo.a + k2 * k2));
+                const double st = stab_sym<STAB>(geo, p.dt, k2);
+                const double iA = 1.0 / (p.a0 + p.dt * k2 * (geo.a + k2 * k2) + st);
                 const double w = hweight(kx, geo.nx);
                 const double re = Nx * psx + Ny * psy;
                 acc[0] -= w * k2 * (Nx * Nx + Ny * Ny) * iA;
-                acc[1] += w * re * iA;
+                if constexpr (STAB) acc[1] += w * (re + st * (Nx * X.x + Ny * X.y)) * iA;
+                else acc[1] += w * re * iA;
                 acc[2] += w * re;
-                pair_partials<T>(X, Y, kx, k2, line == 0 && e == 0, geo, accE);
+                pair_partials<T, STAB>(X, Y, kx, k2, line == 0 && e == 0, geo, accE);
                 p.nhat[lbase + e] = mk<T>(T(Nx), T(Ny));
             } else {
                 // phi^{-1} = phi^0 - dt Delta_N (N + L_N phi^0)  (eq. scheme-SAV-initial-1)
@@ -595,20 +667,20 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     if constexpr (MODE == FWD_SOLVE) {
         const size_t wg = (size_t)mem * gridDim.x + blockIdx.x;
         block_sum_store<NPART_P>(acc, p.partP + NPART_P * wg);
-        block_sum_store<NPART_E>(accE, p.partE + NPART_E * wg);
+        store_energy_partials<STAB>(accE, p.partE + NPART_E * wg);
     }
 }
 
 // ------------------------------------------------------------------ elementwise pending update
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool STAB>
 __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
     const int mem = blockIdx.y;
     const Geo geo = p.geos[mem];
     const FinishIn fi = member_fin(p.fi, mem);
     const double xi = p.fin ? finish_in_kernel(fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : fi.sc_in->xi;
     const size_t mbase = (size_t)mem * p.fs;
-    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < p.total;
          i += (long long)gridDim.x * blockDim.x) {
         const int line = (int)(i / p.NL), e = (int)(i - (long long)line * p.NL);
@@ -617,13 +689,14 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         spec_index<DIM>(line, p.B, e, kx, ky, kz);
         spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
         const cpx<T> cur = p.cur[mbase + i], prv = p.prev[mbase + i], nh = p.nhat[mbase + i];
-        const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2));
-        const double f1 = -p.udt * xi * k2 * iA, f2 = p.ua1 * iA, f3 = p.ua2 * iA;
+        const double st = stab_sym<STAB>(geo, p.udt, k2);
+        const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2) + st);
+        const double f1 = -p.udt * xi * k2 * iA, f2 = (p.ua1 + st) * iA, f3 = p.ua2 * iA;
         const cpx<T> X = mk<T>(T(f1 * nh.x + f2 * cur.x + f3 * prv.x), T(f1 * nh.y + f2 * cur.y + f3 * prv.y));
         p.out_new[mbase + i] = X;
-        pair_partials<T>(X, cur, kx, k2, i == 0, geo, acc);
+        pair_partials<T, STAB>(X, cur, kx, k2, i == 0, geo, acc);
     }
-    block_sum_store<NPART_E>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
+    store_energy_partials<STAB>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
 }
 
 // ------------------------------------------------------------------ rows: real <-> half spectrum

@@ -43,14 +43,17 @@ inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int E = 16
 
 template <typename T>
 struct Kern {
-    static hipError_t spec_inv(int nl, int dim, const SpecInvArgs<T>& a, const LaunchShape& s, hipStream_t st);
+    // stab: the stabilized-scheme variant (any member with a nonzero stabilization)
+    static hipError_t spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a, const LaunchShape& s,
+                               hipStream_t st);
     static hipError_t real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, const LaunchShape& s,
                                 hipStream_t st);
-    static hipError_t spec_fwd(int nl, int dim, int mode, const SpecFwdArgs<T>& a, const LaunchShape& s,
-                               hipStream_t st);
+    static hipError_t spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwdArgs<T>& a,
+                               const LaunchShape& s, hipStream_t st);
     static hipError_t pass(int nl, int dir, int omode, int c, const PassArgs<T>& a, const LaunchShape& s,
                            hipStream_t st);
-    static hipError_t update(int dim, const UpdateArgs<T>& a, int grid, int members, int block, hipStream_t st);
+    static hipError_t update(int dim, bool stab, const UpdateArgs<T>& a, int grid, int members, int block,
+                             hipStream_t st);
     static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
     // values per thread available for line length n
     static bool has_E(int n, int E) { return n < 16 ? E == n : (E == 4 || E == 8 || E == 16); }

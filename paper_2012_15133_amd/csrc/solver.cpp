@@ -167,6 +167,7 @@ int validate(const spfc_grid* g, const spfc_params* p) {
     if (p->precision != SPFC_FP64 && p->precision != SPFC_FP32) return SPFC_E_INVAL;
     if (p->history < 1) return SPFC_E_INVAL;
     if (!std::isfinite(p->energy_tol)) return SPFC_E_INVAL;
+    if (!std::isfinite(p->stab) || p->stab < 0.0) return SPFC_E_INVAL;
     return SPFC_OK;
 }
 
@@ -190,6 +191,7 @@ Geo make_geo(const spfc_grid& g, const spfc_params& prm) {
     geo.cell = vol / npts;
     geo.pscale = vol / (npts * npts);
     geo.e1_const = (1.0 + 1.0 / prm.c4) * vol;
+    geo.stab = prm.stab;
     return geo;
 }
 
@@ -202,7 +204,7 @@ struct CkptHeader {
     int32_t pad;
     DevScalars sc;
 };
-constexpr uint64_t kMagic = 0x5350464353415632ull;
+constexpr uint64_t kMagic = 0x5350464353415633ull;
 
 }  // namespace
 
@@ -224,6 +226,7 @@ struct spfc_ctx {
     bool broken;
     double energy_tol;
     int cur_sc;        // which of the two scalar-block copies holds the latest values
+    bool stab;         // some member uses the stabilized scheme: launch the stabilized kernels
     bool fin_in;       // close each step inside the next update kernel
     // graph replay of two steady steps
     bool use_graph;
@@ -417,7 +420,7 @@ struct Pipe {
         a.geos = ctx->dgeos();
         {
             Timed tm(ctx, R_SPEC_INV, timed);
-            CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, a, ctx->sh.A, ctx->stream));
+            CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, ctx->stab, a, ctx->sh.A, ctx->stream));
         }
         if (a.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
@@ -485,14 +488,16 @@ struct Pipe {
         a.fs = ctx->lay.fs;
         a.geos = ctx->dgeos();
         Timed tm(ctx, R_SPEC_FWD, timed);
-        CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, a, ctx->sh.Cf, ctx->stream));
+        CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, ctx->stab, a, ctx->sh.Cf, ctx->stream));
         return SPFC_OK;
     }
 
     // one workgroup per member: close a step (FIN_STEP) or a state / query pass
-    int finalize(int mode, int nQ, int check_rise, const Pending* pend = nullptr, bool timed = false) {
+    int finalize(int mode, int nQ, int check_rise, const Pending* pend = nullptr, bool timed = false,
+                 double dt = 0.0) {
         FinalizeArgs f{};
         f.mode = mode;
+        f.dt = dt;
         f.partQ = ctx->partQ();
         f.nQ = nQ;
         f.partB = ctx->partB();
@@ -698,12 +703,12 @@ struct Pipe {
         u.part = ctx->partQ();
         u.fs = ctx->lay.fs;
         u.geos = ctx->dgeos();
-        CK(Kern<T>::update(ctx->sz.dim, u, ctx->sh.updGrid, ctx->M, 256, ctx->stream));
+        CK(Kern<T>::update(ctx->sz.dim, ctx->stab, u, ctx->sh.updGrid, ctx->M, 256, ctx->stream));
         if (u.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         ctx->slotY = ctx->slotX;
         ctx->slotX = target;
         ctx->step += 1;
-        if ((rc = finalize(FIN_STATE, ctx->sh.updGrid, 1))) return rc;
+        if ((rc = finalize(FIN_STATE, ctx->sh.updGrid, 1, nullptr, false, dt))) return rc;
         ctx->started = true;
         ctx->dt_prev = dt;
         return SPFC_OK;
@@ -834,7 +839,11 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     if (!ctx) return SPFC_E_NOMEM;
     ctx->prm = p0;
     ctx->M = M;
-    for (int m = 0; m < M; ++m) ctx->geos.push_back(make_geo(grids[idx[m]], params[idx[m]]));
+    ctx->stab = false;
+    for (int m = 0; m < M; ++m) {
+        ctx->geos.push_back(make_geo(grids[idx[m]], params[idx[m]]));
+        ctx->stab = ctx->stab || params[idx[m]].stab != 0.0;
+    }
     ctx->sz = sizes_of(grids[idx[0]], p0.precision);
     ctx->plan = tune_plan();
     if (!plan_fits(ctx->sz, M, ctx->plan, device_lds_max())) {
@@ -938,7 +947,8 @@ int ctx_energy(spfc_ctx* ctx, int m, spfc_energy_t* out) {
     CK(hipStreamSynchronize(ctx->stream));
     const Geo& g = ctx->geos[m];
     const double rn = sc.r_n, rm = sc.r_nm1;
-    out->modified_energy = 0.25 * (sc.q_norm[0] + sc.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm));
+    out->modified_energy = 0.25 * (sc.q_norm[0] + sc.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm)) +
+                           0.25 * g.stab * ctx->dt_prev * sc.q_norm[4];
     out->E1 = sc.q_E1;
     out->energy = sc.q_E1 - g.e1_const + 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3];
     out->sav_energy = 0.5 * g.a * sc.q_norm[2] + 0.5 * sc.q_norm[3] + rn * rn;
