@@ -207,6 +207,14 @@ int spfc_set_graph(spfc_ctx* ctx, int enable);
  * spfc_get_plan writes 8 ints: (values per thread, threads per workgroup) of the
  * gradient/inverse, real-space, forward and (3-D) middle-axis kernels, 0 where
  * unused. */
+/* Kernel durations of a steady step of size dt > 0: from a snapshot of the run state
+ * (in scratch_dev, spfc_tune_bytes bytes), one untimed step, then one step in which
+ * each step kernel is launched `reps` >= 1 times back to back between two HIP
+ * events on the context stream, so that the average is the kernel's own duration
+ * rather than launch-to-launch time.  The repeats of the update kernel overwrite
+ * the older state; the run state is restored from the snapshot at the end.  Read
+ * the results with spfc_kernel_times.  Synchronizes.  Errors as spfc_tune. */
+int spfc_time_kernels(spfc_ctx* ctx, double dt, int reps, void* scratch_dev, size_t scratch_bytes);
 int spfc_tune_bytes(spfc_ctx* ctx, size_t* bytes);
 int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes);
 int spfc_get_plan(spfc_ctx* ctx, int* plan8);
@@ -251,6 +259,10 @@ int spfc_batch_tune_bytes(spfc_batch* b, size_t* bytes);
 int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch_dev,
                     size_t scratch_bytes);
 int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8);
+/* spfc_time_kernels for every class (scratch of spfc_batch_tune_bytes bytes); read the
+ * results with spfc_batch_kernel_times. */
+int spfc_batch_time_kernels(spfc_batch* b, double dt, int reps, void* scratch_dev,
+                            size_t scratch_bytes);
 /* Kernel timing as spfc_profile / spfc_kernel_times, summed over the classes: for
  * each step kernel, avg_ms is the sum over classes of its average launch time
  * (the time that kernel takes per step for the whole batch), bytes_per_launch the

@@ -28,7 +28,7 @@ EXPORTS = [
     "spfc_batch_step_count", "spfc_batch_status", "spfc_batch_mass", "spfc_batch_energy", "spfc_batch_history",
     "spfc_batch_get_phi", "spfc_batch_destroy", "spfc_batch_profile", "spfc_batch_kernel_times",
     "spfc_tune_bytes", "spfc_tune", "spfc_get_plan", "spfc_batch_tune_bytes", "spfc_batch_tune",
-    "spfc_batch_get_plan",
+    "spfc_batch_get_plan", "spfc_time_kernels", "spfc_batch_time_kernels",
 ]
 
 
@@ -107,6 +107,8 @@ def load_library(path: str | None = None):
         "spfc_batch_tune_bytes": [vp, P(sz)],
         "spfc_batch_tune": [vp, dbl, i64, vp, sz],
         "spfc_batch_get_plan": [vp, i32, P(i32)],
+        "spfc_time_kernels": [vp, dbl, i32, vp, sz],
+        "spfc_batch_time_kernels": [vp, dbl, i32, vp, sz],
         "spfc_batch_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
     }
     for name, args in sig.items():
@@ -339,6 +341,16 @@ def spfc_tune(ctx, dt: float, trial_steps: int, scratch_ptr: int, scratch_bytes:
     _check("spfc_tune", load_library().spfc_tune(ctx, float(dt), int(trial_steps), scratch_ptr, int(scratch_bytes)))
 
 
+def spfc_time_kernels(ctx, dt: float, reps: int, scratch_ptr: int, scratch_bytes: int):
+    _check("spfc_time_kernels", load_library().spfc_time_kernels(ctx, float(dt), int(reps), scratch_ptr,
+                                                                 int(scratch_bytes)))
+
+
+def spfc_batch_time_kernels(b, dt: float, reps: int, scratch_ptr: int, scratch_bytes: int):
+    _check("spfc_batch_time_kernels", load_library().spfc_batch_time_kernels(b, float(dt), int(reps), scratch_ptr,
+                                                                             int(scratch_bytes)))
+
+
 def _plan(arr):
     keys = ("inv", "real", "fwd", "mid")
     return {k: (arr[2 * i], arr[2 * i + 1]) for i, k in enumerate(keys) if arr[2 * i]}
@@ -475,6 +487,15 @@ class Solver:
     def plan(self):
         return spfc_get_plan(self.ctx)
 
+    def time_kernels(self, dt, reps=20):
+        """Per-launch kernel durations of a steady step (back-to-back launches; the run
+        state is kept); same entries as kernel_times()."""
+        nb = spfc_tune_bytes(self.ctx)
+        scratch = self.torch.empty(nb, dtype=self.torch.uint8, device="cuda")
+        spfc_time_kernels(self.ctx, dt, reps, scratch.data_ptr(), nb)
+        del scratch
+        return spfc_kernel_times(self.ctx)
+
     def profile(self, enable=True):
         spfc_profile(self.ctx, enable)
 
@@ -559,6 +580,13 @@ class Batch:
 
     def plan(self, m):
         return spfc_batch_get_plan(self.b, m)
+
+    def time_kernels(self, dt, reps=20):
+        nb = spfc_batch_tune_bytes(self.b)
+        scratch = self.torch.empty(nb, dtype=self.torch.uint8, device="cuda")
+        spfc_batch_time_kernels(self.b, dt, reps, scratch.data_ptr(), nb)
+        del scratch
+        return spfc_batch_kernel_times(self.b)
 
     def profile(self, enable=True):
         spfc_batch_profile(self.b, enable)

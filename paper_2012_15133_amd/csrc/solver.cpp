@@ -234,7 +234,13 @@ struct spfc_ctx {
     // profiling
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    struct EvUse {
+        int role, reps;
+        hipEvent_t a, b;
+    };
+    std::vector<EvUse> ev_used;
+    int reps;            // launches per timed kernel call (1; more in spfc_time_kernels)
+    int64_t timed_from;  // first step of a call whose kernels are timed
     double role_ms[R_COUNT];
     int64_t role_n[R_COUNT];
 
@@ -292,31 +298,36 @@ int drain_events(spfc_ctx* ctx) {
     CK(hipStreamSynchronize(ctx->stream));
     for (auto& u : ctx->ev_used) {
         float ms = 0.f;
-        CK(hipEventElapsedTime(&ms, u.second.first, u.second.second));
-        ctx->role_ms[u.first] += ms;
-        ctx->role_n[u.first] += 1;
-        ctx->ev_pool.push_back(u.second.first);
-        ctx->ev_pool.push_back(u.second.second);
+        CK(hipEventElapsedTime(&ms, u.a, u.b));
+        ctx->role_ms[u.role] += ms / u.reps;
+        ctx->role_n[u.role] += 1;
+        ctx->ev_pool.push_back(u.a);
+        ctx->ev_pool.push_back(u.b);
     }
     ctx->ev_used.clear();
     return SPFC_OK;
 }
 
+// HIP events around the launches of one kernel role on the context stream.
+// reps() launches go between the two events (more than one only inside
+// spfc_time_kernels, which restores the run state afterwards).
 struct Timed {
     spfc_ctx* ctx;
     int role;
+    bool on;
     hipEvent_t a = nullptr, b = nullptr;
-    Timed(spfc_ctx* c, int r, bool on) : ctx(c), role(r) {
-        if (on && ctx->profiling) {
+    Timed(spfc_ctx* c, int r, bool timed) : ctx(c), role(r), on(timed && c->profiling) {
+        if (on) {
             a = take_event(ctx);
             b = take_event(ctx);
             if (a && b) (void)hipEventRecord(a, ctx->stream);
         }
     }
+    int reps() const { return on ? ctx->reps : 1; }
     ~Timed() {
         if (a && b) {
             (void)hipEventRecord(b, ctx->stream);
-            ctx->ev_used.push_back({role, {a, b}});
+            ctx->ev_used.push_back({role, reps(), a, b});
         }
     }
 };
@@ -420,7 +431,8 @@ struct Pipe {
         a.geos = ctx->dgeos();
         {
             Timed tm(ctx, R_SPEC_INV, timed);
-            CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, ctx->stab, a, ctx->sh.A, ctx->stream));
+            for (int r = 0; r < tm.reps(); ++r)
+                CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, ctx->stab, a, ctx->sh.A, ctx->stream));
         }
         if (a.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
@@ -441,7 +453,7 @@ struct Pipe {
         a.G = s.G;
         a.fs = ctx->lay.fs;
         Timed tm(ctx, role, timed);
-        CK(Kern<T>::pass(ctx->sz.ny, dir, OUT_SWAP, 3, a, s, ctx->stream));
+        for (int r = 0; r < tm.reps(); ++r) CK(Kern<T>::pass(ctx->sz.ny, dir, OUT_SWAP, 3, a, s, ctx->stream));
         return SPFC_OK;
     }
 
@@ -460,7 +472,8 @@ struct Pipe {
         a.fs = ctx->lay.fs;
         a.geos = ctx->dgeos();
         Timed tm(ctx, R_REAL, timed);
-        CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, a, ctx->sh.B, ctx->stream));
+        for (int r = 0; r < tm.reps(); ++r)
+            CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, a, ctx->sh.B, ctx->stream));
         return SPFC_OK;
     }
 
@@ -488,7 +501,8 @@ struct Pipe {
         a.fs = ctx->lay.fs;
         a.geos = ctx->dgeos();
         Timed tm(ctx, R_SPEC_FWD, timed);
-        CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, ctx->stab, a, ctx->sh.Cf, ctx->stream));
+        for (int r = 0; r < tm.reps(); ++r)
+            CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, ctx->stab, a, ctx->sh.Cf, ctx->stream));
         return SPFC_OK;
     }
 
@@ -517,7 +531,7 @@ struct Pipe {
         f.geos = ctx->dgeos();
         {
             Timed tm(ctx, R_FINAL, timed);
-            CK(launch_finalize(f, ctx->M, ctx->stream));
+            for (int r = 0; r < tm.reps(); ++r) CK(launch_finalize(f, ctx->M, ctx->stream));
         }
         if (mode == FIN_STEP) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
@@ -679,8 +693,9 @@ struct Pipe {
             }
             const bool sav1 = first_order && i == 0;
             const int check = (i == 0 && restart) ? 0 : 1;
-            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, true);
-            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, true);
+            const bool timed = i >= ctx->timed_from;
+            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, timed);
+            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, timed);
             if (rc) return rc;
             ++i;
         }
@@ -864,6 +879,8 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     set_plan(ctx, ctx->plan);
     ctx->use_graph = false;
     ctx->profiling = false;
+    ctx->reps = 1;
+    ctx->timed_from = 0;
     for (int i = 0; i < R_COUNT; ++i) {
         ctx->role_ms[i] = 0;
         ctx->role_n[i] = 0;
@@ -894,8 +911,8 @@ void free_ctx(spfc_ctx* ctx) {
     if (!ctx->broken) (void)hipStreamSynchronize(ctx->stream);
     drop_graph(ctx);
     for (auto& u : ctx->ev_used) {
-        (void)hipEventDestroy(u.second.first);
-        (void)hipEventDestroy(u.second.second);
+        (void)hipEventDestroy(u.a);
+        (void)hipEventDestroy(u.b);
     }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -1119,6 +1136,35 @@ int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
     return SPFC_OK;
 }
 
+// Per-launch duration of each step kernel in a steady step: from a snapshot, one
+// untimed step, then one step in which every kernel is launched `reps` times back
+// to back between two events (repeats of the update kernel overwrite the older
+// state, so the run state is restored from the snapshot afterwards).
+int time_ctx(spfc_ctx* ctx, double dt, int reps, char* snap) {
+    HostState hs;
+    int rc;
+    if ((rc = snapshot(ctx, snap, hs))) return rc;
+    if ((rc = drain_events(ctx))) return rc;
+    const bool was = ctx->profiling;
+    for (int i = 0; i < R_COUNT; ++i) {
+        ctx->role_ms[i] = 0;
+        ctx->role_n[i] = 0;
+    }
+    if ((rc = ctx_step(ctx, dt, 2))) return rc;   // steady, same dt
+    ctx->profiling = true;
+    ctx->reps = reps;
+    ctx->timed_from = 1;
+    rc = ctx_step(ctx, dt, 2);
+    ctx->profiling = was;
+    ctx->reps = 1;
+    ctx->timed_from = 0;
+    if (rc) return rc;
+    if ((rc = drain_events(ctx))) return rc;
+    if ((rc = restore(ctx, snap, hs))) return rc;
+    CK(hipStreamSynchronize(ctx->stream));
+    return SPFC_OK;
+}
+
 // values per thread and threads per workgroup the step kernels actually use
 void get_plan(const spfc_ctx* ctx, int* out) {
     const LaunchShape* sh[4] = {&ctx->sh.A, &ctx->sh.B, &ctx->sh.Cf, &ctx->sh.midI};
@@ -1329,6 +1375,14 @@ int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, 
     return tune_ctx(ctx, dt, trial_steps, reinterpret_cast<char*>(scratch_dev));
 }
 
+int spfc_time_kernels(spfc_ctx* ctx, double dt, int reps, void* scratch_dev, size_t scratch_bytes) {
+    if (!ctx || !scratch_dev || reps < 1) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return SPFC_E_INVAL;
+    if (scratch_bytes < snapshot_bytes(ctx)) return SPFC_E_NOMEM;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    return time_ctx(ctx, dt, reps, reinterpret_cast<char*>(scratch_dev));
+}
+
 int spfc_get_plan(spfc_ctx* ctx, int* plan8) {
     if (!ctx || !plan8) return SPFC_E_INVAL;
     get_plan(ctx, plan8);
@@ -1489,6 +1543,15 @@ int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch
     if (!(dt > 0.0) || !std::isfinite(dt) || trial_steps < 1) return SPFC_E_INVAL;
     for (auto* c : b->cls) {
         const int rc = spfc_tune(c, dt, trial_steps, scratch_dev, scratch_bytes);
+        if (rc) return rc;
+    }
+    return SPFC_OK;
+}
+
+int spfc_batch_time_kernels(spfc_batch* b, double dt, int reps, void* scratch_dev, size_t scratch_bytes) {
+    if (!b) return SPFC_E_INVAL;
+    for (auto* c : b->cls) {
+        const int rc = spfc_time_kernels(c, dt, reps, scratch_dev, scratch_bytes);
         if (rc) return rc;
     }
     return SPFC_OK;

@@ -216,3 +216,27 @@ def test_batch_tune_then_step_matches_untuned_members():
         for x, y in zip(b.history(i, 0, 26), hist):
             assert abs(x["energy"] - y["energy"]) <= 1e-13 * abs(y["energy"])
     b.close()
+
+
+def test_time_kernels_keeps_the_run_state():
+    """Back-to-back kernel timing perturbs the older state while it runs and restores
+    the snapshot afterwards: the run continues bit for bit as an untimed run."""
+    from paper_2012_15133_amd import Solver
+    n, L = (128, 128), (16 * math.pi,) * 2
+    phi0 = noise_ic((128, 128), -0.2, 14)
+    a = Solver(n, L, phi0, 0.25, history=64)
+    b = Solver(n, L, phi0, 0.25, history=64)
+    a.step(0.01, 12)
+    b.step(0.01, 12)
+    kt = a.time_kernels(0.01, reps=5)
+    names = {k["name"] for k in kt}
+    assert {"spec_inv", "real_pass", "spec_fwd"} <= names
+    assert all(k["avg_ms"] > 0 and k["launches"] == 1 for k in kt if k["name"] != "step_finalize")
+    assert a.step_count() == 12
+    a.step(0.01, 9)
+    b.step(0.01, 9)
+    assert np.array_equal(a.phi().cpu().numpy(), b.phi().cpu().numpy())
+    assert a.history(0, 22) == b.history(0, 22)
+    assert a.status() == b.status()
+    a.close()
+    b.close()
