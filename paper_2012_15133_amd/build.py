@@ -1,4 +1,5 @@
-"""Build the HIP library libspfc.so for gfx950 (in-tree, next to this file).
+"""Build the HIP libraries libspfc.so (SAV-BDF2 stepper) and libspfc_fno.so (FNO
+surrogate) for gfx950, in-tree next to this file.
 
 Usage: python -m paper_2012_15133_amd.build [--jobs N]
 """
@@ -17,6 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libspfc.so")
+FNO_SRC = os.path.join(HERE, "fno")
+FNO_LIB = os.path.join(HERE, "libspfc_fno.so")
+FNO_SOURCES = ["fno_kernels.hip", "fno.cpp"]
 SOURCES = [f"kern_{p}_{k}.hip" for p in ("f64", "f32") for k in ("inv", "real", "fwd", "aux")] + [
     "finalize.hip", "solver.cpp"]
 
@@ -39,20 +43,25 @@ def _run(cmd):
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile both libraries (all objects in one pool); returns the stepper's path."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    cmds = []
+    objs, fobjs, cmds = [], [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    for src in FNO_SOURCES:
+        obj = os.path.join(BUILD, "fno_" + os.path.splitext(src)[0] + ".o")
+        fobjs.append(obj)
+        cmds.append([HIPCC, *FLAGS, "-I", FNO_SRC, "-c", os.path.join(FNO_SRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=jobs or min(len(cmds), os.cpu_count() or 1)) as ex:
         for out in ex.map(_run, cmds):
             if verbose and out:
                 print(out)
-    tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
+    for lib, ob in ((LIB, objs), (FNO_LIB, fobjs)):
+        tmp = lib + ".tmp"
+        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *ob])
+        os.replace(tmp, lib)
     return LIB
 
 
@@ -72,4 +81,5 @@ if __name__ == "__main__":
     ap.add_argument("-v", "--verbose", action="store_true")
     a = ap.parse_args()
     print(build(a.jobs, a.verbose))
+    print(FNO_LIB)
     sys.exit(0)

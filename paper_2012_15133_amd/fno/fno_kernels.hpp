@@ -1,0 +1,95 @@
+// Kernels of the Fourier-neural-operator surrogate (include/spfc_fno.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fno {
+
+constexpr int C = 32;                 // channels of the Fourier layers
+constexpr int MX = 16, MY = 16;       // retained kx, retained |ky| per sign
+constexpr int NMODE = MX * 2 * MY;    // 512
+constexpr int H = 64;                 // projection hidden width
+constexpr int LAYERS = 4;
+constexpr int TPB = 256;              // threads per workgroup of every kernel
+constexpr int GRED = 512;             // workgroups of the weight-gradient kernels
+
+// ---------------------------------------------------------------- parameter layout
+constexpr int64_t P_LW = 0, P_LB = 2 * C, P_L0 = P_LB + C;
+constexpr int64_t W_SIZE = (int64_t)NMODE * C * C;
+constexpr int64_t LAYER_SIZE = 2 * W_SIZE + C * C + C;
+__host__ __device__ constexpr int64_t p_wr(int l) { return P_L0 + l * LAYER_SIZE; }
+__host__ __device__ constexpr int64_t p_wi(int l) { return p_wr(l) + W_SIZE; }
+__host__ __device__ constexpr int64_t p_pw(int l) { return p_wi(l) + W_SIZE; }
+__host__ __device__ constexpr int64_t p_pb(int l) { return p_pw(l) + C * C; }
+constexpr int64_t P_Q1 = P_L0 + LAYERS * LAYER_SIZE, P_QB1 = P_Q1 + H * C, P_Q2 = P_QB1 + H, P_QB2 = P_Q2 + H;
+constexpr int64_t P_TOTAL = P_QB2 + 1;
+
+// sizes of the per-workgroup weight-gradient partials
+constexpr int PART_PW = C * C + C;          // Pw, Pb of one layer
+constexpr int PART_PROJ = H * C + H + H + 1;  // Q1, q1, Q2, q2
+constexpr int PART_LIFT = 2 * C + C;        // Lw, Lb
+constexpr int PART_MAX = PART_PROJ;
+
+// ---------------------------------------------------------------- bfloat16 storage
+__host__ __device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite values)
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+template <typename T>
+__device__ inline float ldf(const T* p, size_t i);
+template <>
+__device__ inline float ldf<float>(const float* p, size_t i) { return p[i]; }
+template <>
+__device__ inline float ldf<uint16_t>(const uint16_t* p, size_t i) { return bf2f(p[i]); }
+
+// gelu(z) = z Phi(z), Phi the standard normal distribution function; and its derivative
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// ---------------------------------------------------------------- kernel declarations
+// (definitions in fno_kernels.hip; launch helpers for the host below)
+
+struct Twid {
+    const float2* tw;   // N entries: (cos, sin)(2 pi j / N)
+};
+
+hipError_t launch_lift(int n, int batch, const float* phi, const float* eps, const float* prm, uint16_t* v0,
+                       hipStream_t st);
+// planes P = batch * C; out [NMODE][P]; scale s0 for kx = 0, s1 otherwise
+hipError_t launch_analysis_bf16(int n, int planes, const uint16_t* in, float s0, float s1, float2* out,
+                                const float2* tw, hipStream_t st);
+hipError_t launch_analysis_f32(int n, int planes, const float* in, float s0, float s1, float2* out, const float2* tw,
+                               hipStream_t st);
+hipError_t launch_synthesis(int n, int planes, const float2* in, float s0, float s1, float* out, int accumulate,
+                            const float2* tw, hipStream_t st);
+enum { MIX_FWD = 0, MIX_BWD_DATA = 1, MIX_BWD_WEIGHT = 2 };
+// FWD: out = mix(a) with packed weights wpk [NMODE][64][64] bf16.
+// BWD_DATA: out = gradient with respect to the mixing input, from a = gradient of its output.
+// BWD_WEIGHT: gWr/gWi = weight gradients from a = mixing input, g = gradient of its output.
+hipError_t launch_mix(int mode, int batch, const float2* a, const float2* g, const uint16_t* wpk, float2* out,
+                      float* gwr, float* gwi, hipStream_t st);
+hipError_t launch_pack_weights(const float* wr, const float* wi, uint16_t* wpk, hipStream_t st);
+hipError_t launch_pointwise(int n, int batch, bool act, const float* w, const uint16_t* v, const float* pw,
+                            const float* pb, uint16_t* vout, uint16_t* uout, hipStream_t st);
+hipError_t launch_project(int n, int batch, const uint16_t* v4, const float* prm, float* out_raw, float* part,
+                          hipStream_t st);
+hipError_t launch_finish(int n, int batch, const float* phi, const float* out_raw, const float* part,
+                         const float* target, float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st);
+hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gpred,
+                              const float* gpart, float* gv, float* partials, hipStream_t st);
+hipError_t launch_pointwise_bwd(int n, int batch, bool act, const float* gout, const uint16_t* u, const uint16_t* v,
+                                const float* pw, float* gu, float* gv, float* partials, hipStream_t st);
+hipError_t launch_lift_bwd(int n, int batch, const float* gv0, const float* phi, const float* eps, float* partials,
+                           hipStream_t st);
+hipError_t launch_reduce(const float* partials, int nrows, int cnt, float scale, float* dst, hipStream_t st);
+hipError_t launch_adam(int64_t count, float* prm, const float* grad, float* m, float* v, float lr, float c1,
+                       float c2, hipStream_t st);
+
+}  // namespace fno

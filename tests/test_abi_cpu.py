@@ -156,3 +156,38 @@ def test_line_fft_schedule_matches_dft(fp32, n, e):
             err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
             # FFT rounding grows like eps * log2(n)
             assert err <= (4e-7 if fp32 else 2e-15 * np.log2(n)), (n, sign, c, err)
+
+
+def test_fno_header_declares_and_library_exports_all():
+    header = os.path.join(ROOT, "include", "spfc_fno.h")
+    decl = set(re.findall(r"\b(spfc_fno_[a-z_]+)\s*\(", open(header).read()))
+    _lib()
+    from paper_2012_15133_amd import surrogate as S
+    assert set(S.EXPORTS) == decl
+    lib = os.path.join(ROOT, "paper_2012_15133_amd", "libspfc_fno.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (spfc_fno_[a-z_]+)", out))
+    assert decl <= exported, decl - exported
+
+
+def test_fno_sizes_and_validation_without_a_device():
+    _lib()
+    from paper_2012_15133_amd import surrogate as S
+    assert S.spfc_fno_param_count() == sum(int(np.prod(s)) for _, s in S.param_layout()) == 4200801
+    small = S.spfc_fno_workspace_bytes(S.spfc_fno_shape(64, 4, 0))
+    train = S.spfc_fno_workspace_bytes(S.spfc_fno_shape(64, 4, 1))
+    big = S.spfc_fno_workspace_bytes(S.spfc_fno_shape(256, 64, 1))
+    assert small < train < big
+    lib = S.load_library()
+    n = ctypes.c_size_t()
+    for bad in ((100, 4, 0), (64, 0, 0), (64, 129, 0), (64, 4, 2), (512, 4, 0)):
+        assert lib.spfc_fno_workspace_bytes(ctypes.byref(S.spfc_fno_shape(*bad)), ctypes.byref(n)) == 1
+    h = ctypes.c_void_p()
+    assert lib.spfc_fno_init(ctypes.byref(S.spfc_fno_shape(64, 4, 0)), None, 256, 1 << 30, None,
+                             ctypes.byref(h)) == 1
+    assert lib.spfc_fno_init(ctypes.byref(S.spfc_fno_shape(64, 4, 0)), 256, 257, 1 << 30, None,
+                             ctypes.byref(h)) == 1
+    assert lib.spfc_fno_init(ctypes.byref(S.spfc_fno_shape(64, 4, 0)), 256, 256, 1024, None,
+                             ctypes.byref(h)) == 2
+    assert lib.spfc_fno_forward(None, 1, 256, 256, 256) == 1
+    assert lib.spfc_fno_destroy(None) == 1
