@@ -12,7 +12,8 @@ Network (a Fourier neural operator: lifting, Fourier layers, projection):
   layer l    u_l[o] = synth(mix_l(anal(v_l)))[o] + sum_i Pw_l[o,i] v_l[i] + Pb_l[o]
              v_{l+1} = gelu(u_l) for l < L-1, v_L = u_{L-1}
   projection h[k] = gelu(sum_c Q1[k,c] v_L[c] + q1[k]),  out = sum_k Q2[k] h[k] + q2
-  output     phi_pred = phi + out - mean(out)   (the mean of phi is kept exactly)
+  filter     out_f = synth(anal(out))   (the increment restricted to the retained modes)
+  output     phi_pred = phi + out_f - mean(out_f)   (the mean of phi is kept exactly)
 
 Truncated transforms on an N x N grid (x contiguous), retained modes
 kx in [0, MX) and ky in [0, MY) u [N - MY, N), mode index m = kx * 2MY + j with
@@ -164,6 +165,7 @@ def forward(s: FnoShape, p: dict, phi: torch.Tensor, eps: torch.Tensor, bf16: bo
         v = _q(v, bf16)
     hpre = torch.einsum("kc,bcyx->bkyx", p["Q1"], v) + p["q1"][None, :, None, None]
     out = torch.einsum("k,bkyx->byx", p["Q2"], gelu(hpre)) + p["q2"][0]
+    out = synthesis(s, analysis(s, out))
     return phi + out - out.mean(dim=(1, 2), keepdim=True)
 
 

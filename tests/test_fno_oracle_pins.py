@@ -100,3 +100,17 @@ def test_gradients_match_finite_differences():
             fd = (float(F.mse(F.forward(S, tp, phi, eps), tgt)) - float(F.mse(F.forward(S, tm, phi, eps), tgt))) / (2 * h)
             g = float(grads[name][idx])
             assert abs(fd - g) <= 1e-6 * max(1e-6, abs(g)) + 1e-12, (name, idx, fd, g)
+
+
+def test_output_is_band_limited():
+    """The increment phi_pred - phi lies in the retained modes (up to the unpaired
+    (0, -MY) entry, whose synthesis keeps only its real-part pair)."""
+    p = F.init_params(S, 8)
+    phi, eps, _ = _batch(S)
+    d = (F.forward(S, p, phi, eps) - phi).numpy()
+    spec = np.fft.rfft2(d)
+    kx, ky = F.mode_indices(S)
+    mask = np.zeros(spec.shape[1:], bool)
+    mask[ky, kx] = True
+    mask[S.my, 0] = True      # conjugate partner of (0, -MY) in the kx = 0 column
+    assert np.max(np.abs(spec[:, ~mask])) <= 1e-12 * np.max(np.abs(spec))
