@@ -270,6 +270,29 @@ int spfc_batch_time_kernels(spfc_batch* b, double dt, int reps, void* scratch_de
 int spfc_batch_profile(spfc_batch* b, int enable);
 int spfc_batch_kernel_times(spfc_batch* b, int cap, const char** names, double* avg_ms,
                             int64_t* launches, double* bytes_per_launch, int* count);
+/* Start every member's run again from new fields phi_dev[member] (as spfc_batch_init,
+ * in the same workspace): step 0, the start-up mode on the next step, flags and
+ * history cleared.  For a jump of a surrogate model or a restart from outside data.
+ * The SAV variable of the new state (both levels of the pair) is sqrt(E_1(phi)) as at
+ * init, plus r_shift[member] when r_shift (host, one finite value per member) is given:
+ * a jump that keeps r - sqrt(E_1(phi)) of the state it leaves passes that difference.
+ * A member whose shifted r would not be positive keeps sqrt(E_1(phi)) and the call
+ * returns SPFC_E_INVAL after resetting every member.  The fields are not copied to the
+ * host for a finiteness check (unlike init): a non-finite field sets the member's
+ * NONFINITE flag in the E_1 pass of the restart.  Synchronizes.
+ * Errors: SPFC_E_INVAL (null pointer, r_shift not finite, shifted r not positive),
+ * SPFC_E_DEVICE. */
+int spfc_batch_reset(spfc_batch* b, const double* const* phi_dev, const double* r_shift);
+/* Every member's newest field into out_dev[member] (device, n_z x n_y x n_x, x fastest,
+ * dtype SPFC_FP64 or SPFC_FP32): spfc_batch_get_phi for all members, with one launch
+ * per transform pass for every 64 members of a grid size.  Queued on the batch's
+ * stream, does not synchronize.  Errors: SPFC_E_INVAL (null pointer, dtype),
+ * SPFC_E_DEVICE. */
+int spfc_batch_get_phi_all(spfc_batch* b, void* const* out_dev, int dtype);
+/* Energies of every member's current state (out: one entry per member) from one query
+ * pass per class.  Returns SPFC_E_NONFINITE if any member's NONFINITE flag is set (the
+ * entries are still filled).  Synchronizes. */
+int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out);
 /* Free the host side of the batch.  Does not touch caller memory. */
 int spfc_batch_destroy(spfc_batch* b);
 

@@ -9,7 +9,10 @@
  *               v_{l+1} = gelu(u) (l < 3),  v_4 = u (l = 3)
  *   projection  h[k] = gelu(sum_c Q1[k][c] v_4[c] + q1[k])  (k < 64),
  *               out = sum_k Q2[k] h[k] + q2
- *   output      phi_pred = phi + out - mean(out)  (keeps the mean of phi, as the SPFC
+ *   filter      out_f = synth(anal(out))  (the increment restricted to the retained modes:
+ *               the SPFC dynamics leaves nothing above them in 50 steps, and bf16 noise
+ *               there would raise the energy the fallback judges by)
+ *   output      phi_pred = phi + out_f - mean(out_f)  (keeps the mean of phi, as the SPFC
  *               dynamics does: Theorem 2.1 of the scheme)
  * on an N x N grid (x contiguous), N in {64, 128, 256}.  Truncated transforms with the
  * retained modes kx in [0,16), ky in [0,16) u [N-16, N) (512 modes, mode index
@@ -47,7 +50,7 @@ extern "C" {
 
 typedef struct spfc_fno spfc_fno;
 
-/* n: grid points per axis (64, 128 or 256); max_batch: samples per call (1..256);
+/* n: grid points per axis (64, 128 or 256); max_batch: samples per call (1..128);
  * train: 1 to also hold gradients, Adam moments and the activations backward needs. */
 typedef struct {
     int n;

@@ -28,7 +28,8 @@ EXPORTS = [
     "spfc_batch_step_count", "spfc_batch_status", "spfc_batch_mass", "spfc_batch_energy", "spfc_batch_history",
     "spfc_batch_get_phi", "spfc_batch_destroy", "spfc_batch_profile", "spfc_batch_kernel_times",
     "spfc_tune_bytes", "spfc_tune", "spfc_get_plan", "spfc_batch_tune_bytes", "spfc_batch_tune",
-    "spfc_batch_get_plan", "spfc_time_kernels", "spfc_batch_time_kernels",
+    "spfc_batch_get_plan", "spfc_time_kernels", "spfc_batch_time_kernels", "spfc_batch_reset",
+    "spfc_batch_energies", "spfc_batch_get_phi_all",
 ]
 
 
@@ -109,6 +110,9 @@ def load_library(path: str | None = None):
         "spfc_batch_get_plan": [vp, i32, P(i32)],
         "spfc_time_kernels": [vp, dbl, i32, vp, sz],
         "spfc_batch_time_kernels": [vp, dbl, i32, vp, sz],
+        "spfc_batch_reset": [vp, P(vp), P(dbl)],
+        "spfc_batch_energies": [vp, P(spfc_energy_t)],
+        "spfc_batch_get_phi_all": [vp, P(vp), i32],
         "spfc_batch_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
     }
     for name, args in sig.items():
@@ -379,6 +383,25 @@ def spfc_batch_get_plan(b, member: int) -> dict:
     return _plan(arr)
 
 
+def spfc_batch_reset(b, phi_ptrs, r_shift=None):
+    ptrs = (ctypes.c_void_p * len(phi_ptrs))(*phi_ptrs)
+    rr = None if r_shift is None else (ctypes.c_double * len(r_shift))(*[float(x) for x in r_shift])
+    _check("spfc_batch_reset", load_library().spfc_batch_reset(b, ptrs, rr))
+
+
+def spfc_batch_get_phi_all(b, out_ptrs, dtype: int = SPFC_FP64):
+    ptrs = (ctypes.c_void_p * len(out_ptrs))(*out_ptrs)
+    _check("spfc_batch_get_phi_all", load_library().spfc_batch_get_phi_all(b, ptrs, int(dtype)))
+
+
+def spfc_batch_energies(b, count: int, allow_nonfinite: bool = False) -> list:
+    buf = (spfc_energy_t * count)()
+    st = load_library().spfc_batch_energies(b, buf)
+    if not (st == SPFC_OK or (allow_nonfinite and st == SPFC_E_NONFINITE)):
+        _check("spfc_batch_energies", st)
+    return [{k: getattr(buf[i], k) for k, _ in spfc_energy_t._fields_} for i in range(count)]
+
+
 def spfc_batch_profile(b, enable: bool):
     _check("spfc_batch_profile", load_library().spfc_batch_profile(b, 1 if enable else 0))
 
@@ -562,6 +585,29 @@ class Batch:
 
     def history(self, m, first, count):
         return spfc_batch_history(self.b, m, first, count)
+
+    def reset(self, fields, r_shift=None):
+        """Start every member again from new fields (sequence of arrays or tensors); the
+        SAV variable is sqrt(E_1(field)) plus r_shift[m] when given."""
+        import numpy as np
+        torch = self.torch
+        dev = [_device_field(torch, np, f, tuple(reversed(n))) for f, n in zip(fields, self.ns)]
+        spfc_batch_reset(self.b, [d.data_ptr() for d in dev], r_shift)
+        del dev
+
+    def energies(self):
+        return spfc_batch_energies(self.b, len(self.ns))
+
+    def phi_all(self, out):
+        """Every member's field into out[m] (float32 or float64 device tensor of shape
+        [members, n_y, n_x]; all members of one grid size)."""
+        dt = SPFC_FP32 if out.dtype == self.torch.float32 else SPFC_FP64
+        if not out.is_contiguous() or out.shape[0] != len(self.ns):
+            raise ValueError("out must be a contiguous [members, n_y, n_x] tensor")
+        step = out[0].numel() * out.element_size()
+        spfc_batch_get_phi_all(self.b, [out.data_ptr() + m * step for m in range(len(self.ns))], dt)
+        self.stream.synchronize()
+        return out
 
     def phi(self, m, dtype="fp64"):
         torch = self.torch

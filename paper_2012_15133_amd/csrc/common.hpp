@@ -159,15 +159,19 @@ struct PassArgs {
     size_t fs;
 };
 
-// Real rows <-> half-spectrum rows (set-up and queries).
+// Real rows <-> half-spectrum rows (set-up and queries), for up to ROW_TAB members in
+// one launch: member y = blockIdx.y has its real field at real[y] (caller memory) and its
+// half spectrum at spec + y * fs (workspace).
+constexpr int ROW_TAB = 64;
 template <typename T>
 struct RowArgs {
-    const void* in;
-    void* out;
+    cpx<T>* spec;
+    size_t fs;
     const cpx<T>* tw;
     int tws;
     int nrows, G;
     double scale;
+    void* real[ROW_TAB];
 };
 
 // Pending update applied elementwise (end of a run of steps).

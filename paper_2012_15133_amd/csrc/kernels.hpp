@@ -712,7 +712,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * 2;
     const bool act = row0 < p.nrows;
-    const InT* in = reinterpret_cast<const InT*>(p.in);
+    const InT* in = reinterpret_cast<const InT*>(p.real[blockIdx.y]);
     cpx<T> v[1][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(RowArgs<T> p) {
     line_store<T, PL, 1>(v, lds, t);
     __syncthreads();
     if (!act) return;
-    cpx<T>* out = reinterpret_cast<cpx<T>*>(p.out);
+    cpx<T>* out = p.spec + (size_t)blockIdx.y * p.fs;
     const T half = T(0.5);
 #pragma unroll
     for (int m = 0; m <= E / 2; ++m) {
@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int row0 = (xcd_block(blockIdx.x, gridDim.x) * p.G + g) * 2;
     const bool act = row0 < p.nrows;
-    const cpx<T>* in = reinterpret_cast<const cpx<T>*>(p.in);
+    const cpx<T>* in = p.spec + (size_t)blockIdx.y * p.fs;
     const cpx<T>* h1 = in + (size_t)(act ? row0 : 0) * NXH;
     const cpx<T>* h2 = in + (size_t)(act ? row0 + 1 : 0) * NXH;
     cpx<T> v[1][E];
@@ -759,7 +759,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
     fft_run<T, PL, +1, 1>(v, lds, t, ltw);
     if (!act) return;
-    OutT* out = reinterpret_cast<OutT*>(p.out);
+    OutT* out = reinterpret_cast<OutT*>(p.real[blockIdx.y]);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int x = t + P * m;

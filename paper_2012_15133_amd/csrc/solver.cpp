@@ -267,6 +267,8 @@ struct spfc_ctx {
 struct spfc_batch {
     std::vector<spfc_ctx*> cls;
     std::vector<std::pair<int, int>> where;  // member -> (class, index within the class)
+    std::vector<std::vector<int>> members;   // class -> member indices
+    std::vector<size_t> npts;                // member -> grid points
 };
 
 namespace {
@@ -729,21 +731,30 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    // real field of member m (doubles, x fastest) -> its half spectrum in slot `s`
-    int forward_real(const double* phi, int s, int m) {
-        const size_t mo = ctx->moff(m);
-        RowArgs<T> r{};
-        r.in = phi;
-        r.out = ctx->bufA(0) + mo;
-        r.tw = (const C*)ctx->tw();
-        r.tws = ctx->lay.ntab / ctx->sz.nx;
-        r.nrows = ctx->sz.ny * ctx->sz.nz;
-        r.G = ctx->sh.r2c.G;
-        r.scale = 1.0;
-        CK(Kern<T>::r2c_rows(ctx->sz.nx, r, ctx->sh.r2c, ctx->stream));
+    // Real fields (doubles, x fastest) of members m0 .. m0 + count - 1 -> their half
+    // spectra in slot `s`; real[j] is member m0 + j's field.  One launch per pass for up
+    // to ROW_TAB members.
+    int forward_real(const double* const* real, int m0, int count, int s) {
+        for (int c0 = 0; c0 < count; c0 += ROW_TAB) {
+            const int cn = std::min(ROW_TAB, count - c0);
+            const size_t mo = ctx->moff(m0 + c0);
+            RowArgs<T> r{};
+            r.spec = (C*)(ctx->bufA(0) + mo);
+            r.fs = ctx->lay.fs;
+            r.tw = (const C*)ctx->tw();
+            r.tws = ctx->lay.ntab / ctx->sz.nx;
+            r.nrows = ctx->sz.ny * ctx->sz.nz;
+            r.G = ctx->sh.r2c.G;
+            r.scale = 1.0;
+            for (int j = 0; j < cn; ++j) r.real[j] = const_cast<double*>(real[c0 + j]);
+            LaunchShape rs = ctx->sh.r2c;
+            rs.members = cn;
+            CK(Kern<T>::r2c_rows(ctx->sz.nx, r, rs, ctx->stream));
+        }
         PassArgs<T> p{};
         p.tw = (const C*)ctx->tw();
-        p.fs = 0;
+        p.fs = ctx->lay.fs;
+        const size_t mo = ctx->moff(m0);
         if (ctx->sz.dim == 3) {
             // [X][Z][Y] -> transform y -> [X][Y][Z]
             p.in[0] = (const C*)(ctx->bufA(0) + mo);
@@ -752,7 +763,9 @@ struct Pipe {
             p.nlines = ctx->sz.nxh * ctx->sz.nz;
             p.B = ctx->sz.nz;
             p.G = ctx->sh.swapInit.G;
-            CK(Kern<T>::pass(ctx->sz.ny, -1, OUT_SWAP, 1, p, ctx->sh.swapInit, ctx->stream));
+            LaunchShape ss = ctx->sh.swapInit;
+            ss.members = count;
+            CK(Kern<T>::pass(ctx->sz.ny, -1, OUT_SWAP, 1, p, ss, ctx->stream));
             p.in[0] = (const C*)(ctx->bufB(0) + mo);
         } else {
             p.in[0] = (const C*)(ctx->bufA(0) + mo);
@@ -762,24 +775,28 @@ struct Pipe {
         p.nlines = ctx->nlines();
         p.B = ctx->lineB();
         p.G = ctx->sh.keep.G;
-        CK(Kern<T>::pass(ctx->nl(), -1, OUT_KEEP, 1, p, ctx->sh.keep, ctx->stream));
+        LaunchShape ks = ctx->sh.keep;
+        ks.members = count;
+        CK(Kern<T>::pass(ctx->nl(), -1, OUT_KEEP, 1, p, ks, ctx->stream));
         return SPFC_OK;
     }
 
-    // half spectrum of member m's newest state -> real field
-    int inverse_real(int m, void* out, bool out_fp32) {
-        const size_t mo = ctx->moff(m);
+    // half spectra of members m0 .. m0 + count - 1's newest state -> real fields out[j]
+    int inverse_real(int m0, int count, void* const* out, bool out_fp32) {
+        const size_t mo = ctx->moff(m0);
         PassArgs<T> p{};
         p.tw = (const C*)ctx->tw();
-        p.fs = 0;
+        p.fs = ctx->lay.fs;
         p.in[0] = (const C*)(ctx->slot(ctx->slotX) + mo);
         p.out[0] = (C*)(ctx->bufA(0) + mo);
         p.tws = ctx->lay.ntab / ctx->nl();
         p.nlines = ctx->nlines();
         p.B = ctx->lineB();
         p.G = ctx->sh.rot.G;
-        CK(Kern<T>::pass(ctx->nl(), +1, OUT_ROTATE, 1, p, ctx->sh.rot, ctx->stream));
-        const char* rows = ctx->bufA(0) + mo;
+        LaunchShape rs = ctx->sh.rot;
+        rs.members = count;
+        CK(Kern<T>::pass(ctx->nl(), +1, OUT_ROTATE, 1, p, rs, ctx->stream));
+        char* rows = ctx->bufA(0);
         if (ctx->sz.dim == 3) {
             // [Z][X][Y] -> transform y -> [Z][Y][X]
             p.in[0] = (const C*)(ctx->bufA(0) + mo);
@@ -788,18 +805,26 @@ struct Pipe {
             p.nlines = ctx->sz.nz * ctx->sz.nxh;
             p.B = ctx->sz.nxh;
             p.G = ctx->sh.swapGet.G;
-            CK(Kern<T>::pass(ctx->sz.ny, +1, OUT_SWAP, 1, p, ctx->sh.swapGet, ctx->stream));
-            rows = ctx->bufB(0) + mo;
+            LaunchShape ss = ctx->sh.swapGet;
+            ss.members = count;
+            CK(Kern<T>::pass(ctx->sz.ny, +1, OUT_SWAP, 1, p, ss, ctx->stream));
+            rows = ctx->bufB(0);
         }
-        RowArgs<T> r{};
-        r.in = rows;
-        r.out = out;
-        r.tw = (const C*)ctx->tw();
-        r.tws = ctx->lay.ntab / ctx->sz.nx;
-        r.nrows = ctx->sz.ny * ctx->sz.nz;
-        r.G = ctx->sh.c2r.G;
-        r.scale = ctx->geos[m].inv_npts;
-        CK(Kern<T>::c2r_rows(ctx->sz.nx, out_fp32, r, ctx->sh.c2r, ctx->stream));
+        for (int c0 = 0; c0 < count; c0 += ROW_TAB) {
+            const int cn = std::min(ROW_TAB, count - c0);
+            RowArgs<T> r{};
+            r.spec = (C*)(rows + ctx->moff(m0 + c0));
+            r.fs = ctx->lay.fs;
+            r.tw = (const C*)ctx->tw();
+            r.tws = ctx->lay.ntab / ctx->sz.nx;
+            r.nrows = ctx->sz.ny * ctx->sz.nz;
+            r.G = ctx->sh.c2r.G;
+            r.scale = ctx->geos[m0].inv_npts;   // one grid size per class
+            for (int j = 0; j < cn; ++j) r.real[j] = out[c0 + j];
+            LaunchShape cs = ctx->sh.c2r;
+            cs.members = cn;
+            CK(Kern<T>::c2r_rows(ctx->sz.nx, out_fp32, r, cs, ctx->stream));
+        }
         return SPFC_OK;
     }
 
@@ -893,8 +918,9 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
         rc = with_pipe(ctx, [&](auto& p) {
             int r;
             if ((r = p.write_tables())) return r;
-            for (int m = 0; m < M; ++m)
-                if ((r = p.forward_real(phi0[idx[m]], 0, m))) return r;
+            std::vector<const double*> in(M);
+            for (int m = 0; m < M; ++m) in[m] = phi0[idx[m]];
+            if ((r = p.forward_real(in.data(), 0, M, 0))) return r;
             // r^0 = sqrt(E_1(phi^0)) (after eq. scheme-SAV-initial-1)
             return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
         });
@@ -904,6 +930,29 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
         return rc;
     }
     *out = ctx;
+    return SPFC_OK;
+}
+
+// Start the run of every member of a class again from new fields (as at init): state
+// from the fields, step 0, start-up mode on the next step, flags and history cleared.
+int reset_ctx(spfc_ctx* ctx, const int* idx, const double* const* phi) {
+    if (ctx->broken) return SPFC_E_DEVICE;
+    drop_graph(ctx);
+    CK(hipMemsetAsync(ctx->ws + ctx->lay.off_sc, 0, ctx->lay.total - ctx->lay.off_sc, ctx->stream));
+    ctx->slotX = ctx->slotY = 0;
+    ctx->step = 0;
+    ctx->dt_prev = 0.0;
+    ctx->started = false;
+    ctx->cur_sc = 0;
+    int rc = with_pipe(ctx, [&](auto& p) {
+        int r;
+        std::vector<const double*> in(ctx->M);
+        for (int m = 0; m < ctx->M; ++m) in[m] = phi[idx[m]];
+        if ((r = p.forward_real(in.data(), 0, ctx->M, 0))) return r;
+        return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
+    });
+    if (rc) return rc;
+    CK(hipStreamSynchronize(ctx->stream));
     return SPFC_OK;
 }
 
@@ -994,7 +1043,8 @@ int ctx_history(spfc_ctx* ctx, int m, int64_t first, int64_t count, spfc_record*
 
 int ctx_get_phi(spfc_ctx* ctx, int m, void* out_dev, int dtype) {
     if (ctx->broken) return SPFC_E_DEVICE;
-    return with_pipe(ctx, [&](auto& p) { return p.inverse_real(m, out_dev, dtype == SPFC_FP32); });
+    void* out[1] = {out_dev};
+    return with_pipe(ctx, [&](auto& p) { return p.inverse_real(m, 1, out, dtype == SPFC_FP32); });
 }
 
 // members grouped by (dim, n, precision), classes in order of first appearance
@@ -1422,6 +1472,10 @@ int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params
     spfc_batch* b = new (std::nothrow) spfc_batch();
     if (!b) return SPFC_E_NOMEM;
     b->where.assign(count, {0, 0});
+    for (int i = 0; i < count; ++i) {
+        const Sizes s = sizes_of(grids[i], params[i].precision);
+        b->npts.push_back((size_t)s.nx * s.ny * s.nz);
+    }
     char* ws = reinterpret_cast<char*>(workspace_dev);
     for (size_t c = 0; c < classes.size(); ++c) {
         const auto& idx = classes[c];
@@ -1436,6 +1490,7 @@ int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params
         ws += class_bytes(grids[idx[0]], params[idx[0]], M);
         for (int k = 0; k < M; ++k) b->where[idx[k]] = {(int)c, k};
         b->cls.push_back(ctx);
+        b->members.push_back(idx);
     }
     *out = b;
     return SPFC_OK;
@@ -1561,6 +1616,84 @@ int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8) {
     if (!member_ok(b, member) || !plan8) return SPFC_E_INVAL;
     get_plan(b->cls[b->where[member].first], plan8);
     return SPFC_OK;
+}
+
+int spfc_batch_reset(spfc_batch* b, const double* const* phi_dev, const double* r_shift) {
+    if (!b || !phi_dev) return SPFC_E_INVAL;
+    for (size_t i = 0; i < b->npts.size(); ++i) {
+        if (!phi_dev[i]) return SPFC_E_INVAL;
+        if (r_shift && !std::isfinite(r_shift[i])) return SPFC_E_INVAL;
+    }
+    int worst = SPFC_OK;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        spfc_ctx* ctx = b->cls[c];
+        const int rc = reset_ctx(ctx, b->members[c].data(), phi_dev);
+        if (rc) return rc;
+        if (r_shift) {
+            // the restart pass left r = sqrt(E_1(phi)) in both levels of the pair
+            std::vector<DevScalars> sc(ctx->M);
+            CK(hipMemcpyAsync(sc.data(), ctx->sc(0), ctx->M * sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+            CK(hipStreamSynchronize(ctx->stream));
+            for (int m = 0; m < ctx->M; ++m) {
+                const double r = sc[m].r_n + r_shift[b->members[c][m]];
+                if (r > 0.0) {
+                    sc[m].r_n = sc[m].r_nm1 = r;
+                } else {
+                    worst = SPFC_E_INVAL;
+                }
+            }
+            CK(hipMemcpyAsync(ctx->sc(0), sc.data(), ctx->M * sizeof(DevScalars), hipMemcpyHostToDevice, ctx->stream));
+            CK(hipStreamSynchronize(ctx->stream));
+        }
+    }
+    return worst;
+}
+
+int spfc_batch_get_phi_all(spfc_batch* b, void* const* out_dev, int dtype) {
+    if (!b || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
+    for (size_t i = 0; i < b->npts.size(); ++i)
+        if (!out_dev[i]) return SPFC_E_INVAL;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        spfc_ctx* ctx = b->cls[c];
+        if (ctx->broken) return SPFC_E_DEVICE;
+        std::vector<void*> out(ctx->M);
+        for (int m = 0; m < ctx->M; ++m) out[m] = out_dev[b->members[c][m]];
+        const int rc = with_pipe(ctx, [&](auto& p) { return p.inverse_real(0, ctx->M, out.data(), dtype == SPFC_FP32); });
+        if (rc) return rc;
+    }
+    return SPFC_OK;
+}
+
+int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out) {
+    if (!b || !out) return SPFC_E_INVAL;
+    int worst = SPFC_OK;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        spfc_ctx* ctx = b->cls[c];
+        if (ctx->broken) return SPFC_E_DEVICE;
+        int rc = with_pipe(ctx, [&](auto& p) {
+            return p.e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FIN_QUERY);
+        });
+        if (rc) return rc;
+        std::vector<DevScalars> sc(ctx->M);
+        CK(hipMemcpyAsync(sc.data(), ctx->sc(0), ctx->M * sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        for (int m = 0; m < ctx->M; ++m) {
+            const Geo& g = ctx->geos[m];
+            const DevScalars& d = sc[m];
+            spfc_energy_t& e = out[b->members[c][m]];
+            const double rn = d.r_n, rm = d.r_nm1;
+            e.modified_energy = 0.25 * (d.q_norm[0] + d.q_norm[1]) + 0.5 * (rn * rn + (2 * rn - rm) * (2 * rn - rm)) +
+                                0.25 * g.stab * ctx->dt_prev * d.q_norm[4];
+            e.E1 = d.q_E1;
+            e.energy = d.q_E1 - g.e1_const + 0.5 * g.a * d.q_norm[2] + 0.5 * d.q_norm[3];
+            e.sav_energy = 0.5 * g.a * d.q_norm[2] + 0.5 * d.q_norm[3] + rn * rn;
+            e.r = rn;
+            e.mean = d.mean;
+            e.step = ctx->step;
+            if (d.flags & SPFC_FLAG_NONFINITE) worst = SPFC_E_NONFINITE;
+        }
+    }
+    return worst;
 }
 
 int spfc_batch_destroy(spfc_batch* b) {

@@ -18,8 +18,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t prm, wpk, tw, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, part, lpart, gpart, partials, grad, m,
-        vv, total;
+    size_t prm, wpk, tw, bhi, blo, xp, zz, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, part, lpart, gpart,
+        partials, grad, m, vv, total;
     size_t field_bf, field_f, spec;   // bytes of one activation (bf16), one f32 field set, one spectrum set
 };
 
@@ -45,6 +45,10 @@ Layout layout_of(const spfc_fno_shape& s) {
     L.prm = take(P_TOTAL * sizeof(float));
     L.wpk = take((size_t)LAYERS * NMODE * 64 * 64 * sizeof(uint16_t));
     L.tw = take((size_t)s.n * sizeof(float2));
+    L.bhi = take((size_t)s.n * 2 * MX * sizeof(uint16_t));
+    L.blo = take((size_t)s.n * 2 * MX * sizeof(uint16_t));
+    L.xp = take(planes * s.n * MX * sizeof(float2));
+    L.zz = take(planes * s.n * MX * sizeof(float2));
     L.v = take((tr ? LAYERS + 1 : 2) * align_up(L.field_bf));
     L.u = take(tr ? LAYERS * align_up(L.field_bf) : 0);
     L.w = take(L.field_f);
@@ -59,7 +63,7 @@ Layout layout_of(const spfc_fno_shape& s) {
     L.part = take((size_t)s.max_batch * nwg * sizeof(float));
     L.lpart = take((size_t)s.max_batch * nwg * sizeof(float));
     L.gpart = take((size_t)s.max_batch * nwg * sizeof(float));
-    L.partials = take(tr ? (size_t)GRED * PART_MAX * sizeof(float) : 0);
+    L.partials = take(tr ? (size_t)GRED64 * PART_MAX * sizeof(float) : 0);
     L.grad = take(tr ? P_TOTAL * sizeof(float) : 0);
     L.m = take(tr ? P_TOTAL * sizeof(float) : 0);
     L.vv = take(tr ? P_TOTAL * sizeof(float) : 0);
@@ -95,6 +99,10 @@ struct spfc_fno {
     }
     float2* uh() const { return at<float2>(lay.uh); }
     float2* gvh() const { return at<float2>(lay.gvh); }
+    float2* xp() const { return at<float2>(lay.xp); }
+    float2* zz() const { return at<float2>(lay.zz); }
+    const uint16_t* bhi() const { return at<uint16_t>(lay.bhi); }
+    const uint16_t* blo() const { return at<uint16_t>(lay.blo); }
 };
 
 namespace {
@@ -120,18 +128,26 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     const float inv = 1.0f / ((float)n * (float)n);
     hipStream_t st = f->stream;
     const bool tr = f->shape.train != 0 && target;
-    CK(launch_lift(n, batch, phi, eps, f->prm(), f->v(0), st));
+    // rows: lifting + x-analysis; per layer: y-analysis, mixing, y-synthesis, then the row
+    // kernel (x-synthesis, pointwise, activation, next x-analysis)
+    CK(launch_row(n, batch, true, phi, eps, f->prm(), 0, nullptr, nullptr, f->v(0), nullptr, f->xp(), f->bhi(),
+                  f->blo(), f->tw(), st));
     for (int l = 0; l < LAYERS; ++l) {
-        CK(launch_analysis_bf16(n, planes, f->v(l), inv, inv, f->vh(l), f->tw(), st));
+        CK(launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->tw(), st));
         CK(launch_mix(MIX_FWD, batch, f->vh(l), nullptr, f->wpk(l), f->uh(), nullptr, nullptr, st));
-        CK(launch_synthesis(n, planes, f->uh(), 1.0f, 2.0f, f->w(), 0, f->tw(), st));
-        CK(launch_pointwise(n, batch, l < LAYERS - 1, f->w(), f->v(l), f->prm() + p_pw(l), f->prm() + p_pb(l),
-                            f->v(l + 1), tr ? f->u(l) : nullptr, st));
+        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, f->zz(), f->tw(), st));
+        CK(launch_row(n, batch, false, nullptr, nullptr, f->prm(), l, f->zz(), f->v(l), f->v(l + 1),
+                      tr ? f->u(l) : nullptr, l < LAYERS - 1 ? f->xp() : nullptr, f->bhi(), f->blo(), f->tw(), st));
     }
     float* out_raw = f->at<float>(f->lay.out_raw);
     float* part = f->at<float>(f->lay.part);
     CK(launch_project(n, batch, f->v(LAYERS), f->prm(), out_raw, part, st));
-    CK(launch_finish(n, batch, phi, out_raw, part, target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
+    // the increment restricted to the retained modes (one plane per sample); its mean is
+    // that of out_raw (the filter keeps the k = 0 mode)
+    float* out_f = f->w();
+    CK(launch_analysis_f32(n, batch, out_raw, inv, inv, f->uh(), f->tw(), st));
+    CK(launch_synthesis(n, batch, f->uh(), 1.0f, 2.0f, out_f, 0, f->tw(), st));
+    CK(launch_finish(n, batch, phi, out_f, part, target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
                      f->at<float>(f->lay.lpart), f->at<float>(f->lay.gpart), st));
     return OK;
 }
@@ -149,14 +165,19 @@ int backward(spfc_fno* f, int batch, const float* phi, const float* eps, const f
     CK(launch_reduce(f->at<float>(f->lay.lpart), batch * nwg, 1, inv / (float)batch, loss_dev, st));
     float* ga = f->at<float>(f->lay.ga);
     float* gb = f->at<float>(f->lay.gb);
-    CK(launch_project_bwd(n, batch, f->v(LAYERS), f->prm(), f->at<float>(f->lay.gpred), f->at<float>(f->lay.gpart),
-                          ga, partials, st));
-    CK(launch_reduce(partials, GRED, PART_PROJ, 1.0f, grad + P_Q1, st));
+    // adjoints of the mean restoration and of the filter (synth o anal)^T = anal^T synth^T
+    float* gcen = f->at<float>(f->lay.out_raw);
+    float* gout = f->at<float>(f->lay.pred);
+    CK(launch_center(n, batch, f->at<float>(f->lay.gpred), f->at<float>(f->lay.gpart), gcen, st));
+    CK(launch_analysis_f32(n, batch, gcen, 1.0f, 2.0f, f->uh(), f->tw(), st));
+    CK(launch_synthesis(n, batch, f->uh(), inv, inv, gout, 0, f->tw(), st));
+    CK(launch_project_bwd(n, batch, f->v(LAYERS), f->prm(), gout, ga, partials, st));
+    CK(launch_reduce(partials, GRED64, PART_PROJ, 1.0f, grad + P_Q1, st));
     for (int l = LAYERS - 1; l >= 0; --l) {
         float* gu = f->w();
         CK(launch_pointwise_bwd(n, batch, l < LAYERS - 1, ga, f->u(l), f->v(l), f->prm() + p_pw(l), gu, gb, partials,
                                 st));
-        CK(launch_reduce(partials, GRED, PART_PW, 1.0f, grad + p_pw(l), st));
+        CK(launch_reduce(partials, GRED64, PART_PW, 1.0f, grad + p_pw(l), st));
         // adjoint of the synthesis: analysis with the synthesis weights and no 1/N^2
         CK(launch_analysis_f32(n, planes, gu, 1.0f, 2.0f, f->uh(), f->tw(), st));
         CK(launch_mix(MIX_BWD_WEIGHT, batch, f->vh(l), f->uh(), nullptr, nullptr, grad + p_wr(l), grad + p_wi(l),
@@ -229,6 +250,9 @@ int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* wo
             return fail(E_DEVICE);
     }
     if (pack_all(f)) return fail(E_DEVICE);
+    if (launch_basis(shape->n, f->at<uint16_t>(lay.bhi), f->at<uint16_t>(lay.blo),
+                     f->stream) != hipSuccess)
+        return fail(E_DEVICE);
     if (hipStreamSynchronize(f->stream) != hipSuccess) return fail(E_DEVICE);
     *out = f;
     return OK;

@@ -235,6 +235,197 @@ __global__ void __launch_bounds__(TPB) k_mix(int batch, const float2* a, const f
     }
 }
 
+// ---------------------------------------------------------------- row / column form of the forward pass
+
+// X'[b][c][y][kx] = sum_x v[b][c][y][x] e^{-2 pi i kx x / N} (the x half of the analysis),
+// Z[b][o][y][kx] = sum_j s_kx U[kx][j] e^{+2 pi i ky y / N} (the y half of the synthesis).
+// Rows: one workgroup takes R = 256 / N rows (r, y) of one sample, thread = (r, x).
+
+// bf16 DFT basis for the x half of the analysis, split in two parts so that hi + lo
+// carries FP32 accuracy: B[x][n] = cos(2 pi n x / N) (n < 16), -sin(2 pi (n-16) x / N).
+__global__ void __launch_bounds__(TPB) k_basis(int n, uint16_t* hi, uint16_t* lo) {
+    for (int e = blockIdx.x * TPB + threadIdx.x; e < n * 2 * MX; e += gridDim.x * TPB) {
+        const int x = e / (2 * MX), c = e - x * 2 * MX;
+        const int k = c & 15;
+        const double a = 6.283185307179586476925286766559 * (double)((k * x) % n) / (double)n;
+        const float v = c < MX ? (float)cos(a) : -(float)sin(a);
+        const uint16_t h = f2bf(v);
+        hi[e] = h;
+        lo[e] = f2bf(v - bf2f(h));
+    }
+}
+
+// Row kernel.  LIFT: v = Lw phi + Lw eps + Lb.  LAYER: u = synth_x(Z) + Pw v + Pb,
+// v' = gelu(u) (act) or u, as one matrix-core product per row:
+//   u[o][x] = sum_k A[o][k] B[k][x],  A = [Re Z | Im Z | Pw] (32 x 64),
+//   B = [cos(kx x) ; -sin(kx x) ; v] (64 x N),
+// with A and the basis split into bf16 hi + lo parts (hi hi + lo hi + hi lo: FP32
+// accuracy; v is stored as bf16 already).  Stores v' (bf16), u (bf16, if uout) and, if
+// xout, X' = analysis_x(v') (bf16 v' times the hi + lo basis, FP32 sums).
+template <int N, bool LIFT>
+__global__ void __launch_bounds__(TPB) k_row(const float* phi, const float* eps, const float* prm, int layer,
+                                             const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout,
+                                             float2* xout, const uint16_t* bhi, const uint16_t* blo,
+                                             const float2* twg) {
+    constexpr int R = TPB / N;            // rows per workgroup
+    __shared__ uint16_t Zh[R * C * 2 * MX], Zl[R * C * 2 * MX];   // [r][o][k < 32]
+    __shared__ uint16_t Ph[C * C], Pl[C * C];                     // [o][i]
+    __shared__ float pb[C];
+    __shared__ uint16_t Vin[R * C * N];   // v of the rows [r][i][x]; later u
+    __shared__ uint16_t Vs[R * C * N];    // v' of the rows, [r][c][x]
+    const int t = threadIdx.x, r = t / N, x = t - r * N;
+    const int b = blockIdx.y, y0 = blockIdx.x * R, y = y0 + r;
+    const int npts = N * N;
+    const size_t base = (size_t)b * C * npts + (size_t)y * N + x;   // + c * npts
+    const int wave = t >> 6, lane = t & 63;
+    const int col = lane & 15, rb = 4 * (lane >> 4);
+    if constexpr (LIFT) {
+        const float f = phi[(size_t)b * npts + (size_t)y * N + x], e = eps[b];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            Vs[(r * C + c) * N + x] = f2bf(prm[P_LW + 2 * c] * f + prm[P_LW + 2 * c + 1] * e + prm[P_LB + c]);
+    } else {
+        const float* pw = prm + p_pw(layer);
+        for (int i = t; i < C * C; i += TPB) {
+            const float w = pw[i];
+            const uint16_t h = f2bf(w);
+            Ph[i] = h;
+            Pl[i] = f2bf(w - bf2f(h));
+        }
+        if (t < C) pb[t] = pw[C * C + t];
+        for (int i = t; i < R * C * MX; i += TPB) {
+            const int rr = i / (C * MX), rest = i - rr * C * MX, o = rest / MX, k = rest - o * MX;
+            const float2 z = Z[(((size_t)b * C + o) * N + y0 + rr) * MX + k];
+            const int a = (rr * C + o) * 2 * MX + k;
+            const uint16_t hr = f2bf(z.x), hi = f2bf(z.y);
+            Zh[a] = hr;
+            Zl[a] = f2bf(z.x - bf2f(hr));
+            Zh[a + MX] = hi;
+            Zl[a + MX] = f2bf(z.y - bf2f(hi));
+        }
+#pragma unroll
+        for (int i = 0; i < C; ++i) Vin[(r * C + i) * N + x] = v[base + (size_t)i * npts];
+        __syncthreads();
+        // tiles: per row 2 (o) x N/16 (x); R rows -> 32 tiles, 8 per wave
+        f32x4 acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int tile = wave * 8 + q;
+            const int rr = tile / (2 * N / 16), rest = tile - rr * (2 * N / 16);
+            const int mt = rest / (N / 16), x0 = (rest - mt * (N / 16)) * 16;
+            const uint16_t* zh = Zh + (rr * C + mt * 16) * 2 * MX;
+            const uint16_t* zl = Zl + (rr * C + mt * 16) * 2 * MX;
+            f32x4 a = {0.f, 0.f, 0.f, 0.f};
+            // k < 32: the x-synthesis of the row's coefficients
+            a = mma16x16x32(a, zh, 2 * MX, 1, bhi + x0 * 2 * MX, 1, 2 * MX);
+            a = mma16x16x32(a, zl, 2 * MX, 1, bhi + x0 * 2 * MX, 1, 2 * MX);
+            a = mma16x16x32(a, zh, 2 * MX, 1, blo + x0 * 2 * MX, 1, 2 * MX);
+            // k >= 32: the pointwise layer Pw v
+            const uint16_t* vb = Vin + rr * C * N + x0;
+            a = mma16x16x32(a, Ph + mt * 16 * C, C, 1, vb, N, 1);
+            a = mma16x16x32(a, Pl + mt * 16 * C, C, 1, vb, N, 1);
+            acc[q] = a;
+        }
+        __syncthreads();   // Vin is read by every wave above; it now takes u
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int tile = wave * 8 + q;
+            const int rr = tile / (2 * N / 16), rest = tile - rr * (2 * N / 16);
+            const int mt = rest / (N / 16), x0 = (rest - mt * (N / 16)) * 16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = mt * 16 + rb + j;
+                const float u = acc[q][j] + pb[o];
+                const int a = (rr * C + o) * N + x0 + col;
+                Vin[a] = f2bf(u);
+                Vs[a] = f2bf(layer < LAYERS - 1 ? gelu(u) : u);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        vout[base + (size_t)c * npts] = Vs[(r * C + c) * N + x];
+        if constexpr (!LIFT)
+            if (uout) uout[base + (size_t)c * npts] = Vin[(r * C + c) * N + x];
+    }
+    if (!xout) return;
+    // X'[(r, c)][n] = sum_x Vs[(r, c)][x] B[x][n]: M = R * 32 rows, 32 columns, K = N
+    constexpr int MT = R * C / 16, TILES = MT * 2;
+    for (int tile = wave; tile < TILES; tile += TPB / 64) {
+        const int mt = tile >> 1, nt = tile & 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < N; k0 += 32) {
+            acc = mma16x16x32(acc, Vs + mt * 16 * N + k0, N, 1, bhi + k0 * 2 * MX + nt * 16, 2 * MX, 1);
+            acc = mma16x16x32(acc, Vs + mt * 16 * N + k0, N, 1, blo + k0 * 2 * MX + nt * 16, 2 * MX, 1);
+        }
+        // D(row, col): row = (r, c), col n: n < 16 real part of kx = n, else imaginary of n - 16
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = mt * 16 + rb + j, rr = row / C, c = row - rr * C;
+            float* dst = reinterpret_cast<float*>(xout + (((size_t)b * C + c) * N + y0 + rr) * MX + col);
+            dst[nt] = acc[j];   // nt = 0: .x (real), 1: .y (imaginary)
+        }
+    }
+}
+
+// Column kernels, one workgroup per plane (b, c).  ANAL: V[m][plane] = s sum_y X'[y][kx] e^{-i ky y}.
+// SYNTH: Z[plane][y][kx] = sum_j s_kx U[m][plane] e^{+i ky y}.
+template <int N>
+__global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float2* xp, float s, float2* out,
+                                                  const float2* twg) {
+    __shared__ float2 tw[N];
+    __shared__ float2 X[N * MX];
+    const int t = threadIdx.x, p = blockIdx.x;
+    for (int i = t; i < N; i += TPB) tw[i] = twg[i];
+    for (int i = t; i < N * MX; i += TPB) X[i] = xp[(size_t)p * N * MX + i];
+    __syncthreads();
+    const int kx = t & 15;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = (t >> 4) + 16 * h;
+        const int ky = j < MY ? j : N - 2 * MY + j;
+        float re = 0.f, im = 0.f;
+#pragma unroll 8
+        for (int y = 0; y < N; ++y) {
+            const float2 a = X[y * MX + kx];
+            const float2 w = tw[(ky * y) & (N - 1)];
+            re += a.x * w.x + a.y * w.y;
+            im += a.y * w.x - a.x * w.y;
+        }
+        out[(size_t)(kx * 2 * MY + j) * planes + p] = make_float2(re * s, im * s);
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(TPB) k_col_synth(int planes, const float2* in, float s0, float s1, float2* zout,
+                                                   const float2* twg) {
+    constexpr int UP = 2 * MY + 1;   // padded row: the 16 kx of a wave fall in different banks
+    __shared__ float2 tw[N];
+    __shared__ float2 U[MX * UP];
+    const int t = threadIdx.x, p = blockIdx.x;
+    for (int i = t; i < N; i += TPB) tw[i] = twg[i];
+    for (int m = t; m < NMODE; m += TPB) {
+        const float sc = (m >> 5) == 0 ? s0 : s1;
+        const float2 u = in[(size_t)m * planes + p];
+        U[(m >> 5) * UP + (m & 31)] = make_float2(u.x * sc, u.y * sc);
+    }
+    __syncthreads();
+    const int kx = t & 15;
+    for (int y = t >> 4; y < N; y += 16) {
+        float re = 0.f, im = 0.f;
+#pragma unroll 8
+        for (int j = 0; j < 2 * MY; ++j) {
+            const int ky = j < MY ? j : N - 2 * MY + j;
+            const float2 w = tw[(ky * y) & (N - 1)];
+            const float2 u = U[kx * UP + j];
+            re += u.x * w.x - u.y * w.y;
+            im += u.x * w.y + u.y * w.x;
+        }
+        zout[((size_t)p * N + y) * MX + kx] = make_float2(re, im);
+    }
+}
+
 // Wm of every mode from the FP32 weights, as bf16: Wm[i][o] = Wr, Wm[i][32+o] = Wi,
 // Wm[32+i][o] = -Wi, Wm[32+i][32+o] = Wr.
 __global__ void __launch_bounds__(TPB) k_pack(const float* wr, const float* wi, uint16_t* wpk) {
@@ -281,10 +472,8 @@ __global__ void __launch_bounds__(TPB) k_pointwise(int npts, int act, const floa
 // out_raw[b][p] = sum_k Q2[k] gelu(sum_c Q1[k][c] v4[c] + q1[k]) + q2; part[b][wg] = sum over the workgroup
 __global__ void __launch_bounds__(TPB) k_project(int npts, const uint16_t* v4, const float* prm, float* out_raw,
                                                  float* part) {
-    __shared__ float q[H * C + H + H + 1];
     __shared__ float red[TPB / 64];
-    for (int i = threadIdx.x; i < H * C + H + H + 1; i += TPB) q[i] = prm[P_Q1 + i];
-    __syncthreads();
+    const float* q = prm + P_Q1;   // uniform: scalar loads
     const int b = blockIdx.y;
     const int p = blockIdx.x * TPB + threadIdx.x;
     float o = 0.f;
@@ -347,22 +536,34 @@ __global__ void __launch_bounds__(TPB) k_finish(int npts, int batch, const float
 // (chunk id = blockIdx.x, + GRED, ...; a chunk lies inside one sample), and write one
 // row of partial sums; launch_reduce adds the rows in a fixed order.
 
-// projection (workgroups of 64 threads, one point each per chunk of 64 points):
-// g_out = gpred - mean(gpred); recompute pre/h; gv4[c] = sum_k Q1[k][c] g_pre[k];
+// gout[b][p] = gpred[b][p] - mean_p(gpred[b]) (the adjoint of restoring the mean), the
+// mean from the per-workgroup sums gpart of the finish pass
+__global__ void __launch_bounds__(TPB) k_center(int npts, const float* gpred, const float* gpart, float* gout) {
+    __shared__ float mean_s;
+    const int b = blockIdx.y, nwg = gridDim.x;
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int w = 0; w < nwg; ++w) s += gpart[(size_t)b * nwg + w];
+        mean_s = s / (float)npts;
+    }
+    __syncthreads();
+    const size_t i = (size_t)b * npts + blockIdx.x * TPB + threadIdx.x;
+    gout[i] = gpred[i] - mean_s;
+}
+
+// projection (workgroups of 64 threads, one point each per chunk of 64 points): given
+// g_out (the gradient of the projection output), recompute pre/h; gv4[c] = sum_k Q1[k][c] g_pre[k];
 // partials: Q1 (g_pre v4), q1 (g_pre), Q2 (g_out h), q2 (g_out).  Thread t owns row k = t
 // of Q1 and q1[t], Q2[t]; thread 0 also q2.
 __global__ void __launch_bounds__(64) k_project_bwd(int npts, int batch, const uint16_t* v4, const float* prm,
-                                                    const float* gpred, const float* gpart, float* gv,
-                                                    float* partials) {
+                                                    const float* gouts, float* gv, float* partials) {
     constexpr int Q = 64;
-    __shared__ float q[H * C + H + H + 1];
     __shared__ float gp_s[H * Q];
     __shared__ float h_s[H * Q];
     __shared__ float x_s[C * Q];
     __shared__ float go_s[Q];
     const int t = threadIdx.x;
-    for (int i = t; i < H * C + H + H + 1; i += Q) q[i] = prm[P_Q1 + i];
-    const int nwf = npts / TPB;   // workgroups per sample of the finish pass (its partial sums)
+    const float* q = prm + P_Q1;   // uniform: scalar loads
     const int per = npts / Q, chunks = batch * per;
     float aQ1[C];
 #pragma unroll
@@ -372,10 +573,7 @@ __global__ void __launch_bounds__(64) k_project_bwd(int npts, int batch, const u
     for (int ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
         const int b = ch / per;
         const int p = (ch - b * per) * Q + t;
-        float gmean = 0.f;
-        for (int w = 0; w < nwf; ++w) gmean += gpart[(size_t)b * nwf + w];
-        gmean /= (float)npts;
-        const float go = gpred[(size_t)b * npts + p] - gmean;
+        const float go = gouts[(size_t)b * npts + p];
         const size_t base = (size_t)b * C * npts + p;
         float x[C], gx[C];
 #pragma unroll
@@ -473,49 +671,57 @@ __global__ void __launch_bounds__(64) k_pointwise_bwd(int npts, int batch, int a
     if ((t & 1) == 0) row[C * C + o] = ab;
 }
 
-// lifting: partials Lw[c][0] (g phi), Lw[c][1] (g eps), Lb[c] (g)
+// lifting: partials Lw[c][0] (g phi), Lw[c][1] (g eps), Lb[c] (g).  Each thread sums its
+// points; the workgroup then adds the 256 thread sums of each value in order.
 __global__ void __launch_bounds__(TPB) k_lift_bwd(int npts, int batch, const float* gv0, const float* phi,
                                                   const float* eps, float* partials) {
-    constexpr int Q = 64;
-    __shared__ float g_s[C * Q];
-    __shared__ float f_s[Q];
-    __shared__ float e_s;
+    __shared__ float red[TPB * (C + 1)];
     const int t = threadIdx.x;
     const int nwg = npts / TPB, chunks = batch * nwg;
-    const int c = t < 2 * C ? t >> 1 : t - 2 * C;
-    const int kind = t < 2 * C ? (t & 1) : 2;   // 0: phi, 1: eps, 2: bias
-    float acc = 0.f;
+    float a0[C], a1[C], a2[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) a0[c] = a1[c] = a2[c] = 0.f;
     for (int ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
         const int b = ch / nwg;
         const int p = (ch - b * nwg) * TPB + t;
         const size_t base = (size_t)b * C * npts + p;
-        for (int qq = 0; qq < TPB / Q; ++qq) {
-            __syncthreads();
-            if ((t / Q) == qq) {
-                const int pt = t - qq * Q;
+        const float f = phi[(size_t)b * npts + p], e = eps[b];
 #pragma unroll
-                for (int cc = 0; cc < C; ++cc) g_s[cc * Q + pt] = gv0[base + (size_t)cc * npts];
-                f_s[pt] = phi[(size_t)b * npts + p];
-            }
-            if (t == 0) e_s = eps[b];
-            __syncthreads();
-            if (t < 3 * C)
-                for (int pt = 0; pt < Q; ++pt) {
-                    const float g = g_s[c * Q + pt];
-                    acc += kind == 0 ? g * f_s[pt] : (kind == 1 ? g * e_s : g);
-                }
+        for (int c = 0; c < C; ++c) {
+            const float g = gv0[base + (size_t)c * npts];
+            a0[c] += g * f;
+            a1[c] += g * e;
+            a2[c] += g;
         }
     }
-    if (t < 3 * C) partials[(size_t)blockIdx.x * PART_LIFT + t] = acc;
+    float* row = partials + (size_t)blockIdx.x * PART_LIFT;
+    for (int kind = 0; kind < 3; ++kind) {
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) red[t * (C + 1) + c] = kind == 0 ? a0[c] : (kind == 1 ? a1[c] : a2[c]);
+        __syncthreads();
+        if (t < C) {
+            float sum = 0.f;
+            for (int i = 0; i < TPB; ++i) sum += red[i * (C + 1) + t];
+            if (kind < 2) row[2 * t + kind] = sum;
+            else row[2 * C + t] = sum;
+        }
+    }
 }
 
-// dst[j] = scale * sum_r partials[r][j] (rows in order)
+// dst[j] = scale * sum_r partials[r][j]: 64 columns per workgroup, four row slices
+// (coalesced over the columns), the slices added in order.
 __global__ void __launch_bounds__(TPB) k_reduce(const float* partials, int nrows, int cnt, float scale, float* dst) {
-    const int j = blockIdx.x * TPB + threadIdx.x;
-    if (j >= cnt) return;
+    __shared__ float part[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int r0 = (int)((long long)nrows * g / 4), r1 = (int)((long long)nrows * (g + 1) / 4);
     float s = 0.f;
-    for (int r = 0; r < nrows; ++r) s += partials[(size_t)r * cnt + j];
-    dst[j] = scale * s;
+    if (j < cnt)
+        for (int r = r0; r < r1; ++r) s += partials[(size_t)r * cnt + j];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < cnt) dst[j] = scale * (((part[0][c] + part[1][c]) + part[2][c]) + part[3][c]);
 }
 
 // Adam with bias correction: c1 = 1 - beta1^t, c2 = 1 - beta2^t
@@ -587,6 +793,42 @@ hipError_t launch_mix(int mode, int batch, const float2* a, const float2* g, con
     return hipGetLastError();
 }
 
+hipError_t launch_basis(int n, uint16_t* hi, uint16_t* lo, hipStream_t st) {
+    hipLaunchKernelGGL(k_basis, dim3((n * 2 * MX + TPB - 1) / TPB), dim3(TPB), 0, st, n, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_row(int n, int batch, bool lift, const float* phi, const float* eps, const float* prm, int layer,
+                      const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout, float2* xout,
+                      const uint16_t* bhi, const uint16_t* blo, const float2* tw, hipStream_t st) {
+    const dim3 g(n / (TPB / n), batch), b(TPB);
+#define FNO_ROW(NN)                                                                                               \
+    if (lift) hipLaunchKernelGGL((k_row<NN, true>), g, b, 0, st, phi, eps, prm, layer, Z, v, vout, uout, xout, bhi, \
+                                 blo, tw);                                                                         \
+    else hipLaunchKernelGGL((k_row<NN, false>), g, b, 0, st, phi, eps, prm, layer, Z, v, vout, uout, xout, bhi, blo, \
+                            tw);
+    switch (n) {
+        case 64: FNO_ROW(64) break;
+        case 128: FNO_ROW(128) break;
+        case 256: FNO_ROW(256) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FNO_ROW
+    return hipGetLastError();
+}
+
+hipError_t launch_col_anal(int n, int planes, const float2* xp, float s, float2* out, const float2* tw,
+                           hipStream_t st) {
+    FNO_LAUNCH_N(k_col_anal, dim3(planes), dim3(TPB), 0, st, planes, xp, s, out, tw)
+    return hipGetLastError();
+}
+
+hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, float2* zout, const float2* tw,
+                            hipStream_t st) {
+    FNO_LAUNCH_N(k_col_synth, dim3(planes), dim3(TPB), 0, st, planes, in, s0, s1, zout, tw)
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_weights(const float* wr, const float* wi, uint16_t* wpk, hipStream_t st) {
     hipLaunchKernelGGL(k_pack, dim3(NMODE), dim3(TPB), 0, st, wr, wi, wpk);
     return hipGetLastError();
@@ -615,15 +857,20 @@ hipError_t launch_finish(int n, int batch, const float* phi, const float* out_ra
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gpred,
-                              const float* gpart, float* gv, float* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_project_bwd, dim3(GRED), dim3(64), 0, st, n * n, batch, v4, prm, gpred, gpart, gv, partials);
+hipError_t launch_center(int n, int batch, const float* gpred, const float* gpart, float* gout, hipStream_t st) {
+    hipLaunchKernelGGL(k_center, dim3(n * n / TPB, batch), dim3(TPB), 0, st, n * n, gpred, gpart, gout);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gout, float* gv,
+                              float* partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_project_bwd, dim3(GRED64), dim3(64), 0, st, n * n, batch, v4, prm, gout, gv, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_pointwise_bwd(int n, int batch, bool act, const float* gout, const uint16_t* u, const uint16_t* v,
                                 const float* pw, float* gu, float* gv, float* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_pointwise_bwd, dim3(GRED), dim3(64), 0, st, n * n, batch, act ? 1 : 0, gout, u, v, pw, gu,
+    hipLaunchKernelGGL(k_pointwise_bwd, dim3(GRED64), dim3(64), 0, st, n * n, batch, act ? 1 : 0, gout, u, v, pw, gu,
                        gv, partials);
     return hipGetLastError();
 }
@@ -635,7 +882,7 @@ hipError_t launch_lift_bwd(int n, int batch, const float* gv0, const float* phi,
 }
 
 hipError_t launch_reduce(const float* partials, int nrows, int cnt, float scale, float* dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3((cnt + TPB - 1) / TPB), dim3(TPB), 0, st, partials, nrows, cnt, scale, dst);
+    hipLaunchKernelGGL(k_reduce, dim3((cnt + 63) / 64), dim3(TPB), 0, st, partials, nrows, cnt, scale, dst);
     return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ constexpr int NMODE = MX * 2 * MY;    // 512
 constexpr int H = 64;                 // projection hidden width
 constexpr int LAYERS = 4;
 constexpr int TPB = 256;              // threads per workgroup of every kernel
-constexpr int GRED = 512;             // workgroups of the weight-gradient kernels
+constexpr int GRED = 512;             // workgroups of the 256-thread weight-gradient kernels
+constexpr int GRED64 = 2048;          // workgroups of the 64-thread weight-gradient kernels
 
 // ---------------------------------------------------------------- parameter layout
 constexpr int64_t P_LW = 0, P_LB = 2 * C, P_L0 = P_LB + C;
@@ -76,14 +77,25 @@ enum { MIX_FWD = 0, MIX_BWD_DATA = 1, MIX_BWD_WEIGHT = 2 };
 hipError_t launch_mix(int mode, int batch, const float2* a, const float2* g, const uint16_t* wpk, float2* out,
                       float* gwr, float* gwi, hipStream_t st);
 hipError_t launch_pack_weights(const float* wr, const float* wi, uint16_t* wpk, hipStream_t st);
+// Row/column form of the forward pass (see fno_kernels.hip): basis tables, row kernel
+// (lifting or layer, with the next x-analysis), column halves of the transforms.
+hipError_t launch_basis(int n, uint16_t* hi, uint16_t* lo, hipStream_t st);
+hipError_t launch_row(int n, int batch, bool lift, const float* phi, const float* eps, const float* prm, int layer,
+                      const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout, float2* xout,
+                      const uint16_t* bhi, const uint16_t* blo, const float2* tw, hipStream_t st);
+hipError_t launch_col_anal(int n, int planes, const float2* xp, float s, float2* out, const float2* tw,
+                           hipStream_t st);
+hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, float2* zout, const float2* tw,
+                            hipStream_t st);
 hipError_t launch_pointwise(int n, int batch, bool act, const float* w, const uint16_t* v, const float* pw,
                             const float* pb, uint16_t* vout, uint16_t* uout, hipStream_t st);
 hipError_t launch_project(int n, int batch, const uint16_t* v4, const float* prm, float* out_raw, float* part,
                           hipStream_t st);
 hipError_t launch_finish(int n, int batch, const float* phi, const float* out_raw, const float* part,
                          const float* target, float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st);
-hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gpred,
-                              const float* gpart, float* gv, float* partials, hipStream_t st);
+hipError_t launch_center(int n, int batch, const float* gpred, const float* gpart, float* gout, hipStream_t st);
+hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gout, float* gv,
+                              float* partials, hipStream_t st);
 hipError_t launch_pointwise_bwd(int n, int batch, bool act, const float* gout, const uint16_t* u, const uint16_t* v,
                                 const float* pw, float* gu, float* gv, float* partials, hipStream_t st);
 hipError_t launch_lift_bwd(int n, int batch, const float* gv0, const float* phi, const float* eps, float* partials,

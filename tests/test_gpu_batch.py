@@ -240,3 +240,67 @@ def test_time_kernels_keeps_the_run_state():
     assert a.status() == b.status()
     a.close()
     b.close()
+
+
+def test_phi_all_equals_per_member_fields_bitwise():
+    """spfc_batch_get_phi_all (one launch per pass for every 64 members) gives what the
+    member-by-member call gives, for a class wider than one launch and a 3-D class."""
+    import torch
+    from paper_2012_15133_amd import Batch
+    from paper_2012_15133_amd.binding import SPFC_FP32, SPFC_FP64, spfc_batch_get_phi_all
+    specs = [((32, 32), (4 * math.pi,) * 2, 0.1 + 0.004 * k, -0.2, 100 + k, "fp64") for k in range(70)]
+    specs += [((16, 16, 16), (4 * math.pi,) * 3, 0.25, -0.25, 7 + k, "fp32") for k in range(2)]
+    members = _members(specs)
+    b = Batch(members, history=8)
+    b.step(0.01, 5)
+    for dt, code in (("fp64", SPFC_FP64), ("fp32", SPFC_FP32)):
+        outs = [torch.full(tuple(reversed(m["n"])), float("nan"), device="cuda",
+                           dtype=torch.float64 if dt == "fp64" else torch.float32) for m in members]
+        spfc_batch_get_phi_all(b.b, [o.data_ptr() for o in outs], code)
+        b.stream.synchronize()
+        for i in range(len(members)):
+            assert torch.equal(outs[i], b.phi(i, dt)), (dt, i)
+    same = torch.empty((70, 32, 32), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        b.phi_all(same)          # the batch holds two grid sizes
+    b.close()
+
+
+def test_reset_restarts_like_init_and_shifts_r():
+    import torch
+    from paper_2012_15133_amd import Batch
+    from paper_2012_15133_amd.binding import SpfcError
+    specs = [((64, 64), (8 * math.pi,) * 2, 0.1 + 0.05 * k, -0.2, 40 + k, "fp64") for k in range(4)]
+    members = _members(specs)
+    b = Batch(members, history=8)
+    b.step(0.01, 150)
+    before = b.energies()
+    fields = b.phi_all(torch.empty((4, 64, 64), dtype=torch.float64, device="cuda"))
+    fields = [fields[m].clone() for m in range(4)]
+    # a restart without a shift is the same run as a batch started from those fields
+    fresh = Batch([dict(m, phi0=f.cpu().numpy()) for m, f in zip(members, fields)], history=8)
+    b.reset(fields)
+    assert b.step_count() == 0
+    b.step(0.01, 20)
+    fresh.step(0.01, 20)
+    for m in range(4):
+        assert torch.equal(b.phi(m), fresh.phi(m))
+    # with the shift r - sqrt(E_1) the SAV variable of the state is carried over exactly
+    shift = [p["r"] - math.sqrt(p["E1"]) for p in before]
+    assert max(abs(s) for s in shift) > 1e-6          # the run has drifted from sqrt(E_1)
+    b.reset(fields, shift)
+    after = b.energies()
+    for p, a in zip(before, after):
+        assert a["r"] == pytest.approx(p["r"], rel=1e-13)
+        assert a["E1"] == pytest.approx(p["E1"], rel=1e-13)
+        assert a["sav_energy"] == pytest.approx(p["sav_energy"], rel=1e-13)
+    # a shift that makes r non-positive: error, and that member keeps sqrt(E_1)
+    bad = list(shift)
+    bad[2] = -2.0 * math.sqrt(before[2]["E1"])
+    with pytest.raises(SpfcError):
+        b.reset(fields, bad)
+    e = b.energies()
+    assert e[2]["r"] == pytest.approx(math.sqrt(e[2]["E1"]), rel=1e-15)
+    assert e[1]["r"] == pytest.approx(before[1]["r"], rel=1e-13)
+    b.close()
+    fresh.close()
