@@ -173,12 +173,90 @@ def run_ensemble(args):
     print(json.dumps(out))
 
 
+SURROGATES = {
+    # name: (held-out members, n, training members, snapshots, training iterations)
+    "surrogate64_256": (64, 256, 48, 40, 1500),
+}
+
+
+def run_surrogate(args):
+    """FNO surrogate (4 Fourier layers, width 32, 16 x 16 modes, BF16 matrix-core mixing)
+    trained on the GPU on SAV trajectories (256^2, side 16 pi, epsilon ~ U[0.1, 0.4),
+    mean -0.2, noise initial data, 50-step increments), then 64 held-out members
+    advanced by jumps of 50 steps judged by the SAV energy, against the plain steps over
+    the same stretch.  --steps is the stretch in plain steps (a multiple of 50),
+    --warmup the plain steps before it."""
+    import torch
+    from paper_2012_15133_amd import Batch
+    from paper_2012_15133_amd import surrogate_run as R
+    from paper_2012_15133_amd.surrogate import Surrogate, init_params
+
+    count, n, n_train, snaps, iters = SURROGATES[args.workload]
+    jumps = max(1, args.steps // R.JUMP)
+    steps = jumps * R.JUMP
+    traj, eps_tr = R.trajectories(R.members(n_train, seed=11), snaps=snaps, warm=500)
+    net = Surrogate(n, init_params(0), max_batch=32, train=True)
+    t_train = R.timed(lambda: R.train(net, traj, eps_tr, iters=iters, batch=32, lr=1e-3, log_every=iters), net.stream)
+    loss = float(net.loss.item())
+    params = net.params()
+    net.close()
+    del traj
+
+    test = R.members(count, seed=77)
+    eps = torch.tensor([m["epsilon"] for m in test], dtype=torch.float32, device="cuda")
+    inf = Surrogate(n, params, max_batch=count)
+    plain = Batch(test, history=16)
+    run = Batch(test, history=16)
+    for b in (plain, run):
+        b.step(R.DT, args.warmup)
+    start = plain.phi_all(torch.empty((count, n, n), dtype=torch.float64, device="cuda")).clone()
+    t_plain = R.timed(lambda: plain.step(R.DT, steps), plain.stream)
+    J = R.Jumper(run, Batch(test, history=16), inf, eps)
+    t_jump = R.timed(lambda: [J.jump() for _ in range(jumps)], run.stream)
+    ref = plain.phi_all(torch.empty_like(start))
+    got = J.b.phi_all(torch.empty_like(start))
+    err = (got - ref).flatten(1).norm(dim=1) / (ref - start).flatten(1).norm(dim=1)
+    # the network alone
+    phi32 = got.to(torch.float32)
+    inf.forward(phi32, eps)
+    t_fwd = R.timed(lambda: [inf.forward(phi32, eps) for _ in range(10)], inf.stream)
+    inf.close()
+    for b in (plain, J.b, J.spare):
+        b.close()
+
+    sec = t_jump[1]
+    out = {
+        "metric": "grid-point-steps/s",
+        "value": count * n * n * steps / sec,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "members": count, "n": n, "side": "16 pi", "dt": R.DT,
+                   "jump": R.JUMP, "epsilon": "U[0.1,0.4)", "train_members": n_train, "train_snapshots": snaps,
+                   "train_iters": iters, "train_batch": 32},
+        "surrogate": {"jumps": jumps, "accepted": J.accepted, "rejected": J.rejected,
+                      "err_over_change_mean": float(err.mean()), "err_over_change_max": float(err.max()),
+                      "plain_ms_per_50_steps": t_plain[1] * 1e3 / jumps, "ms_per_jump": sec * 1e3 / jumps,
+                      "speedup_vs_plain": t_plain[1] / sec, "forward_ms_batch64": t_fwd[0] * 1e3 / 10,
+                      "train_ms_per_iter": t_train[0] * 1e3 / iters, "final_train_loss": loss},
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS) + sorted(ENSEMBLES))
+    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(SURROGATES))
     ap.add_argument("--no-seq", action="store_true", help="ensembles: skip the one-after-another comparison")
     ap.add_argument("--tune", type=int, default=0,
                     help="ensembles: tune the launch plan of each size class with this many trial steps first")
@@ -209,6 +287,9 @@ def main():
 
     if args.workload in ENSEMBLES:
         run_ensemble(args)
+        return
+    if args.workload in SURROGATES:
+        run_surrogate(args)
         return
 
     import numpy as np

@@ -18,8 +18,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t prm, wpk, tw, bhi, blo, xp, zz, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, part, lpart, gpart,
-        partials, grad, m, vv, total;
+    size_t prm, wpk, tw, bx, bxt, xp, zz, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, lpart, gpart, partials,
+        grad, m, vv, total;
     size_t field_bf, field_f, spec;   // bytes of one activation (bf16), one f32 field set, one spectrum set
 };
 
@@ -45,10 +45,10 @@ Layout layout_of(const spfc_fno_shape& s) {
     L.prm = take(P_TOTAL * sizeof(float));
     L.wpk = take((size_t)LAYERS * NMODE * 64 * 64 * sizeof(uint16_t));
     L.tw = take((size_t)s.n * sizeof(float2));
-    L.bhi = take((size_t)s.n * 2 * MX * sizeof(uint16_t));
-    L.blo = take((size_t)s.n * 2 * MX * sizeof(uint16_t));
-    L.xp = take(planes * s.n * MX * sizeof(float2));
-    L.zz = take(planes * s.n * MX * sizeof(float2));
+    L.bx = take(2 * (size_t)s.n * 2 * MX * sizeof(uint16_t));
+    L.bxt = take(2 * (size_t)s.n * 2 * MX * sizeof(uint16_t));
+    L.xp = take(planes * s.n * 2 * MX * sizeof(float));
+    L.zz = take(planes * s.n * 2 * MX * sizeof(float));
     L.v = take((tr ? LAYERS + 1 : 2) * align_up(L.field_bf));
     L.u = take(tr ? LAYERS * align_up(L.field_bf) : 0);
     L.w = take(L.field_f);
@@ -60,7 +60,6 @@ Layout layout_of(const spfc_fno_shape& s) {
     L.out_raw = take((size_t)s.max_batch * npts * sizeof(float));
     L.pred = take(tr ? (size_t)s.max_batch * npts * sizeof(float) : 0);
     L.gpred = take(tr ? (size_t)s.max_batch * npts * sizeof(float) : 0);
-    L.part = take((size_t)s.max_batch * nwg * sizeof(float));
     L.lpart = take((size_t)s.max_batch * nwg * sizeof(float));
     L.gpart = take((size_t)s.max_batch * nwg * sizeof(float));
     L.partials = take(tr ? (size_t)GRED64 * PART_MAX * sizeof(float) : 0);
@@ -99,10 +98,10 @@ struct spfc_fno {
     }
     float2* uh() const { return at<float2>(lay.uh); }
     float2* gvh() const { return at<float2>(lay.gvh); }
-    float2* xp() const { return at<float2>(lay.xp); }
-    float2* zz() const { return at<float2>(lay.zz); }
-    const uint16_t* bhi() const { return at<uint16_t>(lay.bhi); }
-    const uint16_t* blo() const { return at<uint16_t>(lay.blo); }
+    float* xp() const { return at<float>(lay.xp); }
+    float* zz() const { return at<float>(lay.zz); }
+    const uint16_t* bx() const { return at<uint16_t>(lay.bx); }
+    const uint16_t* bxt() const { return at<uint16_t>(lay.bxt); }
 };
 
 namespace {
@@ -129,25 +128,38 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     hipStream_t st = f->stream;
     const bool tr = f->shape.train != 0 && target;
     // rows: lifting + x-analysis; per layer: y-analysis, mixing, y-synthesis, then the row
-    // kernel (x-synthesis, pointwise, activation, next x-analysis)
-    CK(launch_row(n, batch, true, phi, eps, f->prm(), 0, nullptr, nullptr, f->v(0), nullptr, f->xp(), f->bhi(),
-                  f->blo(), f->tw(), st));
+    // kernel (x-synthesis, pointwise layer, activation, next x-analysis; the last layer's
+    // row kernel also projects and takes the x-analysis of the output)
+    RowIn in{};
+    in.phi = phi;
+    in.eps = eps;
+    in.prm = f->prm();
+    in.bx = f->bx();
+    in.bxt = f->bxt();
+    in.tw = f->tw();
+    in.vout = f->v(0);
+    in.xout = f->xp();
+    CK(launch_row(n, batch, RK_LIFT, in, st));
+    // the output's x-analysis goes to out_raw's space (free during the forward pass)
+    float* xo = f->at<float>(f->lay.out_raw);
     for (int l = 0; l < LAYERS; ++l) {
+        const bool last = l == LAYERS - 1;
         CK(launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->tw(), st));
         CK(launch_mix(MIX_FWD, batch, f->vh(l), nullptr, f->wpk(l), f->uh(), nullptr, nullptr, st));
-        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, f->zz(), f->tw(), st));
-        CK(launch_row(n, batch, false, nullptr, nullptr, f->prm(), l, f->zz(), f->v(l), f->v(l + 1),
-                      tr ? f->u(l) : nullptr, l < LAYERS - 1 ? f->xp() : nullptr, f->bhi(), f->blo(), f->tw(), st));
+        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, false, f->zz(), f->tw(), st));
+        in.layer = l;
+        in.Z = f->zz();
+        in.v = f->v(l);
+        in.vout = (!last || tr) ? f->v(l + 1) : nullptr;
+        in.uout = (tr && !last) ? f->u(l) : nullptr;
+        in.xout = last ? xo : f->xp();
+        CK(launch_row(n, batch, last ? RK_LAST : RK_LAYER, in, st));
     }
-    float* out_raw = f->at<float>(f->lay.out_raw);
-    float* part = f->at<float>(f->lay.part);
-    CK(launch_project(n, batch, f->v(LAYERS), f->prm(), out_raw, part, st));
-    // the increment restricted to the retained modes (one plane per sample); its mean is
-    // that of out_raw (the filter keeps the k = 0 mode)
-    float* out_f = f->w();
-    CK(launch_analysis_f32(n, batch, out_raw, inv, inv, f->uh(), f->tw(), st));
-    CK(launch_synthesis(n, batch, f->uh(), 1.0f, 2.0f, out_f, 0, f->tw(), st));
-    CK(launch_finish(n, batch, phi, out_f, part, target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
+    // the increment restricted to the retained modes, without its mean (the k = 0 mode
+    // dropped), added to phi
+    CK(launch_col_anal(n, batch, xo, inv, f->uh(), f->tw(), st));
+    CK(launch_col_synth(n, batch, f->uh(), 1.0f, 2.0f, true, f->zz(), f->tw(), st));
+    CK(launch_finish(n, batch, phi, f->zz(), f->tw(), target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
                      f->at<float>(f->lay.lpart), f->at<float>(f->lay.gpart), st));
     return OK;
 }
@@ -250,8 +262,7 @@ int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* wo
             return fail(E_DEVICE);
     }
     if (pack_all(f)) return fail(E_DEVICE);
-    if (launch_basis(shape->n, f->at<uint16_t>(lay.bhi), f->at<uint16_t>(lay.blo),
-                     f->stream) != hipSuccess)
+    if (launch_basis(shape->n, f->at<uint16_t>(lay.bx), f->at<uint16_t>(lay.bxt), f->stream) != hipSuccess)
         return fail(E_DEVICE);
     if (hipStreamSynchronize(f->stream) != hipSuccess) return fail(E_DEVICE);
     *out = f;

@@ -27,20 +27,6 @@ __device__ inline float block_sum_f(float v, float* red /* >= TPB/64 floats of L
 
 }  // namespace
 
-// ---------------------------------------------------------------- lifting
-
-// v0[b][c][p] = Lw[c][0] phi[b][p] + Lw[c][1] eps[b] + Lb[c]
-__global__ void __launch_bounds__(TPB) k_lift(int npts, const float* phi, const float* eps, const float* prm,
-                                              uint16_t* v0) {
-    const int b = blockIdx.y;
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    if (p >= npts) return;
-    const float f = phi[(size_t)b * npts + p], e = eps[b];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        v0[((size_t)b * C + c) * npts + p] = f2bf(prm[P_LW + 2 * c] * f + prm[P_LW + 2 * c + 1] * e + prm[P_LB + c]);
-}
-
 // ---------------------------------------------------------------- truncated transforms
 
 // One workgroup per plane.  out[m][plane] = s_kx sum_{y,x} in[y][x] e^{-2 pi i (kx x + ky y)/N}:
@@ -51,7 +37,7 @@ __global__ void __launch_bounds__(TPB) k_analysis(int planes, const TIn* in, flo
                                                   const float2* twg) {
     __shared__ float2 tw[N];
     __shared__ float chunk[16 * N];
-    __shared__ float2 X[N * MX];
+    __shared__ __align__(16) float2 X[N * MX];
     const int t = threadIdx.x, p = blockIdx.x;
     const TIn* src = in + (size_t)p * N * N;
     for (int i = t; i < N; i += TPB) tw[i] = twg[i];
@@ -236,193 +222,480 @@ __global__ void __launch_bounds__(TPB) k_mix(int batch, const float2* a, const f
 }
 
 // ---------------------------------------------------------------- row / column form of the forward pass
+//
+// Activations (bf16) are stored channel-blocked: row (b, y) is one block of C N values
+// [c / 8][x][c % 8], so that the 8 channels a matrix-core operand takes at one point are
+// 16 contiguous bytes.
+//
+// X'[b][c][y][n], the x half of the analysis, is planar: n < 16 holds Re, n >= 16 Im of
+// kx = n % 16:  X'[c][y][n] = sum_x v[c][y][x] Bx[x][n] with Bx[x][n] = cos(2 pi n x / N)
+// (n < 16) and -sin(2 pi (n - 16) x / N) (n >= 16).  Z[b][c][y][k], the y half of the
+// synthesis (kx weights included), is planar in the same way.
 
-// X'[b][c][y][kx] = sum_x v[b][c][y][x] e^{-2 pi i kx x / N} (the x half of the analysis),
-// Z[b][o][y][kx] = sum_j s_kx U[kx][j] e^{+2 pi i ky y / N} (the y half of the synthesis).
-// Rows: one workgroup takes R = 256 / N rows (r, y) of one sample, thread = (r, x).
+typedef short i16x4 __attribute__((ext_vector_type(4)));
 
-// bf16 DFT basis for the x half of the analysis, split in two parts so that hi + lo
-// carries FP32 accuracy: B[x][n] = cos(2 pi n x / N) (n < 16), -sin(2 pi (n-16) x / N).
-__global__ void __launch_bounds__(TPB) k_basis(int n, uint16_t* hi, uint16_t* lo) {
+__device__ inline f32x4 mfma32(const bf16x8& a, const bf16x8& b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x16_bf16: lane l holds A(l % 16, 4 (l / 16) + j), B(4 (l / 16) + j, l % 16)
+// and D(4 (l / 16) + j, l % 16), j < 4 -- a result tile is itself a B operand.
+__device__ inline f32x4 mfma16(const i16x4& a, const i16x4& b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline bf16x8 ld_bf8(const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p)); }
+__device__ inline i16x4 ld_bf4(const uint16_t* p) { return __builtin_bit_cast(i16x4, *reinterpret_cast<const uint2*>(p)); }
+__device__ inline void split8(const float* f, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint16_t h = f2bf(f[j]);
+        hi[j] = __builtin_bit_cast(__bf16, h);
+        lo[j] = __builtin_bit_cast(__bf16, f2bf(f[j] - bf2f(h)));
+    }
+}
+__device__ inline void split4(const float* f, i16x4& hi, i16x4& lo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint16_t h = f2bf(f[j]);
+        hi[j] = (short)h;
+        lo[j] = (short)f2bf(f[j] - bf2f(h));
+    }
+}
+// offset of (channel c, column x) inside a channel-blocked row of length N
+__device__ inline int act_in_row(int N, int c, int x) { return ((c >> 3) * N + x) * 8 + (c & 7); }
+// store 4 channels c .. c + 3 (c % 4 == 0) at one column from an f32 tile column
+__device__ inline void store4(uint16_t* dst, const f32x4& v) {
+    uint2 w;
+    w.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+    w.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+    *reinterpret_cast<uint2*>(dst) = w;
+}
+
+// x-basis tables, bf16 hi + lo so that hi + lo carries FP32 accuracy:
+// bx[part][x][n] = Bx[x][n], bxt[part][n][x] = Bx[x][n] (part 0: hi, 1: lo).
+__global__ void __launch_bounds__(TPB) k_basis(int n, uint16_t* bx, uint16_t* bxt) {
     for (int e = blockIdx.x * TPB + threadIdx.x; e < n * 2 * MX; e += gridDim.x * TPB) {
         const int x = e / (2 * MX), c = e - x * 2 * MX;
         const int k = c & 15;
         const double a = 6.283185307179586476925286766559 * (double)((k * x) % n) / (double)n;
         const float v = c < MX ? (float)cos(a) : -(float)sin(a);
-        const uint16_t h = f2bf(v);
-        hi[e] = h;
-        lo[e] = f2bf(v - bf2f(h));
+        const uint16_t h = f2bf(v), l = f2bf(v - bf2f(h));
+        bx[e] = h;
+        bx[n * 2 * MX + e] = l;
+        bxt[c * n + x] = h;
+        bxt[2 * MX * n + c * n + x] = l;
     }
 }
 
-// Row kernel.  LIFT: v = Lw phi + Lw eps + Lb.  LAYER: u = synth_x(Z) + Pw v + Pb,
-// v' = gelu(u) (act) or u, as one matrix-core product per row:
-//   u[o][x] = sum_k A[o][k] B[k][x],  A = [Re Z | Im Z | Pw] (32 x 64),
-//   B = [cos(kx x) ; -sin(kx x) ; v] (64 x N),
-// with A and the basis split into bf16 hi + lo parts (hi hi + lo hi + hi lo: FP32
-// accuracy; v is stored as bf16 already).  Stores v' (bf16), u (bf16, if uout) and, if
-// xout, X' = analysis_x(v') (bf16 v' times the hi + lo basis, FP32 sums).
-template <int N, bool LIFT>
-__global__ void __launch_bounds__(TPB) k_row(const float* phi, const float* eps, const float* prm, int layer,
-                                             const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout,
-                                             float2* xout, const uint16_t* bhi, const uint16_t* blo,
-                                             const float2* twg) {
-    constexpr int R = TPB / N;            // rows per workgroup
-    __shared__ uint16_t Zh[R * C * 2 * MX], Zl[R * C * 2 * MX];   // [r][o][k < 32]
-    __shared__ uint16_t Ph[C * C], Pl[C * C];                     // [o][i]
-    __shared__ float pb[C];
-    __shared__ uint16_t Vin[R * C * N];   // v of the rows [r][i][x]; later u
-    __shared__ uint16_t Vs[R * C * N];    // v' of the rows, [r][c][x]
-    const int t = threadIdx.x, r = t / N, x = t - r * N;
-    const int b = blockIdx.y, y0 = blockIdx.x * R, y = y0 + r;
-    const int npts = N * N;
-    const size_t base = (size_t)b * C * npts + (size_t)y * N + x;   // + c * npts
-    const int wave = t >> 6, lane = t & 63;
-    const int col = lane & 15, rb = 4 * (lane >> 4);
-    if constexpr (LIFT) {
-        const float f = phi[(size_t)b * npts + (size_t)y * N + x], e = eps[b];
+constexpr int RROWS = 4;     // rows per workgroup of the row kernel
+constexpr int XPITCH = 36;   // floats per channel in the LDS partials of the x-analysis
+
+// Row kernel: one workgroup takes RROWS rows (b, y) in turn; wave w owns the x-tiles
+// w N / 64 .. (w + 1) N / 64 - 1 of 16 points.
+//   LIFT:  v0[c][x] = Lw[c][0] phi + Lw[c][1] eps + Lb[c]; X' of v0.
+//   LAYER: u^T = Bx Z^T + v^T Pw^T + Pb (matrix cores, 16 x 16 tiles: rows x, columns
+//          channels; Z and Bx as bf16 hi + lo, hi hi + lo hi + hi lo, and Pw as hi + lo:
+//          FP32 accuracy); v' = gelu(u); X' of v' from the tiles directly (a result tile
+//          is the B operand of the 16x16x16 product with BxT); v' and u stored
+//          channel-blocked after a product with the identity transposes the tile.
+//   LAST:  u as LAYER without the activation, v4 = bf16(u) (stored when vout is set);
+//          the projection out = Q2 gelu(Q1 v4 + q1) + q2 on matrix cores (the transposed
+//          v4 tile is the B operand); then the x half of the analysis of out into
+//          xout[b][y][32].
+struct RowParams {
+    const float* phi;
+    const float* eps;
+    const float* prm;
+    int layer;
+    const float* Z;
+    const uint16_t* v;
+    uint16_t* vout;
+    uint16_t* uout;
+    float* xout;
+    const uint16_t* bx;
+    const uint16_t* bxt;
+    const float2* tw;
+};
+
+template <int N, int KIND>
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k_rowmm(RowParams a) {
+    constexpr int XPW = N / 64;
+    // LAST: the projected row [N], analysis partials [8][32], twiddles [N] (float2),
+    // q1 and Q2 [2][H]; otherwise two buffers of per-wave analysis partials
+    constexpr int LDS_F = KIND == RK_LAST ? (N + 8 * 32 + 2 * N + 2 * H) : (2 * 4 * C * XPITCH);
+    __shared__ __align__(16) float lds[LDS_F];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, col = lane & 15, g = lane >> 4;
+    const int b = blockIdx.y;
+    const float* prm = a.prm;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    i16x4 ident;   // B(k = 4 g + j, n = col) = (4 g + j == col), bf16 1.0 = 0x3F80
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            Vs[(r * C + c) * N + x] = f2bf(prm[P_LW + 2 * c] * f + prm[P_LW + 2 * c + 1] * e + prm[P_LB + c]);
-    } else {
-        const float* pw = prm + p_pw(layer);
-        for (int i = t; i < C * C; i += TPB) {
-            const float w = pw[i];
-            const uint16_t h = f2bf(w);
-            Ph[i] = h;
-            Pl[i] = f2bf(w - bf2f(h));
+    for (int j = 0; j < 4; ++j) ident[j] = (4 * g + j == col) ? (short)0x3F80 : (short)0;
+
+    // constant operands
+    bf16x8 bxh[XPW], bxl[XPW];        // A(x = x0 + col, k = 8 g + j) = Bx[x][k]
+    i16x4 bth[XPW][2], btl[XPW][2];   // A(n = 16 nt + col, x = x0 + 4 g + j) = Bx[x][n]
+    bf16x8 ph[2], pl[2];              // B(i = 8 g + j, o = 16 ot + col) = Pw[o][i]
+    float pbv[2] = {0.f, 0.f};
+#pragma unroll
+    for (int xt = 0; xt < XPW; ++xt) {
+        const int x0 = (wave * XPW + xt) * 16;
+        if constexpr (KIND == RK_LAYER) {   // LAST reloads them per tile (register budget)
+            bxh[xt] = ld_bf8(a.bx + (x0 + col) * 32 + 8 * g);
+            bxl[xt] = ld_bf8(a.bx + N * 32 + (x0 + col) * 32 + 8 * g);
         }
-        if (t < C) pb[t] = pw[C * C + t];
-        for (int i = t; i < R * C * MX; i += TPB) {
-            const int rr = i / (C * MX), rest = i - rr * C * MX, o = rest / MX, k = rest - o * MX;
-            const float2 z = Z[(((size_t)b * C + o) * N + y0 + rr) * MX + k];
-            const int a = (rr * C + o) * 2 * MX + k;
-            const uint16_t hr = f2bf(z.x), hi = f2bf(z.y);
-            Zh[a] = hr;
-            Zl[a] = f2bf(z.x - bf2f(hr));
-            Zh[a + MX] = hi;
-            Zl[a + MX] = f2bf(z.y - bf2f(hi));
-        }
+        if constexpr (KIND != RK_LAST) {
 #pragma unroll
-        for (int i = 0; i < C; ++i) Vin[(r * C + i) * N + x] = v[base + (size_t)i * npts];
-        __syncthreads();
-        // tiles: per row 2 (o) x N/16 (x); R rows -> 32 tiles, 8 per wave
-        f32x4 acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int tile = wave * 8 + q;
-            const int rr = tile / (2 * N / 16), rest = tile - rr * (2 * N / 16);
-            const int mt = rest / (N / 16), x0 = (rest - mt * (N / 16)) * 16;
-            const uint16_t* zh = Zh + (rr * C + mt * 16) * 2 * MX;
-            const uint16_t* zl = Zl + (rr * C + mt * 16) * 2 * MX;
-            f32x4 a = {0.f, 0.f, 0.f, 0.f};
-            // k < 32: the x-synthesis of the row's coefficients
-            a = mma16x16x32(a, zh, 2 * MX, 1, bhi + x0 * 2 * MX, 1, 2 * MX);
-            a = mma16x16x32(a, zl, 2 * MX, 1, bhi + x0 * 2 * MX, 1, 2 * MX);
-            a = mma16x16x32(a, zh, 2 * MX, 1, blo + x0 * 2 * MX, 1, 2 * MX);
-            // k >= 32: the pointwise layer Pw v
-            const uint16_t* vb = Vin + rr * C * N + x0;
-            a = mma16x16x32(a, Ph + mt * 16 * C, C, 1, vb, N, 1);
-            a = mma16x16x32(a, Pl + mt * 16 * C, C, 1, vb, N, 1);
-            acc[q] = a;
-        }
-        __syncthreads();   // Vin is read by every wave above; it now takes u
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int tile = wave * 8 + q;
-            const int rr = tile / (2 * N / 16), rest = tile - rr * (2 * N / 16);
-            const int mt = rest / (N / 16), x0 = (rest - mt * (N / 16)) * 16;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = mt * 16 + rb + j;
-                const float u = acc[q][j] + pb[o];
-                const int a = (rr * C + o) * N + x0 + col;
-                Vin[a] = f2bf(u);
-                Vs[a] = f2bf(layer < LAYERS - 1 ? gelu(u) : u);
+            for (int nt = 0; nt < 2; ++nt) {
+                bth[xt][nt] = ld_bf4(a.bxt + (16 * nt + col) * N + x0 + 4 * g);
+                btl[xt][nt] = ld_bf4(a.bxt + 32 * N + (16 * nt + col) * N + x0 + 4 * g);
             }
         }
     }
-    __syncthreads();
+    if constexpr (KIND != RK_LIFT) {
+        const float* pw = prm + p_pw(a.layer);
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        vout[base + (size_t)c * npts] = Vs[(r * C + c) * N + x];
-        if constexpr (!LIFT)
-            if (uout) uout[base + (size_t)c * npts] = Vin[(r * C + c) * N + x];
-    }
-    if (!xout) return;
-    // X'[(r, c)][n] = sum_x Vs[(r, c)][x] B[x][n]: M = R * 32 rows, 32 columns, K = N
-    constexpr int MT = R * C / 16, TILES = MT * 2;
-    for (int tile = wave; tile < TILES; tile += TPB / 64) {
-        const int mt = tile >> 1, nt = tile & 1;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < N; k0 += 32) {
-            acc = mma16x16x32(acc, Vs + mt * 16 * N + k0, N, 1, bhi + k0 * 2 * MX + nt * 16, 2 * MX, 1);
-            acc = mma16x16x32(acc, Vs + mt * 16 * N + k0, N, 1, blo + k0 * 2 * MX + nt * 16, 2 * MX, 1);
+        for (int ot = 0; ot < 2; ++ot) {
+            const int o = 16 * ot + col;
+            float f[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) f[j] = pw[o * C + 8 * g + j];
+            split8(f, ph[ot], pl[ot]);
+            pbv[ot] = pw[C * C + o];
         }
-        // D(row, col): row = (r, c), col n: n < 16 real part of kx = n, else imaginary of n - 16
+    }
+    // lifting weights of channel 16 ct + col (x-analysis operand) and of channels
+    // 16 ct + 4 g + j (stored values)
+    float lw[2][3], ls[2][4][3];
+    if constexpr (KIND == RK_LIFT) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int row = mt * 16 + rb + j, rr = row / C, c = row - rr * C;
-            float* dst = reinterpret_cast<float*>(xout + (((size_t)b * C + c) * N + y0 + rr) * MX + col);
-            dst[nt] = acc[j];   // nt = 0: .x (real), 1: .y (imaginary)
+        for (int ct = 0; ct < 2; ++ct) {
+            const int c = 16 * ct + col;
+            lw[ct][0] = prm[P_LW + 2 * c];
+            lw[ct][1] = prm[P_LW + 2 * c + 1];
+            lw[ct][2] = prm[P_LB + c];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c2 = 16 * ct + 4 * g + j;
+                ls[ct][j][0] = prm[P_LW + 2 * c2];
+                ls[ct][j][1] = prm[P_LW + 2 * c2 + 1];
+                ls[ct][j][2] = prm[P_LB + c2];
+            }
+        }
+    }
+    // projection (LAST): A(k = 16 kt + col, c = 16 ot + 4 g + j) = Q1[k][c] in registers;
+    // q1, Q2 in LDS
+    i16x4 qh[KIND == RK_LAST ? 4 : 1][2], ql[KIND == RK_LAST ? 4 : 1][2];
+    float q2c = 0.f;
+    float* q1s = lds + N + 8 * 32 + 2 * N;
+    float* q2s = q1s + H;
+    if constexpr (KIND == RK_LAST) {
+        const float* q = prm + P_Q1;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot) {
+                float f[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f[j] = q[(16 * kt + col) * C + 16 * ot + 4 * g + j];
+                split4(f, qh[kt][ot], ql[kt][ot]);
+            }
+        q2c = q[H * C + 2 * H];
+        float2* tws = reinterpret_cast<float2*>(lds + N + 8 * 32);
+        for (int i = t; i < N; i += TPB) tws[i] = a.tw[i];
+        if (t < H) {
+            q1s[t] = q[H * C + t];
+            q2s[t] = q[H * C + H + t];
+        }
+        __syncthreads();
+    }
+
+    // inputs of a row (LAYER, LAST), loaded one row ahead
+    float4 zq[2][2];
+    uint4 vq[XPW];
+    auto load_row = [&](int yy) {
+        const size_t ro = ((size_t)b * N + yy) * (size_t)(C * N);
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            const float* zp = a.Z + (((size_t)b * C + 16 * ot + col) * N + yy) * 32 + 8 * g;
+            zq[ot][0] = *reinterpret_cast<const float4*>(zp);
+            zq[ot][1] = *reinterpret_cast<const float4*>(zp + 4);
+        }
+        if constexpr (KIND == RK_LAYER)   // LAST loads them per tile (register budget)
+#pragma unroll
+            for (int xt = 0; xt < XPW; ++xt)
+                vq[xt] = *reinterpret_cast<const uint4*>(a.v + ro + act_in_row(N, 8 * g, (wave * XPW + xt) * 16 + col));
+    };
+    if constexpr (KIND != RK_LIFT) load_row(blockIdx.x * RROWS);
+
+    for (int r = 0; r < RROWS; ++r) {
+        const int y = blockIdx.x * RROWS + r;
+        const size_t rowo = ((size_t)b * N + y) * (size_t)(C * N);
+        f32x4 xa[2][2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) xa[ct][nt] = zero4;
+
+        if constexpr (KIND == RK_LIFT) {
+            const float e = a.eps[b];
+            const float* frow = a.phi + ((size_t)b * N + y) * N;
+#pragma unroll
+            for (int xt = 0; xt < XPW; ++xt) {
+                const int x0 = (wave * XPW + xt) * 16;
+                const float4 f4 = *reinterpret_cast<const float4*>(frow + x0 + 4 * g);
+                const float fc = frow[x0 + col];
+                const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    i16x4 vb;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) vb[j] = (short)f2bf(lw[ct][0] * fv[j] + lw[ct][1] * e + lw[ct][2]);
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        xa[ct][nt] = mfma16(bth[xt][nt], vb, xa[ct][nt]);
+                        xa[ct][nt] = mfma16(btl[xt][nt], vb, xa[ct][nt]);
+                    }
+                    f32x4 sv;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sv[j] = ls[ct][j][0] * fc + ls[ct][j][1] * e + ls[ct][j][2];
+                    store4(a.vout + rowo + act_in_row(N, 16 * ct + 4 * g, x0 + col), sv);
+                }
+            }
+        } else {
+            bf16x8 zh[2], zl[2];   // B(k = 8 g + j, o = 16 ot + col) = Z[o][k]
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot) {
+                const float f[8] = {zq[ot][0].x, zq[ot][0].y, zq[ot][0].z, zq[ot][0].w,
+                                    zq[ot][1].x, zq[ot][1].y, zq[ot][1].z, zq[ot][1].w};
+                split8(f, zh[ot], zl[ot]);
+            }
+            bf16x8 vx[XPW];
+            if constexpr (KIND == RK_LAYER)
+#pragma unroll
+                for (int xt = 0; xt < XPW; ++xt) vx[xt] = __builtin_bit_cast(bf16x8, vq[xt]);
+            if (r + 1 < RROWS) load_row(y + 1);
+            float* orow = lds;   // LAST: the projection of the row
+#pragma unroll
+            for (int xt = 0; xt < XPW; ++xt) {
+                const int x0 = (wave * XPW + xt) * 16;
+                i16x4 rb[2];
+                bf16x8 bh, bl, vt;
+                if constexpr (KIND == RK_LAYER) {
+                    bh = bxh[xt];
+                    bl = bxl[xt];
+                    vt = vx[xt];
+                } else {
+                    bh = ld_bf8(a.bx + (x0 + col) * 32 + 8 * g);
+                    bl = ld_bf8(a.bx + N * 32 + (x0 + col) * 32 + 8 * g);
+                    vt = ld_bf8(a.v + rowo + act_in_row(N, 8 * g, x0 + col));
+                }
+#pragma unroll
+                for (int ot = 0; ot < 2; ++ot) {
+                    f32x4 acc = zero4;
+                    acc = mfma32(bh, zh[ot], acc);
+                    acc = mfma32(bh, zl[ot], acc);
+                    acc = mfma32(bl, zh[ot], acc);
+                    acc = mfma32(vt, ph[ot], acc);
+                    acc = mfma32(vt, pl[ot], acc);
+                    // acc[j] = u[o = 16 ot + col] at x = x0 + 4 g + j
+                    i16x4 vb, ub;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float u = acc[j] + pbv[ot];
+                        ub[j] = (short)f2bf(u);
+                        vb[j] = KIND == RK_LAYER ? (short)f2bf(gelu(u)) : ub[j];
+                    }
+                    // tv[j] = value at channel 16 ot + 4 g + j, x = x0 + col
+                    const f32x4 tv = mfma16(vb, ident, zero4);
+                    if constexpr (KIND == RK_LAYER) {
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+                            xa[ot][nt] = mfma16(bth[xt][nt], vb, xa[ot][nt]);
+                            xa[ot][nt] = mfma16(btl[xt][nt], vb, xa[ot][nt]);
+                        }
+                        store4(a.vout + rowo + act_in_row(N, 16 * ot + 4 * g, x0 + col), tv);
+                        if (a.uout)
+                            store4(a.uout + rowo + act_in_row(N, 16 * ot + 4 * g, x0 + col),
+                                   mfma16(ub, ident, zero4));
+                    } else {
+                        if (a.vout) store4(a.vout + rowo + act_in_row(N, 16 * ot + 4 * g, x0 + col), tv);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) rb[ot][j] = (short)f2bf(tv[j]);
+                    }
+                }
+                if constexpr (KIND == RK_LAST) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int kt = 0; kt < 4; ++kt) {
+                        f32x4 h = zero4;
+#pragma unroll
+                        for (int ot = 0; ot < 2; ++ot) {
+                            h = mfma16(qh[kt][ot], rb[ot], h);
+                            h = mfma16(ql[kt][ot], rb[ot], h);
+                        }
+                        // h[j]: hidden unit 16 kt + 4 g + j at x = x0 + col
+                        const float4 q1 = *reinterpret_cast<const float4*>(q1s + 16 * kt + 4 * g);
+                        const float4 q2 = *reinterpret_cast<const float4*>(q2s + 16 * kt + 4 * g);
+                        s += q2.x * gelu(h[0] + q1.x);
+                        s += q2.y * gelu(h[1] + q1.y);
+                        s += q2.z * gelu(h[2] + q1.z);
+                        s += q2.w * gelu(h[3] + q1.w);
+                    }
+                    s += __shfl_xor(s, 16, 64);
+                    s += __shfl_xor(s, 32, 64);
+                    if (g == 0) orow[x0 + col] = s + q2c;
+                }
+            }
+        }
+
+        if constexpr (KIND != RK_LAST) {
+            // X' of the row: partial sums of each wave's x-tiles, added in wave order
+            float* xp = lds + (r & 1) * (4 * C * XPITCH);
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        xp[(wave * C + 16 * ct + col) * XPITCH + 16 * nt + 4 * g + j] = xa[ct][nt][j];
+            __syncthreads();
+            const int c = t >> 3, n0 = (t & 7) * 4;
+            float4 sum = *reinterpret_cast<const float4*>(xp + c * XPITCH + n0);
+#pragma unroll
+            for (int w = 1; w < 4; ++w) {
+                const float4 q = *reinterpret_cast<const float4*>(xp + (w * C + c) * XPITCH + n0);
+                sum.x += q.x;
+                sum.y += q.y;
+                sum.z += q.z;
+                sum.w += q.w;
+            }
+            *reinterpret_cast<float4*>(a.xout + (((size_t)b * C + c) * N + y) * 32 + n0) = sum;
+        } else {
+            // x half of the analysis of the projected row: 8 parts of N / 8 points each
+            __syncthreads();
+            const float* orow = lds;
+            float* pp = lds + N;
+            const float2* tws = reinterpret_cast<const float2*>(lds + N + 8 * 32);
+            const int n = t & 31, part = t >> 5, k = n & 15;
+            float acc = 0.f;
+            for (int x = part * (N / 8); x < (part + 1) * (N / 8); ++x) {
+                const float2 w = tws[(k * x) & (N - 1)];
+                acc += orow[x] * (n < 16 ? w.x : -w.y);
+            }
+            pp[part * 32 + n] = acc;
+            __syncthreads();
+            if (t < 32) {
+                float sum = 0.f;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sum += pp[q * 32 + t];
+                a.xout[((size_t)b * N + y) * 32 + t] = sum;
+            }
         }
     }
 }
 
-// Column kernels, one workgroup per plane (b, c).  ANAL: V[m][plane] = s sum_y X'[y][kx] e^{-i ky y}.
-// SYNTH: Z[plane][y][kx] = sum_j s_kx U[m][plane] e^{+i ky y}.
+// Column kernels, one workgroup per plane p.  ANAL: V[m][p] = s sum_y X'[p][y][kx] e^{-i ky y}.
+// SYNTH: Z[p][y][kx] = sum_j s_kx U[m][p] e^{+i ky y} (without the mode kx = ky = 0 if
+// drop0).  X' and Z planar as above; m = kx * 32 + j, ky = j (j < 16) or N - 32 + j.
+__device__ inline int ky_of(int N, int j) { return j < MY ? j : N - 2 * MY + j; }
+
+// ANAL: thread = (kx pair, 4 j, y quarter); the quarters are added in order.
 template <int N>
-__global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float2* xp, float s, float2* out,
+__global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float* xp, float s, float2* out,
                                                   const float2* twg) {
     __shared__ float2 tw[N];
-    __shared__ float2 X[N * MX];
+    __shared__ __align__(16) float2 X[N * MX];
+    __shared__ float4 part[3][TPB / 4][4];
     const int t = threadIdx.x, p = blockIdx.x;
     for (int i = t; i < N; i += TPB) tw[i] = twg[i];
-    for (int i = t; i < N * MX; i += TPB) X[i] = xp[(size_t)p * N * MX + i];
+    for (int i = t; i < N * MX; i += TPB) {
+        const int y = i / MX, kx = i - y * MX;
+        const float* row = xp + ((size_t)p * N + y) * 32;
+        X[i] = make_float2(row[kx], row[16 + kx]);
+    }
     __syncthreads();
-    const int kx = t & 15;
+    const int kp = t & 7, jg = (t >> 3) & 7, q = t >> 6;
+    const int k0 = 2 * kp;
+    int ky[4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int j = (t >> 4) + 16 * h;
-        const int ky = j < MY ? j : N - 2 * MY + j;
-        float re = 0.f, im = 0.f;
-#pragma unroll 8
-        for (int y = 0; y < N; ++y) {
-            const float2 a = X[y * MX + kx];
-            const float2 w = tw[(ky * y) & (N - 1)];
-            re += a.x * w.x + a.y * w.y;
-            im += a.y * w.x - a.x * w.y;
+    for (int i = 0; i < 4; ++i) ky[i] = ky_of(N, 4 * jg + i);
+    float re[2][4], im[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) re[h][i] = im[h][i] = 0.f;
+    for (int y = q * (N / 4); y < (q + 1) * (N / 4); ++y) {
+        const float4 xx = *reinterpret_cast<const float4*>(&X[y * MX + k0]);   // kx = k0, k0 + 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float2 w = tw[(ky[i] * y) & (N - 1)];
+            re[0][i] += xx.x * w.x + xx.y * w.y;
+            im[0][i] += xx.y * w.x - xx.x * w.y;
+            re[1][i] += xx.z * w.x + xx.w * w.y;
+            im[1][i] += xx.w * w.x - xx.z * w.y;
         }
-        out[(size_t)(kx * 2 * MY + j) * planes + p] = make_float2(re * s, im * s);
+    }
+    const int slot = t & 63;
+    if (q > 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            part[q - 1][slot][2 * h] = make_float4(re[h][0], im[h][0], re[h][1], im[h][1]);
+            part[q - 1][slot][2 * h + 1] = make_float4(re[h][2], im[h][2], re[h][3], im[h][3]);
+        }
+    }
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 a0 = part[qq][slot][2 * h], a1 = part[qq][slot][2 * h + 1];
+                re[h][0] += a0.x;
+                im[h][0] += a0.y;
+                re[h][1] += a0.z;
+                im[h][1] += a0.w;
+                re[h][2] += a1.x;
+                im[h][2] += a1.y;
+                re[h][3] += a1.z;
+                im[h][3] += a1.w;
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[(size_t)((k0 + h) * 2 * MY + 4 * jg + i) * planes + p] = make_float2(re[h][i] * s, im[h][i] * s);
     }
 }
 
+// SYNTH: thread = (kx, y = t / 16 + 16 i); the 32 coefficients of its kx in registers.
 template <int N>
-__global__ void __launch_bounds__(TPB) k_col_synth(int planes, const float2* in, float s0, float s1, float2* zout,
-                                                   const float2* twg) {
-    constexpr int UP = 2 * MY + 1;   // padded row: the 16 kx of a wave fall in different banks
+__global__ void __launch_bounds__(TPB) k_col_synth(int planes, const float2* in, float s0, float s1, int drop0,
+                                                   float* zout, const float2* twg) {
     __shared__ float2 tw[N];
-    __shared__ float2 U[MX * UP];
     const int t = threadIdx.x, p = blockIdx.x;
     for (int i = t; i < N; i += TPB) tw[i] = twg[i];
-    for (int m = t; m < NMODE; m += TPB) {
-        const float sc = (m >> 5) == 0 ? s0 : s1;
-        const float2 u = in[(size_t)m * planes + p];
-        U[(m >> 5) * UP + (m & 31)] = make_float2(u.x * sc, u.y * sc);
+    const int kx = t & 15;
+    const float sc = kx == 0 ? s0 : s1;
+    float2 u[2 * MY];
+#pragma unroll
+    for (int j = 0; j < 2 * MY; ++j) {
+        const float2 v = in[(size_t)(kx * 2 * MY + j) * planes + p];
+        const float f = (drop0 && kx == 0 && j == 0) ? 0.f : sc;
+        u[j] = make_float2(v.x * f, v.y * f);
     }
     __syncthreads();
-    const int kx = t & 15;
     for (int y = t >> 4; y < N; y += 16) {
         float re = 0.f, im = 0.f;
-#pragma unroll 8
+#pragma unroll
         for (int j = 0; j < 2 * MY; ++j) {
-            const int ky = j < MY ? j : N - 2 * MY + j;
-            const float2 w = tw[(ky * y) & (N - 1)];
-            const float2 u = U[kx * UP + j];
-            re += u.x * w.x - u.y * w.y;
-            im += u.x * w.y + u.y * w.x;
+            const float2 w = tw[(ky_of(N, j) * y) & (N - 1)];
+            re += u[j].x * w.x - u[j].y * w.y;
+            im += u[j].x * w.y + u[j].y * w.x;
         }
-        zout[((size_t)p * N + y) * MX + kx] = make_float2(re, im);
+        float* row = zout + ((size_t)p * N + y) * 32;
+        row[kx] = re;
+        row[16 + kx] = im;
     }
 }
 
@@ -441,96 +714,63 @@ __global__ void __launch_bounds__(TPB) k_pack(const float* wr, const float* wi, 
     }
 }
 
-// ---------------------------------------------------------------- pointwise layer
-
-// u[o] = w[o] + sum_i Pw[o][i] v[i] + Pb[o]; vout = gelu(u) (act) or u; uout = u (if set)
-__global__ void __launch_bounds__(TPB) k_pointwise(int npts, int act, const float* w, const uint16_t* v,
-                                                   const float* pw, const float* pb, uint16_t* vout, uint16_t* uout) {
-    __shared__ float sw[C * C + C];
-    for (int i = threadIdx.x; i < C * C; i += TPB) sw[i] = pw[i];
-    if (threadIdx.x < C) sw[C * C + threadIdx.x] = pb[threadIdx.x];
-    __syncthreads();
-    const int b = blockIdx.y;
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    if (p >= npts) return;
-    const size_t base = (size_t)b * C * npts + p;
-    float x[C];
-#pragma unroll
-    for (int i = 0; i < C; ++i) x[i] = bf2f(v[base + (size_t)i * npts]);
-#pragma unroll 4
-    for (int o = 0; o < C; ++o) {
-        float u = w[base + (size_t)o * npts] + sw[C * C + o];
-#pragma unroll
-        for (int i = 0; i < C; ++i) u += sw[o * C + i] * x[i];
-        if (uout) uout[base + (size_t)o * npts] = f2bf(u);
-        vout[base + (size_t)o * npts] = f2bf(act ? gelu(u) : u);
-    }
-}
-
 // ---------------------------------------------------------------- projection and loss
 
-// out_raw[b][p] = sum_k Q2[k] gelu(sum_c Q1[k][c] v4[c] + q1[k]) + q2; part[b][wg] = sum over the workgroup
-__global__ void __launch_bounds__(TPB) k_project(int npts, const uint16_t* v4, const float* prm, float* out_raw,
-                                                 float* part) {
+// pred = phi + the filtered increment without its mean: x half of the synthesis of
+// zo[b][y][32] (planar, kx weights and the dropped k = 0 mode applied by the column
+// kernel).  With a target: lpart = sum (pred - target)^2 per workgroup, gpred =
+// 2 (pred - target) / (batch npts), gpart = its per-workgroup sums.
+template <int N>
+__global__ void __launch_bounds__(TPB) k_finish(int batch, const float* phi, const float* zo, const float2* twg,
+                                                const float* target, float* pred, float* gpred, float* lpart,
+                                                float* gpart) {
+    constexpr int R = TPB / N;
+    __shared__ float2 tw[N];
+    __shared__ float zr[R * 32];
     __shared__ float red[TPB / 64];
-    const float* q = prm + P_Q1;   // uniform: scalar loads
-    const int b = blockIdx.y;
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    float o = 0.f;
-    if (p < npts) {
-        const size_t base = (size_t)b * C * npts + p;
-        float x[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) x[c] = bf2f(v4[base + (size_t)c * npts]);
-        o = q[H * C + H + H];
-#pragma unroll 2
-        for (int k = 0; k < H; ++k) {
-            float pre = q[H * C + k];
-#pragma unroll
-            for (int c = 0; c < C; ++c) pre += q[k * C + c] * x[c];
-            o += q[H * C + H + k] * gelu(pre);
-        }
-        out_raw[(size_t)b * npts + p] = o;
-    }
-    const float s = block_sum_f(o, red);
-    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
-}
-
-// pred = phi + out - mean(out); with a target: lpart = sum (pred - target)^2 per workgroup,
-// gpred = 2 (pred - target) / (batch npts), gpart = its per-workgroup sums.
-__global__ void __launch_bounds__(TPB) k_finish(int npts, int batch, const float* phi, const float* out_raw,
-                                                const float* part, const float* target, float* pred, float* gpred,
-                                                float* lpart, float* gpart) {
-    __shared__ float red[TPB / 64];
-    __shared__ float mean_s;
-    const int b = blockIdx.y, nwg = gridDim.x;
-    if (threadIdx.x == 0) {
-        float s = 0.f;
-        for (int w = 0; w < nwg; ++w) s += part[(size_t)b * nwg + w];
-        mean_s = s / (float)npts;
-    }
+    const int t = threadIdx.x, b = blockIdx.y, r = t / N, x = t - r * N;
+    const int y = blockIdx.x * R + r;
+    for (int i = t; i < N; i += TPB) tw[i] = twg[i];
+    if (t < R * 32) zr[t] = zo[((size_t)b * N + blockIdx.x * R) * 32 + t];
     __syncthreads();
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    float d = 0.f, gd = 0.f;
-    if (p < npts) {
-        const size_t i = (size_t)b * npts + p;
-        const float y = phi[i] + out_raw[i] - mean_s;
-        if (pred) pred[i] = y;
-        if (target) {
-            d = y - target[i];
-            gd = 2.f * d / ((float)batch * (float)npts);
-            gpred[i] = gd;
-        }
+    float inc = 0.f;
+#pragma unroll
+    for (int kx = 0; kx < MX; ++kx) {
+        const float2 w = tw[(kx * x) & (N - 1)];
+        inc += zr[r * 32 + kx] * w.x - zr[r * 32 + 16 + kx] * w.y;
     }
+    const size_t i = ((size_t)b * N + y) * N + x;
+    const float yv = phi[i] + inc;
+    if (pred) pred[i] = yv;
     if (target) {
+        const float d = yv - target[i];
+        const float gd = 2.f * d / ((float)batch * (float)(N * N));
+        gpred[i] = gd;
+        const int nwg = gridDim.x;
         const float l = block_sum_f(d * d, red);
-        if (threadIdx.x == 0) lpart[(size_t)b * nwg + blockIdx.x] = l;
+        if (t == 0) lpart[(size_t)b * nwg + blockIdx.x] = l;
         const float gs = block_sum_f(gd, red);
-        if (threadIdx.x == 0) gpart[(size_t)b * nwg + blockIdx.x] = gs;
+        if (t == 0) gpart[(size_t)b * nwg + blockIdx.x] = gs;
     }
 }
 
 // ---------------------------------------------------------------- backward, weight-gradient partials
+
+// the C channels of point p = y n + x of sample b from channel-blocked activations
+__device__ inline void load_act(const uint16_t* a, int n, int b, int p, float* out) {
+    const int y = p / n, x = p - y * n;
+    const uint16_t* row = a + ((size_t)b * n + y) * (size_t)(C * n) + (size_t)x * 8;
+#pragma unroll
+    for (int cg = 0; cg < C / 8; ++cg) {
+        const uint4 q = *reinterpret_cast<const uint4*>(row + (size_t)cg * n * 8);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            out[cg * 8 + 2 * j] = bf2f((uint16_t)(w[j] & 0xFFFFu));
+            out[cg * 8 + 2 * j + 1] = bf2f((uint16_t)(w[j] >> 16));
+        }
+    }
+}
 
 // The weight-gradient kernels run GRED workgroups that each take chunks of TPB points
 // (chunk id = blockIdx.x, + GRED, ...; a chunk lies inside one sample), and write one
@@ -555,9 +795,10 @@ __global__ void __launch_bounds__(TPB) k_center(int npts, const float* gpred, co
 // g_out (the gradient of the projection output), recompute pre/h; gv4[c] = sum_k Q1[k][c] g_pre[k];
 // partials: Q1 (g_pre v4), q1 (g_pre), Q2 (g_out h), q2 (g_out).  Thread t owns row k = t
 // of Q1 and q1[t], Q2[t]; thread 0 also q2.
-__global__ void __launch_bounds__(64) k_project_bwd(int npts, int batch, const uint16_t* v4, const float* prm,
+__global__ void __launch_bounds__(64) k_project_bwd(int n, int batch, const uint16_t* v4, const float* prm,
                                                     const float* gouts, float* gv, float* partials) {
     constexpr int Q = 64;
+    const int npts = n * n;
     __shared__ float gp_s[H * Q];
     __shared__ float h_s[H * Q];
     __shared__ float x_s[C * Q];
@@ -576,11 +817,9 @@ __global__ void __launch_bounds__(64) k_project_bwd(int npts, int batch, const u
         const float go = gouts[(size_t)b * npts + p];
         const size_t base = (size_t)b * C * npts + p;
         float x[C], gx[C];
+        load_act(v4, n, b, p, x);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            x[c] = bf2f(v4[base + (size_t)c * npts]);
-            gx[c] = 0.f;
-        }
+        for (int c = 0; c < C; ++c) gx[c] = 0.f;
         __syncthreads();   // the previous chunk's LDS is consumed
         for (int k = 0; k < H; ++k) {
             float pre = q[H * C + k];
@@ -620,10 +859,11 @@ __global__ void __launch_bounds__(64) k_project_bwd(int npts, int batch, const u
 // gu[o] = gout[o] gelu'(u[o]) (act) or gout[o]; gv[i] = sum_o Pw[o][i] gu[o];
 // partials: Pw (gu v), Pb (gu).  Thread t owns Pw[o][i0..i0+15] with o = t / 2,
 // i0 = 16 (t % 2), and Pb[o] if t is even.
-__global__ void __launch_bounds__(64) k_pointwise_bwd(int npts, int batch, int act, const float* gout,
+__global__ void __launch_bounds__(64) k_pointwise_bwd(int n, int batch, int act, const float* gout,
                                                       const uint16_t* u, const uint16_t* v, const float* pw,
                                                       float* gu, float* gv, float* partials) {
     constexpr int Q = 64;
+    const int npts = n * n;
     __shared__ float sw[C * C];
     __shared__ float g_s[C * Q];
     __shared__ float x_s[C * Q];
@@ -641,15 +881,17 @@ __global__ void __launch_bounds__(64) k_pointwise_bwd(int npts, int batch, int a
         const int p = (ch - b * per) * Q + t;
         const size_t base = (size_t)b * C * npts + p;
         __syncthreads();   // the previous chunk's LDS is consumed
-        float g[C];
+        float g[C], uu[C], vv[C];
+        if (act) load_act(u, n, b, p, uu);
+        load_act(v, n, b, p, vv);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const size_t i = base + (size_t)c * npts;
             const float go = gout[i];
-            g[c] = act ? go * gelu_d(bf2f(u[i])) : go;
+            g[c] = act ? go * gelu_d(uu[c]) : go;
             gu[i] = g[c];
             g_s[c * Q + t] = g[c];
-            x_s[c * Q + t] = bf2f(v[i]);
+            x_s[c * Q + t] = vv[c];
         }
         for (int i = 0; i < C; ++i) {
             float s = 0.f;
@@ -747,13 +989,6 @@ __global__ void __launch_bounds__(TPB) k_adam(int64_t count, float* prm, const f
         default: return hipErrorInvalidValue;                                                          \
     }
 
-hipError_t launch_lift(int n, int batch, const float* phi, const float* eps, const float* prm, uint16_t* v0,
-                       hipStream_t st) {
-    const int npts = n * n;
-    hipLaunchKernelGGL(k_lift, dim3((npts + TPB - 1) / TPB, batch), dim3(TPB), 0, st, npts, phi, eps, prm, v0);
-    return hipGetLastError();
-}
-
 template <typename TIn>
 static hipError_t analysis_n(int n, int planes, const TIn* in, float s0, float s1, float2* out, const float2* tw,
                              hipStream_t st) {
@@ -764,11 +999,6 @@ static hipError_t analysis_n(int n, int planes, const TIn* in, float s0, float s
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_analysis_bf16(int n, int planes, const uint16_t* in, float s0, float s1, float2* out,
-                                const float2* tw, hipStream_t st) {
-    return analysis_n<uint16_t>(n, planes, in, s0, s1, out, tw, st);
 }
 
 hipError_t launch_analysis_f32(int n, int planes, const float* in, float s0, float s1, float2* out, const float2* tw,
@@ -793,20 +1023,18 @@ hipError_t launch_mix(int mode, int batch, const float2* a, const float2* g, con
     return hipGetLastError();
 }
 
-hipError_t launch_basis(int n, uint16_t* hi, uint16_t* lo, hipStream_t st) {
-    hipLaunchKernelGGL(k_basis, dim3((n * 2 * MX + TPB - 1) / TPB), dim3(TPB), 0, st, n, hi, lo);
+hipError_t launch_basis(int n, uint16_t* bx, uint16_t* bxt, hipStream_t st) {
+    hipLaunchKernelGGL(k_basis, dim3((n * 2 * MX + TPB - 1) / TPB), dim3(TPB), 0, st, n, bx, bxt);
     return hipGetLastError();
 }
 
-hipError_t launch_row(int n, int batch, bool lift, const float* phi, const float* eps, const float* prm, int layer,
-                      const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout, float2* xout,
-                      const uint16_t* bhi, const uint16_t* blo, const float2* tw, hipStream_t st) {
-    const dim3 g(n / (TPB / n), batch), b(TPB);
-#define FNO_ROW(NN)                                                                                               \
-    if (lift) hipLaunchKernelGGL((k_row<NN, true>), g, b, 0, st, phi, eps, prm, layer, Z, v, vout, uout, xout, bhi, \
-                                 blo, tw);                                                                         \
-    else hipLaunchKernelGGL((k_row<NN, false>), g, b, 0, st, phi, eps, prm, layer, Z, v, vout, uout, xout, bhi, blo, \
-                            tw);
+hipError_t launch_row(int n, int batch, int kind, const RowIn& in, hipStream_t st) {
+    RowParams a{in.phi, in.eps, in.prm, in.layer, in.Z, in.v, in.vout, in.uout, in.xout, in.bx, in.bxt, in.tw};
+    const dim3 g(n / RROWS, batch), b(TPB);
+#define FNO_ROW(NN)                                                                                  \
+    if (kind == RK_LIFT) hipLaunchKernelGGL((k_rowmm<NN, RK_LIFT>), g, b, 0, st, a);               \
+    else if (kind == RK_LAYER) hipLaunchKernelGGL((k_rowmm<NN, RK_LAYER>), g, b, 0, st, a);        \
+    else hipLaunchKernelGGL((k_rowmm<NN, RK_LAST>), g, b, 0, st, a);
     switch (n) {
         case 64: FNO_ROW(64) break;
         case 128: FNO_ROW(128) break;
@@ -817,15 +1045,15 @@ hipError_t launch_row(int n, int batch, bool lift, const float* phi, const float
     return hipGetLastError();
 }
 
-hipError_t launch_col_anal(int n, int planes, const float2* xp, float s, float2* out, const float2* tw,
+hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const float2* tw,
                            hipStream_t st) {
     FNO_LAUNCH_N(k_col_anal, dim3(planes), dim3(TPB), 0, st, planes, xp, s, out, tw)
     return hipGetLastError();
 }
 
-hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, float2* zout, const float2* tw,
-                            hipStream_t st) {
-    FNO_LAUNCH_N(k_col_synth, dim3(planes), dim3(TPB), 0, st, planes, in, s0, s1, zout, tw)
+hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, bool drop0, float* zout,
+                            const float2* tw, hipStream_t st) {
+    FNO_LAUNCH_N(k_col_synth, dim3(planes), dim3(TPB), 0, st, planes, in, s0, s1, drop0 ? 1 : 0, zout, tw)
     return hipGetLastError();
 }
 
@@ -834,26 +1062,10 @@ hipError_t launch_pack_weights(const float* wr, const float* wi, uint16_t* wpk, 
     return hipGetLastError();
 }
 
-hipError_t launch_pointwise(int n, int batch, bool act, const float* w, const uint16_t* v, const float* pw,
-                            const float* pb, uint16_t* vout, uint16_t* uout, hipStream_t st) {
-    const int npts = n * n;
-    hipLaunchKernelGGL(k_pointwise, dim3((npts + TPB - 1) / TPB, batch), dim3(TPB), 0, st, npts, act ? 1 : 0, w, v,
-                       pw, pb, vout, uout);
-    return hipGetLastError();
-}
-
-hipError_t launch_project(int n, int batch, const uint16_t* v4, const float* prm, float* out_raw, float* part,
-                          hipStream_t st) {
-    const int npts = n * n;
-    hipLaunchKernelGGL(k_project, dim3(npts / TPB, batch), dim3(TPB), 0, st, npts, v4, prm, out_raw, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_finish(int n, int batch, const float* phi, const float* out_raw, const float* part,
-                         const float* target, float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st) {
-    const int npts = n * n;
-    hipLaunchKernelGGL(k_finish, dim3(npts / TPB, batch), dim3(TPB), 0, st, npts, batch, phi, out_raw, part, target,
-                       pred, gpred, lpart, gpart);
+hipError_t launch_finish(int n, int batch, const float* phi, const float* zo, const float2* tw, const float* target,
+                         float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st) {
+    FNO_LAUNCH_N(k_finish, dim3(n * n / TPB, batch), dim3(TPB), 0, st, batch, phi, zo, tw, target, pred, gpred, lpart,
+                 gpart)
     return hipGetLastError();
 }
 
@@ -864,13 +1076,13 @@ hipError_t launch_center(int n, int batch, const float* gpred, const float* gpar
 
 hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gout, float* gv,
                               float* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_project_bwd, dim3(GRED64), dim3(64), 0, st, n * n, batch, v4, prm, gout, gv, partials);
+    hipLaunchKernelGGL(k_project_bwd, dim3(GRED64), dim3(64), 0, st, n, batch, v4, prm, gout, gv, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_pointwise_bwd(int n, int batch, bool act, const float* gout, const uint16_t* u, const uint16_t* v,
                                 const float* pw, float* gu, float* gv, float* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_pointwise_bwd, dim3(GRED64), dim3(64), 0, st, n * n, batch, act ? 1 : 0, gout, u, v, pw, gu,
+    hipLaunchKernelGGL(k_pointwise_bwd, dim3(GRED64), dim3(64), 0, st, n, batch, act ? 1 : 0, gout, u, v, pw, gu,
                        gv, partials);
     return hipGetLastError();
 }

@@ -57,15 +57,8 @@ __device__ inline float gelu_d(float z) {
 // ---------------------------------------------------------------- kernel declarations
 // (definitions in fno_kernels.hip; launch helpers for the host below)
 
-struct Twid {
-    const float2* tw;   // N entries: (cos, sin)(2 pi j / N)
-};
-
-hipError_t launch_lift(int n, int batch, const float* phi, const float* eps, const float* prm, uint16_t* v0,
-                       hipStream_t st);
-// planes P = batch * C; out [NMODE][P]; scale s0 for kx = 0, s1 otherwise
-hipError_t launch_analysis_bf16(int n, int planes, const uint16_t* in, float s0, float s1, float2* out,
-                                const float2* tw, hipStream_t st);
+// out [NMODE][planes]; scale s0 for kx = 0, s1 otherwise (generic plane transforms, used by
+// the backward pass)
 hipError_t launch_analysis_f32(int n, int planes, const float* in, float s0, float s1, float2* out, const float2* tw,
                                hipStream_t st);
 hipError_t launch_synthesis(int n, int planes, const float2* in, float s0, float s1, float* out, int accumulate,
@@ -77,22 +70,33 @@ enum { MIX_FWD = 0, MIX_BWD_DATA = 1, MIX_BWD_WEIGHT = 2 };
 hipError_t launch_mix(int mode, int batch, const float2* a, const float2* g, const uint16_t* wpk, float2* out,
                       float* gwr, float* gwi, hipStream_t st);
 hipError_t launch_pack_weights(const float* wr, const float* wi, uint16_t* wpk, hipStream_t st);
-// Row/column form of the forward pass (see fno_kernels.hip): basis tables, row kernel
-// (lifting or layer, with the next x-analysis), column halves of the transforms.
-hipError_t launch_basis(int n, uint16_t* hi, uint16_t* lo, hipStream_t st);
-hipError_t launch_row(int n, int batch, bool lift, const float* phi, const float* eps, const float* prm, int layer,
-                      const float2* Z, const uint16_t* v, uint16_t* vout, uint16_t* uout, float2* xout,
-                      const uint16_t* bhi, const uint16_t* blo, const float2* tw, hipStream_t st);
-hipError_t launch_col_anal(int n, int planes, const float2* xp, float s, float2* out, const float2* tw,
+
+// Row/column form of the forward pass (see fno_kernels.hip).  Activations are
+// channel-blocked: row (b, y) is one block [C / 8][n][8] of bf16.
+// x-basis tables bx [2][n][32] and bxt [2][32][n] (bf16 hi, lo).
+hipError_t launch_basis(int n, uint16_t* bx, uint16_t* bxt, hipStream_t st);
+enum { RK_LIFT = 0, RK_LAYER = 1, RK_LAST = 2 };
+struct RowIn {
+    const float* phi;    // LIFT: fields [b][n][n]
+    const float* eps;    // LIFT: [b]
+    const float* prm;
+    int layer;           // LAYER (0 .. LAYERS - 2), LAST (LAYERS - 1)
+    const float* Z;      // LAYER, LAST: y half of the synthesis [b][C][n][32]
+    const uint16_t* v;   // LAYER, LAST: activations in
+    uint16_t* vout;      // activations out (LAST: v4, optional)
+    uint16_t* uout;      // LAYER: pre-activations (optional)
+    float* xout;         // LIFT, LAYER: x half of the analysis [b][C][n][32]; LAST: of the output [b][n][32]
+    const uint16_t* bx;
+    const uint16_t* bxt;
+    const float2* tw;
+};
+hipError_t launch_row(int n, int batch, int kind, const RowIn& in, hipStream_t st);
+hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const float2* tw,
                            hipStream_t st);
-hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, float2* zout, const float2* tw,
-                            hipStream_t st);
-hipError_t launch_pointwise(int n, int batch, bool act, const float* w, const uint16_t* v, const float* pw,
-                            const float* pb, uint16_t* vout, uint16_t* uout, hipStream_t st);
-hipError_t launch_project(int n, int batch, const uint16_t* v4, const float* prm, float* out_raw, float* part,
-                          hipStream_t st);
-hipError_t launch_finish(int n, int batch, const float* phi, const float* out_raw, const float* part,
-                         const float* target, float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st);
+hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, bool drop0, float* zout,
+                            const float2* tw, hipStream_t st);
+hipError_t launch_finish(int n, int batch, const float* phi, const float* zo, const float2* tw, const float* target,
+                         float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st);
 hipError_t launch_center(int n, int batch, const float* gpred, const float* gpart, float* gout, hipStream_t st);
 hipError_t launch_project_bwd(int n, int batch, const uint16_t* v4, const float* prm, const float* gout, float* gv,
                               float* partials, hipStream_t st);
