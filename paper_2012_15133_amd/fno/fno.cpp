@@ -18,7 +18,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t prm, wpk, tw, bx, bxt, xp, zz, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, lpart, gpart, partials,
+    size_t prm, wpk, tw, bx, bxt, ta, ts, xp, zz, v, u, w, ga, gb, vh, uh, gvh, out_raw, pred, gpred, lpart, gpart, partials,
         grad, m, vv, total;
     size_t field_bf, field_f, spec;   // bytes of one activation (bf16), one f32 field set, one spectrum set
 };
@@ -47,6 +47,8 @@ Layout layout_of(const spfc_fno_shape& s) {
     L.tw = take((size_t)s.n * sizeof(float2));
     L.bx = take(2 * (size_t)s.n * 2 * MX * sizeof(uint16_t));
     L.bxt = take(2 * (size_t)s.n * 2 * MX * sizeof(uint16_t));
+    L.ta = take(4 * (size_t)s.n * 2 * MY * sizeof(uint16_t));
+    L.ts = take(4 * (size_t)s.n * 2 * MY * sizeof(uint16_t));
     L.xp = take(planes * s.n * 2 * MX * sizeof(float));
     L.zz = take(planes * s.n * 2 * MX * sizeof(float));
     L.v = take((tr ? LAYERS + 1 : 2) * align_up(L.field_bf));
@@ -102,6 +104,8 @@ struct spfc_fno {
     float* zz() const { return at<float>(lay.zz); }
     const uint16_t* bx() const { return at<uint16_t>(lay.bx); }
     const uint16_t* bxt() const { return at<uint16_t>(lay.bxt); }
+    const uint16_t* ta() const { return at<uint16_t>(lay.ta); }
+    const uint16_t* ts() const { return at<uint16_t>(lay.ts); }
 };
 
 namespace {
@@ -144,9 +148,9 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     float* xo = f->at<float>(f->lay.out_raw);
     for (int l = 0; l < LAYERS; ++l) {
         const bool last = l == LAYERS - 1;
-        CK(launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->tw(), st));
+        CK(launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->ta(), st));
         CK(launch_mix(MIX_FWD, batch, f->vh(l), nullptr, f->wpk(l), f->uh(), nullptr, nullptr, st));
-        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, false, f->zz(), f->tw(), st));
+        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, false, f->zz(), f->ts(), st));
         in.layer = l;
         in.Z = f->zz();
         in.v = f->v(l);
@@ -157,8 +161,8 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     }
     // the increment restricted to the retained modes, without its mean (the k = 0 mode
     // dropped), added to phi
-    CK(launch_col_anal(n, batch, xo, inv, f->uh(), f->tw(), st));
-    CK(launch_col_synth(n, batch, f->uh(), 1.0f, 2.0f, true, f->zz(), f->tw(), st));
+    CK(launch_col_anal(n, batch, xo, inv, f->uh(), f->ta(), st));
+    CK(launch_col_synth(n, batch, f->uh(), 1.0f, 2.0f, true, f->zz(), f->ts(), st));
     CK(launch_finish(n, batch, phi, f->zz(), f->tw(), target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
                      f->at<float>(f->lay.lpart), f->at<float>(f->lay.gpart), st));
     return OK;
@@ -262,7 +266,8 @@ int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* wo
             return fail(E_DEVICE);
     }
     if (pack_all(f)) return fail(E_DEVICE);
-    if (launch_basis(shape->n, f->at<uint16_t>(lay.bx), f->at<uint16_t>(lay.bxt), f->stream) != hipSuccess)
+    if (launch_basis(shape->n, f->at<uint16_t>(lay.bx), f->at<uint16_t>(lay.bxt), f->stream) != hipSuccess ||
+        launch_trig(shape->n, f->at<uint16_t>(lay.ta), f->at<uint16_t>(lay.ts), f->stream) != hipSuccess)
         return fail(E_DEVICE);
     if (hipStreamSynchronize(f->stream) != hipSuccess) return fail(E_DEVICE);
     *out = f;

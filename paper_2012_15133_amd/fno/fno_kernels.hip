@@ -227,10 +227,10 @@ __global__ void __launch_bounds__(TPB) k_mix(int batch, const float2* a, const f
 // [c / 8][x][c % 8], so that the 8 channels a matrix-core operand takes at one point are
 // 16 contiguous bytes.
 //
-// X'[b][c][y][n], the x half of the analysis, is planar: n < 16 holds Re, n >= 16 Im of
-// kx = n % 16:  X'[c][y][n] = sum_x v[c][y][x] Bx[x][n] with Bx[x][n] = cos(2 pi n x / N)
-// (n < 16) and -sin(2 pi (n - 16) x / N) (n >= 16).  Z[b][c][y][k], the y half of the
-// synthesis (kx weights included), is planar in the same way.
+// X'[n][y][p], the x half of the analysis of plane p = b C + c, is planar in n (n < 16
+// holds Re, n >= 16 Im of kx = n % 16) and plane-fastest:  X'[n][y][p] = sum_x v[p][y][x]
+// Bx[x][n] with Bx[x][n] = cos(2 pi n x / N) (n < 16) and -sin(2 pi (n - 16) x / N)
+// (n >= 16).  Z[n][y][p], the y half of the synthesis (kx weights included), likewise.
 
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
@@ -244,29 +244,53 @@ __device__ inline f32x4 mfma16(const i16x4& a, const i16x4& b, f32x4 c) {
 }
 __device__ inline bf16x8 ld_bf8(const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p)); }
 __device__ inline i16x4 ld_bf4(const uint16_t* p) { return __builtin_bit_cast(i16x4, *reinterpret_cast<const uint2*>(p)); }
-__device__ inline void split8(const float* f, bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint16_t h = f2bf(f[j]);
-        hi[j] = __builtin_bit_cast(__bf16, h);
-        lo[j] = __builtin_bit_cast(__bf16, f2bf(f[j] - bf2f(h)));
-    }
+__device__ inline uint32_t pack_pair(float a, float b) {
+    typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+    const bf2_t h = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+    return __builtin_bit_cast(uint32_t, h);
 }
-__device__ inline void split4(const float* f, i16x4& hi, i16x4& lo) {
+__device__ inline float lo_of(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ inline float hi_of(uint32_t w) { return __builtin_bit_cast(float, w & 0xFFFF0000u); }
+// f = hi + lo + O(2^-16 |f|), hi and lo bf16 (pairs converted together)
+__device__ inline void split8(const float* f, bf16x8& hi, bf16x8& lo) {
+    uint4 h, l;
+    uint32_t* hp = &h.x;
+    uint32_t* lp = &l.x;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint16_t h = f2bf(f[j]);
-        hi[j] = (short)h;
-        lo[j] = (short)f2bf(f[j] - bf2f(h));
+        hp[j] = pack_pair(f[2 * j], f[2 * j + 1]);
+        lp[j] = pack_pair(f[2 * j] - lo_of(hp[j]), f[2 * j + 1] - hi_of(hp[j]));
     }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+__device__ inline void split4(const float* f, i16x4& hi, i16x4& lo) {
+    uint2 h, l;
+    h.x = pack_pair(f[0], f[1]);
+    h.y = pack_pair(f[2], f[3]);
+    l.x = pack_pair(f[0] - lo_of(h.x), f[1] - hi_of(h.x));
+    l.y = pack_pair(f[2] - lo_of(h.y), f[3] - hi_of(h.y));
+    hi = __builtin_bit_cast(i16x4, h);
+    lo = __builtin_bit_cast(i16x4, l);
 }
 // offset of (channel c, column x) inside a channel-blocked row of length N
 __device__ inline int act_in_row(int N, int c, int x) { return ((c >> 3) * N + x) * 8 + (c & 7); }
 // store 4 channels c .. c + 3 (c % 4 == 0) at one column from an f32 tile column
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pack_bf2(float a, float b) {
+    const bf16x2 h = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+    return __builtin_bit_cast(uint32_t, h);
+}
+__device__ inline i16x4 pack_op4(float a, float b, float c, float d) {
+    uint2 w;
+    w.x = pack_bf2(a, b);
+    w.y = pack_bf2(c, d);
+    return __builtin_bit_cast(i16x4, w);
+}
 __device__ inline void store4(uint16_t* dst, const f32x4& v) {
     uint2 w;
-    w.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-    w.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+    w.x = pack_bf2(v[0], v[1]);
+    w.y = pack_bf2(v[2], v[3]);
     *reinterpret_cast<uint2*>(dst) = w;
 }
 
@@ -322,9 +346,12 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
     // LAST: the projected row [N], analysis partials [8][32], twiddles [N] (float2),
     // q1 and Q2 [2][H]; otherwise two buffers of per-wave analysis partials
     constexpr int LDS_F = KIND == RK_LAST ? (N + 8 * 32 + 2 * N + 2 * H) : (2 * 4 * C * XPITCH);
+    constexpr int ZP = 36;   // floats per (row, channel) of the staged Z rows
     __shared__ __align__(16) float lds[LDS_F];
+    __shared__ __align__(16) float zs[KIND == RK_LIFT ? 4 : RROWS * C * ZP];   // Z[r][o][k]
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, col = lane & 15, g = lane >> 4;
     const int b = blockIdx.y;
+    const int planes = gridDim.y * C;   // plane stride of Z and X' (LAST's output analysis: gridDim.y)
     const float* prm = a.prm;
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
 
@@ -410,17 +437,26 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
         __syncthreads();
     }
 
-    // inputs of a row (LAYER, LAST), loaded one row ahead
-    float4 zq[2][2];
+    // the Z rows of the workgroup's rows, staged in LDS as zs[r][o][k] (coalesced over the
+    // planes of this sample); activations loaded one row ahead
+    if constexpr (KIND != RK_LIFT) {
+#pragma unroll
+        for (int q = 0; q < RROWS * C * 32 / 4 / TPB; ++q) {
+            const int f = t + TPB * q;
+            const int o4 = f & 7, r = (f >> 3) % RROWS, n = f / (8 * RROWS);
+            const float4 z = *reinterpret_cast<const float4*>(
+                a.Z + ((size_t)n * N + blockIdx.x * RROWS + r) * planes + b * C + 4 * o4);
+            float* d = zs + (r * C + 4 * o4) * ZP + n;
+            d[0] = z.x;
+            d[ZP] = z.y;
+            d[2 * ZP] = z.z;
+            d[3 * ZP] = z.w;
+        }
+        __syncthreads();
+    }
     uint4 vq[XPW];
     auto load_row = [&](int yy) {
         const size_t ro = ((size_t)b * N + yy) * (size_t)(C * N);
-#pragma unroll
-        for (int ot = 0; ot < 2; ++ot) {
-            const float* zp = a.Z + (((size_t)b * C + 16 * ot + col) * N + yy) * 32 + 8 * g;
-            zq[ot][0] = *reinterpret_cast<const float4*>(zp);
-            zq[ot][1] = *reinterpret_cast<const float4*>(zp + 4);
-        }
         if constexpr (KIND == RK_LAYER)   // LAST loads them per tile (register budget)
 #pragma unroll
             for (int xt = 0; xt < XPW; ++xt)
@@ -448,9 +484,10 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct) {
-                    i16x4 vb;
+                    float l4[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) vb[j] = (short)f2bf(lw[ct][0] * fv[j] + lw[ct][1] * e + lw[ct][2]);
+                    for (int j = 0; j < 4; ++j) l4[j] = lw[ct][0] * fv[j] + lw[ct][1] * e + lw[ct][2];
+                    const i16x4 vb = pack_op4(l4[0], l4[1], l4[2], l4[3]);
 #pragma unroll
                     for (int nt = 0; nt < 2; ++nt) {
                         xa[ct][nt] = mfma16(bth[xt][nt], vb, xa[ct][nt]);
@@ -466,8 +503,10 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
             bf16x8 zh[2], zl[2];   // B(k = 8 g + j, o = 16 ot + col) = Z[o][k]
 #pragma unroll
             for (int ot = 0; ot < 2; ++ot) {
-                const float f[8] = {zq[ot][0].x, zq[ot][0].y, zq[ot][0].z, zq[ot][0].w,
-                                    zq[ot][1].x, zq[ot][1].y, zq[ot][1].z, zq[ot][1].w};
+                const float* zr = zs + (r * C + 16 * ot + col) * ZP + 8 * g;
+                const float4 z0 = *reinterpret_cast<const float4*>(zr);
+                const float4 z1 = *reinterpret_cast<const float4*>(zr + 4);
+                const float f[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
                 split8(f, zh[ot], zl[ot]);
             }
             bf16x8 vx[XPW];
@@ -476,8 +515,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 for (int xt = 0; xt < XPW; ++xt) vx[xt] = __builtin_bit_cast(bf16x8, vq[xt]);
             if (r + 1 < RROWS) load_row(y + 1);
             float* orow = lds;   // LAST: the projection of the row
-#pragma unroll
-            for (int xt = 0; xt < XPW; ++xt) {
+            auto tile = [&](int xt) {
                 const int x0 = (wave * XPW + xt) * 16;
                 i16x4 rb[2];
                 bf16x8 bh, bl, vt;
@@ -499,13 +537,11 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                     acc = mfma32(vt, ph[ot], acc);
                     acc = mfma32(vt, pl[ot], acc);
                     // acc[j] = u[o = 16 ot + col] at x = x0 + 4 g + j
-                    i16x4 vb, ub;
+                    float u[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float u = acc[j] + pbv[ot];
-                        ub[j] = (short)f2bf(u);
-                        vb[j] = KIND == RK_LAYER ? (short)f2bf(gelu(u)) : ub[j];
-                    }
+                    for (int j = 0; j < 4; ++j) u[j] = acc[j] + pbv[ot];
+                    const i16x4 ub = pack_op4(u[0], u[1], u[2], u[3]);
+                    const i16x4 vb = KIND == RK_LAYER ? pack_op4(gelu(u[0]), gelu(u[1]), gelu(u[2]), gelu(u[3])) : ub;
                     // tv[j] = value at channel 16 ot + 4 g + j, x = x0 + col
                     const f32x4 tv = mfma16(vb, ident, zero4);
                     if constexpr (KIND == RK_LAYER) {
@@ -520,8 +556,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                                    mfma16(ub, ident, zero4));
                     } else {
                         if (a.vout) store4(a.vout + rowo + act_in_row(N, 16 * ot + 4 * g, x0 + col), tv);
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) rb[ot][j] = (short)f2bf(tv[j]);
+                        rb[ot] = pack_op4(tv[0], tv[1], tv[2], tv[3]);
                     }
                 }
                 if constexpr (KIND == RK_LAST) {
@@ -546,6 +581,13 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                     s += __shfl_xor(s, 32, 64);
                     if (g == 0) orow[x0 + col] = s + q2c;
                 }
+            };
+            if constexpr (KIND == RK_LAYER) {
+#pragma unroll
+                for (int xt = 0; xt < XPW; ++xt) tile(xt);
+            } else {   // one tile at a time (register budget)
+#pragma unroll 1
+                for (int xt = 0; xt < XPW; ++xt) tile(xt);
             }
         }
 
@@ -560,7 +602,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                     for (int j = 0; j < 4; ++j)
                         xp[(wave * C + 16 * ct + col) * XPITCH + 16 * nt + 4 * g + j] = xa[ct][nt][j];
             __syncthreads();
-            const int c = t >> 3, n0 = (t & 7) * 4;
+            const int c = t & 31, n0 = (t >> 5) * 4;
             float4 sum = *reinterpret_cast<const float4*>(xp + c * XPITCH + n0);
 #pragma unroll
             for (int w = 1; w < 4; ++w) {
@@ -570,7 +612,12 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 sum.z += q.z;
                 sum.w += q.w;
             }
-            *reinterpret_cast<float4*>(a.xout + (((size_t)b * C + c) * N + y) * 32 + n0) = sum;
+            float* dst = a.xout + ((size_t)n0 * N + y) * planes + b * C + c;
+            const size_t ns = (size_t)N * planes;
+            dst[0] = sum.x;
+            dst[ns] = sum.y;
+            dst[2 * ns] = sum.z;
+            dst[3 * ns] = sum.w;
         } else {
             // x half of the analysis of the projected row: 8 parts of N / 8 points each
             __syncthreads();
@@ -589,113 +636,147 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 float sum = 0.f;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) sum += pp[q * 32 + t];
-                a.xout[((size_t)b * N + y) * 32 + t] = sum;
+                a.xout[((size_t)t * N + y) * gridDim.y + b] = sum;
             }
         }
     }
 }
 
-// Column kernels, one workgroup per plane p.  ANAL: V[m][p] = s sum_y X'[p][y][kx] e^{-i ky y}.
-// SYNTH: Z[p][y][kx] = sum_j s_kx U[m][p] e^{+i ky y} (without the mode kx = ky = 0 if
-// drop0).  X' and Z planar as above; m = kx * 32 + j, ky = j (j < 16) or N - 32 + j.
+// Column kernels on matrix cores.  m = kx * 32 + j is the mode index, ky_j = j (j < 16) or
+// N - 32 + j, phi = 2 pi ky_j y / N; spectra are [m][p] (plane fastest).
+//   ANAL:  V[m][p] = s sum_y X'[y][p] e^{-i phi}:  Re = C X're + S X'im, Im = C X'im - S X're
+//   SYNTH: Z[y][p] = sum_j w U[m][p] e^{+i phi}:   Re = C Ure - S Uim,   Im = S Ure + C Uim
+// with C = cos phi, S = sin phi from bf16 hi + lo tables (and the data split likewise:
+// hi hi + lo hi + hi lo per product, FP32 accuracy), w = s0 (kx = 0) or s1, and the mode
+// kx = ky = 0 left out of SYNTH if drop0.  One wave per (kx, 16 planes).
 __device__ inline int ky_of(int N, int j) { return j < MY ? j : N - 2 * MY + j; }
 
-// ANAL: thread = (kx pair, 4 j, y quarter); the quarters are added in order.
-template <int N>
-__global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float* xp, float s, float2* out,
-                                                  const float2* twg) {
-    __shared__ float2 tw[N];
-    __shared__ __align__(16) float2 X[N * MX];
-    __shared__ float4 part[3][TPB / 4][4];
-    const int t = threadIdx.x, p = blockIdx.x;
-    for (int i = t; i < N; i += TPB) tw[i] = twg[i];
-    for (int i = t; i < N * MX; i += TPB) {
-        const int y = i / MX, kx = i - y * MX;
-        const float* row = xp + ((size_t)p * N + y) * 32;
-        X[i] = make_float2(row[kx], row[16 + kx]);
-    }
-    __syncthreads();
-    const int kp = t & 7, jg = (t >> 3) & 7, q = t >> 6;
-    const int k0 = 2 * kp;
-    int ky[4];
+// trig tables: ta[part][cs][j][y] (ANAL, y fastest), ts[part][cs][y][j] (SYNTH, j fastest);
+// part 0/1 = hi/lo, cs 0/1 = cos/sin
+__global__ void __launch_bounds__(TPB) k_trig(int n, uint16_t* ta, uint16_t* ts) {
+    const int total = 2 * MY * n;
+    for (int e = blockIdx.x * TPB + threadIdx.x; e < total; e += gridDim.x * TPB) {
+        const int j = e / n, y = e - j * n;
+        const double a = 6.283185307179586476925286766559 * (double)(((long long)ky_of(n, j) * y) % n) / (double)n;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ky[i] = ky_of(N, 4 * jg + i);
-    float re[2][4], im[2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) re[h][i] = im[h][i] = 0.f;
-    for (int y = q * (N / 4); y < (q + 1) * (N / 4); ++y) {
-        const float4 xx = *reinterpret_cast<const float4*>(&X[y * MX + k0]);   // kx = k0, k0 + 1
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float2 w = tw[(ky[i] * y) & (N - 1)];
-            re[0][i] += xx.x * w.x + xx.y * w.y;
-            im[0][i] += xx.y * w.x - xx.x * w.y;
-            re[1][i] += xx.z * w.x + xx.w * w.y;
-            im[1][i] += xx.w * w.x - xx.z * w.y;
+        for (int cs = 0; cs < 2; ++cs) {
+            const float v = cs == 0 ? (float)cos(a) : (float)sin(a);
+            const uint16_t h = f2bf(v), l = f2bf(v - bf2f(h));
+            ta[(size_t)(0 * 2 + cs) * total + j * n + y] = h;
+            ta[(size_t)(1 * 2 + cs) * total + j * n + y] = l;
+            ts[(size_t)(0 * 2 + cs) * total + y * 2 * MY + j] = h;
+            ts[(size_t)(1 * 2 + cs) * total + y * 2 * MY + j] = l;
         }
-    }
-    const int slot = t & 63;
-    if (q > 0) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            part[q - 1][slot][2 * h] = make_float4(re[h][0], im[h][0], re[h][1], im[h][1]);
-            part[q - 1][slot][2 * h + 1] = make_float4(re[h][2], im[h][2], re[h][3], im[h][3]);
-        }
-    }
-    __syncthreads();
-    if (q == 0) {
-#pragma unroll
-        for (int qq = 0; qq < 3; ++qq)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const float4 a0 = part[qq][slot][2 * h], a1 = part[qq][slot][2 * h + 1];
-                re[h][0] += a0.x;
-                im[h][0] += a0.y;
-                re[h][1] += a0.z;
-                im[h][1] += a0.w;
-                re[h][2] += a1.x;
-                im[h][2] += a1.y;
-                re[h][3] += a1.z;
-                im[h][3] += a1.w;
-            }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                out[(size_t)((k0 + h) * 2 * MY + 4 * jg + i) * planes + p] = make_float2(re[h][i] * s, im[h][i] * s);
     }
 }
 
-// SYNTH: thread = (kx, y = t / 16 + 16 i); the 32 coefficients of its kx in registers.
+template <int N>
+__global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float* xp, float s, float2* out,
+                                                  const uint16_t* ta) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int ptiles = (planes + 15) / 16;
+    const int unit = blockIdx.x * 4 + wave;
+    if (unit >= MX * ptiles) return;
+    const int kx = unit / ptiles, p = (unit - kx * ptiles) * 16 + col;
+    const bool pin = p < planes;
+    const size_t tsz = (size_t)2 * MY * N;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    f32x4 are[2], aim[2], asr[2];   // [jt]: C X're + S X'im, C X'im, S X're
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) are[jt] = aim[jt] = asr[jt] = zero4;
+    for (int y0 = 0; y0 < N; y0 += 16) {
+        float xr[4], xi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = y0 + 4 * g + i;
+            xr[i] = pin ? xp[((size_t)kx * N + y) * planes + p] : 0.f;
+            xi[i] = pin ? xp[((size_t)(16 + kx) * N + y) * planes + p] : 0.f;
+        }
+        i16x4 rh, rl, ih, il;
+        split4(xr, rh, rl);
+        split4(xi, ih, il);
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt) {
+            const int o = (16 * jt + col) * N + y0 + 4 * g;
+            const i16x4 ch = ld_bf4(ta + o), sh = ld_bf4(ta + tsz + o);
+            const i16x4 cl = ld_bf4(ta + 2 * tsz + o), sl = ld_bf4(ta + 3 * tsz + o);
+            are[jt] = mfma16(ch, rh, are[jt]);
+            are[jt] = mfma16(cl, rh, are[jt]);
+            are[jt] = mfma16(ch, rl, are[jt]);
+            are[jt] = mfma16(sh, ih, are[jt]);
+            are[jt] = mfma16(sl, ih, are[jt]);
+            are[jt] = mfma16(sh, il, are[jt]);
+            aim[jt] = mfma16(ch, ih, aim[jt]);
+            aim[jt] = mfma16(cl, ih, aim[jt]);
+            aim[jt] = mfma16(ch, il, aim[jt]);
+            asr[jt] = mfma16(sh, rh, asr[jt]);
+            asr[jt] = mfma16(sl, rh, asr[jt]);
+            asr[jt] = mfma16(sh, rl, asr[jt]);
+        }
+    }
+    if (!pin) return;
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * jt + 4 * g + i;
+            out[(size_t)(kx * 2 * MY + j) * planes + p] = make_float2(are[jt][i] * s, (aim[jt][i] - asr[jt][i]) * s);
+        }
+}
+
 template <int N>
 __global__ void __launch_bounds__(TPB) k_col_synth(int planes, const float2* in, float s0, float s1, int drop0,
-                                                   float* zout, const float2* twg) {
-    __shared__ float2 tw[N];
-    const int t = threadIdx.x, p = blockIdx.x;
-    for (int i = t; i < N; i += TPB) tw[i] = twg[i];
-    const int kx = t & 15;
-    const float sc = kx == 0 ? s0 : s1;
-    float2 u[2 * MY];
+                                                   float* zout, const uint16_t* ts) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int ptiles = (planes + 15) / 16;
+    const int unit = blockIdx.x * 4 + wave;
+    if (unit >= MX * ptiles) return;
+    const int kx = unit / ptiles, p = (unit - kx * ptiles) * 16 + col;
+    const bool pin = p < planes;
+    const size_t tsz = (size_t)2 * MY * N;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    // B(j = 8 g + i, p = col) = w U[kx * 32 + j][p]
+    bf16x8 urh, url, uih, uil;
+    {
+        const float w = kx == 0 ? s0 : s1;
+        float ur[8], ui[8];
 #pragma unroll
-    for (int j = 0; j < 2 * MY; ++j) {
-        const float2 v = in[(size_t)(kx * 2 * MY + j) * planes + p];
-        const float f = (drop0 && kx == 0 && j == 0) ? 0.f : sc;
-        u[j] = make_float2(v.x * f, v.y * f);
-    }
-    __syncthreads();
-    for (int y = t >> 4; y < N; y += 16) {
-        float re = 0.f, im = 0.f;
-#pragma unroll
-        for (int j = 0; j < 2 * MY; ++j) {
-            const float2 w = tw[(ky_of(N, j) * y) & (N - 1)];
-            re += u[j].x * w.x - u[j].y * w.y;
-            im += u[j].x * w.y + u[j].y * w.x;
+        for (int i = 0; i < 8; ++i) {
+            const int j = 8 * g + i;
+            const float2 u = pin ? in[(size_t)(kx * 2 * MY + j) * planes + p] : make_float2(0.f, 0.f);
+            const float f = (drop0 && kx == 0 && j == 0) ? 0.f : w;
+            ur[i] = u.x * f;
+            ui[i] = u.y * f;
         }
-        float* row = zout + ((size_t)p * N + y) * 32;
-        row[kx] = re;
-        row[16 + kx] = im;
+        split8(ur, urh, url);
+        split8(ui, uih, uil);
+    }
+    for (int y0 = 0; y0 < N; y0 += 16) {
+        // A(y = y0 + col, j = 8 g + i)
+        const int o = (y0 + col) * 2 * MY + 8 * g;
+        const bf16x8 ch = ld_bf8(ts + o), sh = ld_bf8(ts + tsz + o);
+        const bf16x8 cl = ld_bf8(ts + 2 * tsz + o), sl = ld_bf8(ts + 3 * tsz + o);
+        f32x4 cr = zero4, si = zero4, zi = zero4;
+        cr = mfma32(ch, urh, cr);
+        cr = mfma32(cl, urh, cr);
+        cr = mfma32(ch, url, cr);
+        si = mfma32(sh, uih, si);
+        si = mfma32(sl, uih, si);
+        si = mfma32(sh, uil, si);
+        zi = mfma32(sh, urh, zi);
+        zi = mfma32(sl, urh, zi);
+        zi = mfma32(sh, url, zi);
+        zi = mfma32(ch, uih, zi);
+        zi = mfma32(cl, uih, zi);
+        zi = mfma32(ch, uil, zi);
+        if (pin) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = y0 + 4 * g + i;
+                zout[((size_t)kx * N + y) * planes + p] = cr[i] - si[i];
+                zout[((size_t)(16 + kx) * N + y) * planes + p] = zi[i];
+            }
+        }
     }
 }
 
@@ -717,7 +798,7 @@ __global__ void __launch_bounds__(TPB) k_pack(const float* wr, const float* wi, 
 // ---------------------------------------------------------------- projection and loss
 
 // pred = phi + the filtered increment without its mean: x half of the synthesis of
-// zo[b][y][32] (planar, kx weights and the dropped k = 0 mode applied by the column
+// zo[n][y][b] (planar, kx weights and the dropped k = 0 mode applied by the column
 // kernel).  With a target: lpart = sum (pred - target)^2 per workgroup, gpred =
 // 2 (pred - target) / (batch npts), gpart = its per-workgroup sums.
 template <int N>
@@ -731,7 +812,7 @@ __global__ void __launch_bounds__(TPB) k_finish(int batch, const float* phi, con
     const int t = threadIdx.x, b = blockIdx.y, r = t / N, x = t - r * N;
     const int y = blockIdx.x * R + r;
     for (int i = t; i < N; i += TPB) tw[i] = twg[i];
-    if (t < R * 32) zr[t] = zo[((size_t)b * N + blockIdx.x * R) * 32 + t];
+    if (t < R * 32) zr[t] = zo[((size_t)(t & 31) * N + blockIdx.x * R + (t >> 5)) * batch + b];
     __syncthreads();
     float inc = 0.f;
 #pragma unroll
@@ -1045,15 +1126,22 @@ hipError_t launch_row(int n, int batch, int kind, const RowIn& in, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const float2* tw,
+hipError_t launch_trig(int n, uint16_t* ta, uint16_t* ts, hipStream_t st) {
+    hipLaunchKernelGGL(k_trig, dim3((2 * MY * n + TPB - 1) / TPB), dim3(TPB), 0, st, n, ta, ts);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const uint16_t* ta,
                            hipStream_t st) {
-    FNO_LAUNCH_N(k_col_anal, dim3(planes), dim3(TPB), 0, st, planes, xp, s, out, tw)
+    const int units = MX * ((planes + 15) / 16);
+    FNO_LAUNCH_N(k_col_anal, dim3((units + 3) / 4), dim3(TPB), 0, st, planes, xp, s, out, ta)
     return hipGetLastError();
 }
 
 hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, bool drop0, float* zout,
-                            const float2* tw, hipStream_t st) {
-    FNO_LAUNCH_N(k_col_synth, dim3(planes), dim3(TPB), 0, st, planes, in, s0, s1, drop0 ? 1 : 0, zout, tw)
+                            const uint16_t* ts, hipStream_t st) {
+    const int units = MX * ((planes + 15) / 16);
+    FNO_LAUNCH_N(k_col_synth, dim3((units + 3) / 4), dim3(TPB), 0, st, planes, in, s0, s1, drop0 ? 1 : 0, zout, ts)
     return hipGetLastError();
 }
 

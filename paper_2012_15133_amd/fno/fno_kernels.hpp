@@ -34,11 +34,8 @@ constexpr int PART_LIFT = 2 * C + C;        // Lw, Lb
 constexpr int PART_MAX = PART_PROJ;
 
 // ---------------------------------------------------------------- bfloat16 storage
-__host__ __device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite values)
-    return (uint16_t)(u >> 16);
-}
+// float -> bf16 bits, round to nearest even (the hardware conversion of the target)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 __host__ __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 template <typename T>
@@ -48,10 +45,26 @@ __device__ inline float ldf<float>(const float* p, size_t i) { return p[i]; }
 template <>
 __device__ inline float ldf<uint16_t>(const uint16_t* p, size_t i) { return bf2f(p[i]); }
 
+// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, formula 7.1.26:
+// erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-a^2}, t = 1 / (1 + p a), a >= 0,
+// absolute error <= 1.5e-7 (plus FP32 rounding) -- far below the bf16 resolution of the
+// activations it feeds; branch free (the library erf takes two divergent paths).
+__device__ inline float erf_as(float x) {
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
+    return copysignf(fmaf(-q * t, e, 1.0f), x);
+}
+
 // gelu(z) = z Phi(z), Phi the standard normal distribution function; and its derivative
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ inline float gelu_d(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+           z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
 }
 
 // ---------------------------------------------------------------- kernel declarations
@@ -81,20 +94,22 @@ struct RowIn {
     const float* eps;    // LIFT: [b]
     const float* prm;
     int layer;           // LAYER (0 .. LAYERS - 2), LAST (LAYERS - 1)
-    const float* Z;      // LAYER, LAST: y half of the synthesis [b][C][n][32]
+    const float* Z;      // LAYER, LAST: y half of the synthesis [32][n][b C]
     const uint16_t* v;   // LAYER, LAST: activations in
     uint16_t* vout;      // activations out (LAST: v4, optional)
     uint16_t* uout;      // LAYER: pre-activations (optional)
-    float* xout;         // LIFT, LAYER: x half of the analysis [b][C][n][32]; LAST: of the output [b][n][32]
+    float* xout;         // LIFT, LAYER: x half of the analysis [32][n][b C]; LAST: of the output [32][n][b]
     const uint16_t* bx;
     const uint16_t* bxt;
     const float2* tw;
 };
 hipError_t launch_row(int n, int batch, int kind, const RowIn& in, hipStream_t st);
-hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const float2* tw,
+// trig tables of the column kernels: ta, ts [2][2][32][n] bf16 each
+hipError_t launch_trig(int n, uint16_t* ta, uint16_t* ts, hipStream_t st);
+hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const uint16_t* ta,
                            hipStream_t st);
 hipError_t launch_col_synth(int n, int planes, const float2* in, float s0, float s1, bool drop0, float* zout,
-                            const float2* tw, hipStream_t st);
+                            const uint16_t* ts, hipStream_t st);
 hipError_t launch_finish(int n, int batch, const float* phi, const float* zo, const float2* tw, const float* target,
                          float* pred, float* gpred, float* lpart, float* gpart, hipStream_t st);
 hipError_t launch_center(int n, int batch, const float* gpred, const float* gpart, float* gout, hipStream_t st);
