@@ -145,6 +145,28 @@ int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* ph
  * kernel launches are enqueued.  Errors: SPFC_E_INVAL, SPFC_E_DEVICE. */
 int spfc_step(spfc_ctx* ctx, double dt, int64_t n);
 
+/* Forcing (the manufactured-solution test of Section 5.1, whose forcing the paper adds
+ * without a formula): f(x, t) = sum_{i < terms} c_i(t) G_i(x), added to the phi equation
+ * of every step at t^{n+1}, i.e. psi -> psi + dt f^{n+1} in the right-hand side of the
+ * linear solve (eq. solver-3); the r equation (eq. solver-2) keeps a0 phi^{n+1} - psi.
+ * spfc_forcing_bytes: device bytes the forcing needs (terms + 1 half spectra), 1 <= terms
+ * <= SPFC_MAX_FORCING_TERMS.
+ * spfc_set_forcing: g_dev[i] (device, n_z x n_y x n_x doubles, x fastest) is G_i; they
+ * are transformed once into buf_dev (caller memory of spfc_forcing_bytes bytes, 256-byte
+ * aligned, kept until the forcing is replaced or the context destroyed).  terms = 0
+ * removes the forcing.  Synchronizes.
+ * spfc_step_forced: as spfc_step, the s-th step of the call (s = 0 .. n - 1) with the
+ * coefficients coef_dev[s * terms + i] = c_i(t^{n+1}) of its new time level (device
+ * memory, read by the kernels as they run: keep it until the stream has passed them).
+ * Direct launches (no graph replay).  Not offered with forcing (SPFC_E_INVAL): the ghost
+ * start of a context that has not started (it would need f^0) and the stabilized scheme.
+ * Errors: SPFC_E_INVAL (no forcing set, null or misaligned pointer, terms out of range,
+ * buffer too small), SPFC_E_DEVICE. */
+#define SPFC_MAX_FORCING_TERMS 16
+int spfc_forcing_bytes(spfc_ctx* ctx, int terms, size_t* bytes);
+int spfc_set_forcing(spfc_ctx* ctx, int terms, const double* const* g_dev, void* buf_dev, size_t bytes);
+int spfc_step_forced(spfc_ctx* ctx, double dt, int64_t n, const double* coef_dev);
+
 /* Mean of phi^n (synchronizes).  Theorem 2.1 keeps it at the mean of phi^0. */
 int spfc_mass(spfc_ctx* ctx, double* mean);
 

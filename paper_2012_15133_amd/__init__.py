@@ -14,5 +14,6 @@ from .binding import (  # noqa: F401
     spfc_batch_step_count, spfc_batch_status, spfc_batch_mass, spfc_batch_energy, spfc_batch_history,
     spfc_batch_get_phi, spfc_batch_destroy, spfc_batch_profile, spfc_batch_kernel_times,
     spfc_tune_bytes, spfc_tune, spfc_get_plan, spfc_batch_tune_bytes, spfc_batch_tune, spfc_batch_get_plan,
-    spfc_time_kernels, spfc_batch_time_kernels, spfc_batch_reset, spfc_batch_energies, spfc_batch_get_phi_all,
+    spfc_time_kernels, spfc_batch_time_kernels, spfc_batch_reset, spfc_batch_energies, spfc_batch_get_phi_all, spfc_forcing_bytes, spfc_set_forcing,
+    spfc_step_forced,
 )

@@ -29,7 +29,8 @@ EXPORTS = [
     "spfc_batch_get_phi", "spfc_batch_destroy", "spfc_batch_profile", "spfc_batch_kernel_times",
     "spfc_tune_bytes", "spfc_tune", "spfc_get_plan", "spfc_batch_tune_bytes", "spfc_batch_tune",
     "spfc_batch_get_plan", "spfc_time_kernels", "spfc_batch_time_kernels", "spfc_batch_reset",
-    "spfc_batch_energies", "spfc_batch_get_phi_all",
+    "spfc_batch_energies", "spfc_batch_get_phi_all", "spfc_forcing_bytes", "spfc_set_forcing",
+    "spfc_step_forced",
 ]
 
 
@@ -77,6 +78,9 @@ def load_library(path: str | None = None):
         "spfc_workspace_bytes": [P(spfc_grid), P(spfc_params), P(sz)],
         "spfc_init": [P(spfc_grid), P(spfc_params), vp, vp, sz, vp, P(vp)],
         "spfc_step": [vp, dbl, i64],
+        "spfc_forcing_bytes": [vp, i32, P(sz)],
+        "spfc_set_forcing": [vp, i32, P(vp), vp, sz],
+        "spfc_step_forced": [vp, dbl, i64, vp],
         "spfc_mass": [vp, P(dbl)],
         "spfc_energy": [vp, P(spfc_energy_t)],
         "spfc_history": [vp, i64, i64, P(spfc_record)],
@@ -180,6 +184,21 @@ def spfc_init(grid, params, phi0_ptr: int, workspace_ptr: int, workspace_bytes: 
 
 def spfc_step(ctx, dt: float, n: int):
     _check("spfc_step", load_library().spfc_step(ctx, float(dt), int(n)))
+
+
+def spfc_forcing_bytes(ctx, terms: int) -> int:
+    n = ctypes.c_size_t()
+    _check("spfc_forcing_bytes", load_library().spfc_forcing_bytes(ctx, int(terms), ctypes.byref(n)))
+    return n.value
+
+
+def spfc_set_forcing(ctx, terms: int, field_ptrs, buf_ptr: int, buf_bytes: int):
+    ptrs = (ctypes.c_void_p * max(1, len(field_ptrs)))(*field_ptrs) if field_ptrs else None
+    _check("spfc_set_forcing", load_library().spfc_set_forcing(ctx, int(terms), ptrs, buf_ptr, int(buf_bytes)))
+
+
+def spfc_step_forced(ctx, dt: float, n: int, coef_ptr: int):
+    _check("spfc_step_forced", load_library().spfc_step_forced(ctx, float(dt), int(n), coef_ptr))
 
 
 def spfc_mass(ctx) -> float:
@@ -465,6 +484,36 @@ class Solver:
 
     def step(self, dt, n=1):
         spfc_step(self.ctx, dt, n)
+
+    def set_forcing(self, fields):
+        """f(x, t) = sum_i c_i(t) fields[i](x) from now on (fields: arrays of the grid's
+        shape); an empty sequence removes the forcing."""
+        import numpy as np
+        torch = self.torch
+        if len(fields) == 0:
+            spfc_set_forcing(self.ctx, 0, [], None, 0)
+            self._forcing = None
+            self.forcing_terms = 0
+            return
+        dev = [_device_field(torch, np, f, tuple(reversed(self.n))) for f in fields]
+        nb = spfc_forcing_bytes(self.ctx, len(dev))
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        spfc_set_forcing(self.ctx, len(dev), [d.data_ptr() for d in dev], ptr, nb)
+        self._forcing = buf          # kept while the forcing is in use
+        self.forcing_terms = len(dev)
+
+    def step_forced(self, dt, coef):
+        """len(coef) steps of size dt; coef[s][i] = c_i at the new time level of step s."""
+        import numpy as np
+        if not getattr(self, "forcing_terms", 0):
+            raise ValueError("no forcing set (set_forcing)")
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(len(coef), -1))
+        if c.shape[1] != self.forcing_terms:
+            raise ValueError(f"coefficients have {c.shape[1]} terms, the forcing has {self.forcing_terms}")
+        dev = self.torch.from_numpy(c).to("cuda")
+        spfc_step_forced(self.ctx, dt, c.shape[0], dev.data_ptr())
+        self.stream.synchronize()    # the kernels read the coefficients as they run
 
     def energy(self):
         return spfc_energy(self.ctx)

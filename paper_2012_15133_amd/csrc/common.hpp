@@ -109,6 +109,7 @@ struct SpecInvArgs {
     double* part;           // no update: NPART_E partials of (X, Y) per workgroup
     size_t fs;              // member field stride (elements)
     const Geo* geos;
+    const cpx<T>* fhat;     // update: forcing spectrum of the pending step (or null)
 };
 
 // Rows of the half spectrum along x -> C2R (two real rows per complex line) ->
@@ -143,6 +144,7 @@ struct SpecFwdArgs {
     double* partE;          // NPART_E per workgroup
     size_t fs;
     const Geo* geos;
+    const cpx<T>* fhat;     // SOLVE_FORCED: forcing spectrum f^{n+1} of this step
 };
 
 // Generic batched line transform along the contiguous axis, with the output
@@ -189,9 +191,20 @@ struct UpdateArgs {
     double* part;            // NPART_E per workgroup
     size_t fs;
     const Geo* geos;
+    const cpx<T>* fhat;      // forcing spectrum of the pending step (or null)
 };
 
-enum { FWD_SOLVE = 0, FWD_GHOST = 1 };
+// Forcing spectrum of one step: out = sum_i coef[i] g[i] (terms spectra of one member).
+template <typename T>
+struct ForceArgs {
+    cpx<T>* out;
+    const cpx<T>* g;
+    int terms;
+    const double* coef;      // device, `terms` values
+    long long total;         // complex entries of one spectrum
+};
+
+enum { FWD_SOLVE = 0, FWD_GHOST = 1, FWD_SOLVE_FORCED = 2 };
 
 enum { FIN_STATE = 0, FIN_QUERY = 1, FIN_GHOST_R0 = 2, FIN_GHOST_RM1 = 3, FIN_RESTART = 4, FIN_STEP = 5 };
 

@@ -3,6 +3,8 @@
 #pragma once
 
 #include "kernels.hpp"
+#include <algorithm>
+
 #include "launch.hpp"
 
 #include <type_traits>
@@ -80,10 +82,14 @@ hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwd
         const dim3 g(s.grid, s.members), b(s.block);
         if (dim == 2) {
             if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST, false>), g, b, s.shmem, st, a);
+            else if (mode == FWD_SOLVE_FORCED)
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE_FORCED, false>), g, b, s.shmem, st, a);
             else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, true>), g, b, s.shmem, st, a);
             else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, false>), g, b, s.shmem, st, a);
         } else {
             if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST, false>), g, b, s.shmem, st, a);
+            else if (mode == FWD_SOLVE_FORCED)
+                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE_FORCED, false>), g, b, s.shmem, st, a);
             else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, true>), g, b, s.shmem, st, a);
             else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, false>), g, b, s.shmem, st, a);
         }
@@ -123,6 +129,13 @@ hipError_t Kern<T>::update(int dim, bool stab, const UpdateArgs<T>& a, int grid,
         if (stab) hipLaunchKernelGGL((k_update<T, 3, true>), g, b, 0, st, a);
         else hipLaunchKernelGGL((k_update<T, 3, false>), g, b, 0, st, a);
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Kern<T>::force(const ForceArgs<T>& a, hipStream_t st) {
+    const long long blocks = std::min<long long>((a.total + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_force<T>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

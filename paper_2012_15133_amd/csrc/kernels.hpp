@@ -397,8 +397,14 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
                 const double st = stab_sym<STAB>(geo, p.udt, k2);
                 const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2) + st);
                 const double f1 = -p.udt * xi * k2 * iA, f2 = (p.ua1 + st) * iA, f3 = p.ua2 * iA;
-                X = mk<T>(T(f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x),
-                          T(f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y));
+                double xr = f1 * nh[m].x + f2 * cur[m].x + f3 * prv[m].x;
+                double xi_ = f1 * nh[m].y + f2 * cur[m].y + f3 * prv[m].y;
+                if (p.fhat) {   // forcing of the pending step (not written by this kernel)
+                    const cpx<T> fh = p.fhat[lbase + e];
+                    xr += p.udt * iA * (double)fh.x;
+                    xi_ += p.udt * iA * (double)fh.y;
+                }
+                X = mk<T>(T(xr), T(xi_));
                 Y = cur[m];
                 p.out_new[lbase + e] = X;
             } else {
@@ -645,7 +651,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             }
             const double Nx = dy - 2.0 * k2 * phx;
             const double Ny = -dx - 2.0 * k2 * phy;
-            if constexpr (MODE == FWD_SOLVE) {
+            if constexpr (MODE != FWD_GHOST) {
                 const double psx = p.a1 * X.x + p.a2 * Y.x, psy = p.a1 * X.y + p.a2 * Y.y;
                 const double st = stab_sym<STAB>(geo, p.dt, k2);
                 const double iA = 1.0 / (p.a0 + p.dt * k2 * (geo.a + k2 * k2) + st);
@@ -654,6 +660,10 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
                 acc[0] -= w * k2 * (Nx * Nx + Ny * Ny) * iA;
                 if constexpr (STAB) acc[1] += w * (re + st * (Nx * X.x + Ny * X.y)) * iA;
                 else acc[1] += w * re * iA;
+                if constexpr (MODE == FWD_SOLVE_FORCED) {   // b2 = A^{-1} (psi + dt f): <N, b2> gains dt <N, A^{-1} f>
+                    const cpx<T> f = p.fhat[lbase + e];
+                    acc[1] += w * p.dt * (Nx * (double)f.x + Ny * (double)f.y) * iA;
+                }
                 acc[2] += w * re;
                 pair_partials<T, STAB>(X, Y, kx, k2, line == 0 && e == 0, geo, accE);
                 p.nhat[lbase + e] = mk<T>(T(Nx), T(Ny));
@@ -664,7 +674,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             }
         }
     }
-    if constexpr (MODE == FWD_SOLVE) {
+    if constexpr (MODE != FWD_GHOST) {
         const size_t wg = (size_t)mem * gridDim.x + blockIdx.x;
         block_sum_store<NPART_P>(acc, p.partP + NPART_P * wg);
         store_energy_partials<STAB>(accE, p.partE + NPART_E * wg);
@@ -689,14 +699,34 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs<T> p) {
         spec_index<DIM>(line, p.B, e, kx, ky, kz);
         spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
         const cpx<T> cur = p.cur[mbase + i], prv = p.prev[mbase + i], nh = p.nhat[mbase + i];
+        const cpx<T> fh = p.fhat ? p.fhat[mbase + i] : mk<T>(0, 0);
         const double st = stab_sym<STAB>(geo, p.udt, k2);
         const double iA = 1.0 / (p.ua0 + p.udt * k2 * (geo.a + k2 * k2) + st);
-        const double f1 = -p.udt * xi * k2 * iA, f2 = (p.ua1 + st) * iA, f3 = p.ua2 * iA;
-        const cpx<T> X = mk<T>(T(f1 * nh.x + f2 * cur.x + f3 * prv.x), T(f1 * nh.y + f2 * cur.y + f3 * prv.y));
+        const double f1 = -p.udt * xi * k2 * iA, f2 = (p.ua1 + st) * iA, f3 = p.ua2 * iA, f4 = p.udt * iA;
+        const cpx<T> X = mk<T>(T(f1 * nh.x + f2 * cur.x + f3 * prv.x + f4 * fh.x),
+                               T(f1 * nh.y + f2 * cur.y + f3 * prv.y + f4 * fh.y));
         p.out_new[mbase + i] = X;
         pair_partials<T, STAB>(X, cur, kx, k2, i == 0, geo, acc);
     }
     store_energy_partials<STAB>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
+}
+
+// ------------------------------------------------------------------ forcing of a step
+
+// f^{n+1} = sum_i c_i G_i on the half spectrum (the G_i transformed once); the scheme adds
+// dt f^{n+1} to the right-hand side psi of the step (b2 = A^{-1} (psi + dt f)).
+template <typename T>
+__global__ void __launch_bounds__(256) k_force(ForceArgs<T> p) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < p.total;
+         i += (long long)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < p.terms; ++k) {
+            const cpx<T> gk = p.g[(size_t)k * p.total + i];
+            re += p.coef[k] * (double)gk.x;
+            im += p.coef[k] * (double)gk.y;
+        }
+        p.out[i] = mk<T>(T(re), T(im));
+    }
 }
 
 // ------------------------------------------------------------------ rows: real <-> half spectrum

@@ -55,6 +55,7 @@ struct Kern {
     static hipError_t update(int dim, bool stab, const UpdateArgs<T>& a, int grid, int members, int block,
                              hipStream_t st);
     static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);
+    static hipError_t force(const ForceArgs<T>& a, hipStream_t st);
     // values per thread available for line length n
     static bool has_E(int n, int E) { return n < 16 ? E == n : (E == 4 || E == 8 || E == 16); }
     static hipError_t c2r_rows(int nx, bool out_fp32, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);

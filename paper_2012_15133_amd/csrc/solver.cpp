@@ -230,6 +230,8 @@ struct spfc_ctx {
     bool fin_in;       // close each step inside the next update kernel
     // graph replay of two steady steps
     bool use_graph;
+    char* force_buf = nullptr;   // caller memory: the combined forcing spectrum, then its terms
+    int force_terms = 0;
     std::vector<std::pair<std::tuple<double, int, int, int>, hipGraphExec_t>> graphs;  // newest last
     // profiling
     bool profiling;
@@ -383,6 +385,7 @@ struct Pipe {
         bool open = false;
         double a0 = 0, a1 = 0, a2 = 0, dt = 0;
         int check = 0;
+        bool forced = false;   // its right-hand side holds dt f (spectrum in force_buf)
     };
 
     // What a launch needs to close the step whose N is pending (all members).
@@ -431,6 +434,7 @@ struct Pipe {
         a.part = ctx->partQ();
         a.fs = ctx->lay.fs;
         a.geos = ctx->dgeos();
+        a.fhat = (pend.open && pend.forced) ? (const C*)ctx->force_buf : nullptr;
         {
             Timed tm(ctx, R_SPEC_INV, timed);
             for (int r = 0; r < tm.reps(); ++r)
@@ -480,8 +484,9 @@ struct Pipe {
     }
 
     int spec_fwd(char* const* in, const char* X, const char* Y, int mode, char* ghost_out, double a0, double a1,
-                 double a2, double dt, double e1, double e2, bool timed) {
+                 double a2, double dt, double e1, double e2, bool timed, const char* fhat = nullptr) {
         SpecFwdArgs<T> a{};
+        a.fhat = (const C*)fhat;
         for (int j = 0; j < 3; ++j) a.in[j] = (const C*)in[j];
         a.X = (const C*)X;
         a.Y = (const C*)Y;
@@ -590,8 +595,21 @@ struct Pipe {
 
     // One step: (pending update, closing that step), gradient and inverse passes,
     // real-space pass, forward pass + N + inner products; leaves this step pending.
+    // f^{n+1} of the next step into force_buf from its terms and coefficients coef[terms]
+    int force(const double* coef) {
+        ForceArgs<T> f{};
+        f.out = (C*)ctx->force_buf;
+        f.g = (const C*)(ctx->force_buf + ctx->lay.F);
+        f.terms = ctx->force_terms;
+        f.coef = coef;
+        f.total = (long long)ctx->lay.fs;
+        CK(Kern<T>::force(f, ctx->stream));
+        return SPFC_OK;
+    }
+
+    // coef (device, or null): forcing coefficients of this step
     int body(Pending& pend, double dt, double a0, double a1, double a2, double e1, double e2, int check,
-             bool timed) {
+             bool timed, const double* coef = nullptr) {
         int rc;
         if (!pend.open) {
             if ((rc = spec_inv(ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), nullptr, pend, e1, e2, true, timed)))
@@ -605,11 +623,14 @@ struct Pipe {
             ctx->slotX = target;
             ctx->step += 1;
         }
+        // the pending step's forcing has been read by the update above: now this step's
+        if (coef && (rc = force(coef))) return rc;
         char* fl[3];
         if ((rc = flux(timed, fl))) return rc;
-        if ((rc = spec_fwd(fl, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), FWD_SOLVE, nullptr, a0, a1, a2, dt, e1,
-                           e2, timed)))
+        if ((rc = spec_fwd(fl, ctx->slot(ctx->slotX), ctx->slot(ctx->slotY), coef ? FWD_SOLVE_FORCED : FWD_SOLVE,
+                           nullptr, a0, a1, a2, dt, e1, e2, timed, coef ? ctx->force_buf : nullptr)))
             return rc;
+        pend.forced = coef != nullptr;
         pend.open = true;
         pend.a0 = a0;
         pend.a1 = a1;
@@ -666,7 +687,9 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    int steps(double dt, int64_t n) {
+    // n steps of size dt; coef (device, n x force_terms, or null): the forcing
+    // coefficients of each step (its f^{n+1})
+    int steps(double dt, int64_t n, const double* coef = nullptr) {
         int rc;
         const bool restart = !ctx->started || dt != ctx->dt_prev;
         bool first_order = false;
@@ -680,7 +703,7 @@ struct Pipe {
                 first_order = (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_SAV1);
             }
         }
-        const bool graphs = ctx->use_graph && !ctx->profiling && ctx->stream != nullptr;
+        const bool graphs = ctx->use_graph && !ctx->profiling && ctx->stream != nullptr && !coef;
         Pending pend;
         int64_t i = 0;
         while (i < n) {
@@ -696,8 +719,9 @@ struct Pipe {
             const bool sav1 = first_order && i == 0;
             const int check = (i == 0 && restart) ? 0 : 1;
             const bool timed = i >= ctx->timed_from;
-            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, timed);
-            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, timed);
+            const double* ci = coef ? coef + i * ctx->force_terms : nullptr;
+            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, timed, ci);
+            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, timed, ci);
             if (rc) return rc;
             ++i;
         }
@@ -720,6 +744,7 @@ struct Pipe {
         u.part = ctx->partQ();
         u.fs = ctx->lay.fs;
         u.geos = ctx->dgeos();
+        u.fhat = pend.forced ? (const C*)ctx->force_buf : nullptr;
         CK(Kern<T>::update(ctx->sz.dim, ctx->stab, u, ctx->sh.updGrid, ctx->M, 256, ctx->stream));
         if (u.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         ctx->slotY = ctx->slotX;
@@ -732,9 +757,9 @@ struct Pipe {
     }
 
     // Real fields (doubles, x fastest) of members m0 .. m0 + count - 1 -> their half
-    // spectra in slot `s`; real[j] is member m0 + j's field.  One launch per pass for up
+    // spectra at dst (a field region laid out like a slot); real[j] is member m0 + j's field.  One launch per pass for up
     // to ROW_TAB members.
-    int forward_real(const double* const* real, int m0, int count, int s) {
+    int forward_real(const double* const* real, int m0, int count, char* dst) {
         for (int c0 = 0; c0 < count; c0 += ROW_TAB) {
             const int cn = std::min(ROW_TAB, count - c0);
             const size_t mo = ctx->moff(m0 + c0);
@@ -770,7 +795,7 @@ struct Pipe {
         } else {
             p.in[0] = (const C*)(ctx->bufA(0) + mo);
         }
-        p.out[0] = (C*)(ctx->slot(s) + mo);
+        p.out[0] = (C*)(dst + mo);
         p.tws = ctx->lay.ntab / ctx->nl();
         p.nlines = ctx->nlines();
         p.B = ctx->lineB();
@@ -920,7 +945,7 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
             if ((r = p.write_tables())) return r;
             std::vector<const double*> in(M);
             for (int m = 0; m < M; ++m) in[m] = phi0[idx[m]];
-            if ((r = p.forward_real(in.data(), 0, M, 0))) return r;
+            if ((r = p.forward_real(in.data(), 0, M, ctx->slot(0)))) return r;
             // r^0 = sqrt(E_1(phi^0)) (after eq. scheme-SAV-initial-1)
             return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
         });
@@ -948,7 +973,7 @@ int reset_ctx(spfc_ctx* ctx, const int* idx, const double* const* phi) {
         int r;
         std::vector<const double*> in(ctx->M);
         for (int m = 0; m < ctx->M; ++m) in[m] = phi[idx[m]];
-        if ((r = p.forward_real(in.data(), 0, ctx->M, 0))) return r;
+        if ((r = p.forward_real(in.data(), 0, ctx->M, ctx->slot(0)))) return r;
         return p.e1_pass(ctx->slot(0), ctx->slot(0), FIN_RESTART);
     });
     if (rc) return rc;
@@ -1269,6 +1294,51 @@ int spfc_step(spfc_ctx* ctx, double dt, int64_t n) {
     if (!ctx) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
     return ctx_step(ctx, dt, n);
+}
+
+int spfc_forcing_bytes(spfc_ctx* ctx, int terms, size_t* bytes) {
+    if (!ctx || !bytes || terms < 1 || terms > SPFC_MAX_FORCING_TERMS) return SPFC_E_INVAL;
+    *bytes = (size_t)(terms + 1) * ctx->lay.F;
+    return SPFC_OK;
+}
+
+int spfc_set_forcing(spfc_ctx* ctx, int terms, const double* const* g_dev, void* buf_dev, size_t bytes) {
+    if (!ctx) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (terms == 0) {
+        ctx->force_buf = nullptr;
+        ctx->force_terms = 0;
+        return SPFC_OK;
+    }
+    size_t need = 0;
+    if (spfc_forcing_bytes(ctx, terms, &need) != SPFC_OK || !g_dev || !buf_dev || bytes < need ||
+        (reinterpret_cast<uintptr_t>(buf_dev) & 255u) != 0)
+        return SPFC_E_INVAL;
+    for (int i = 0; i < terms; ++i)
+        if (!g_dev[i]) return SPFC_E_INVAL;
+    char* buf = static_cast<char*>(buf_dev);
+    const int rc = with_pipe(ctx, [&](auto& p) -> int {
+        int r;
+        for (int i = 0; i < terms; ++i)
+            if ((r = p.forward_real(&g_dev[i], 0, 1, buf + (size_t)(i + 1) * ctx->lay.F))) return r;
+        return SPFC_OK;
+    });
+    if (rc) return rc;
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->force_buf = buf;
+    ctx->force_terms = terms;
+    return SPFC_OK;
+}
+
+int spfc_step_forced(spfc_ctx* ctx, double dt, int64_t n, const double* coef_dev) {
+    if (!ctx || !coef_dev || !ctx->force_buf) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
+    // the ghost start would need f^0 as well, and the forced kernels are the plain scheme's:
+    // neither is offered with forcing
+    if ((!ctx->started && ctx->prm.startup == SPFC_STARTUP_GHOST) || ctx->stab) return SPFC_E_INVAL;
+    if (ctx->broken) return SPFC_E_DEVICE;
+    if (n == 0) return SPFC_OK;
+    return with_pipe(ctx, [&](auto& p) { return p.steps(dt, n, coef_dev); });
 }
 
 int spfc_set_graph(spfc_ctx* ctx, int enable) {
