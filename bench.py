@@ -4,8 +4,10 @@ Workload (default): the large single 2-D run, 1024 x 1024 points, L = 128 pi,
 epsilon = 0.25, c4 = 1, phi0 = -0.2 + 0.05 U(-1,1) (SplitMix64 seed 2), dt = 0.01,
 FP64, first step first-order SAV then BDF2.  One "step" is one full SAV-BDF2
 step (all transforms, the pointwise flux, the reductions, the SAV scalar and both
-Fourier solves).  Warm-up steps continue the same run; then K steps are timed
-with HIP events on the solver's stream, inputs resident in HBM.
+Fourier solves).  Warm-up steps continue the same run; the launch plan (values per
+thread and threads per workgroup of each step kernel) is then tuned on the run
+itself (--tune trial steps, state kept); then K steps are timed with HIP events on
+the solver's stream, inputs resident in HBM.
 
 Prints one JSON line: grid-point-steps/s, the roofline of the dominant kernel
 (algorithmic bytes / its average launch duration, from HIP events around
@@ -264,8 +266,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(SURROGATES))
     ap.add_argument("--no-seq", action="store_true", help="ensembles: skip the one-after-another comparison")
-    ap.add_argument("--tune", type=int, default=0,
-                    help="ensembles: tune the launch plan of each size class with this many trial steps first")
+    ap.add_argument("--tune", type=int, default=10,
+                    help="tune the launch plan (each size class of an ensemble) with this many trial steps "
+                         "before the timed steps (0: the built-in plan)")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--reps", type=int, default=20, help="back-to-back launches per kernel for kernel durations")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -313,6 +316,7 @@ def main():
 
     if args.warmup > 0:
         s.step(dt, args.warmup)
+    plan = s.tune(dt, trial_steps=args.tune) if args.tune else None
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -355,7 +359,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(n), "L": [round(v, 6) for v in L], "epsilon": eps,
                    "dt": dt, "mean": mean, "seed": seed, "startup": "sav1",
-                   "launch": "graph" if args.graph else "direct"},
+                   "launch": "graph" if args.graph else "direct", "plan": plan or "default"},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "kernels": per_kernel,

@@ -1149,24 +1149,31 @@ int restore(spfc_ctx* ctx, const char* src, const HostState& hs) {
 }
 
 // Milliseconds of `trial` steps of size dt under plan tp, from the snapshot (after
-// two untimed steps that absorb any restart).
+// two untimed steps that absorb any restart): the smaller of two such timings, so that
+// one disturbed timing does not decide a choice.
 int time_plan(spfc_ctx* ctx, const TunePlan& tp, double dt, int64_t trial, const char* snap, const HostState& hs,
               hipEvent_t e0, hipEvent_t e1, float* ms) {
     set_plan(ctx, tp);
     int rc;
-    if ((rc = restore(ctx, snap, hs))) return rc;
-    if ((rc = ctx_step(ctx, dt, 2))) return rc;
-    CK(hipEventRecord(e0, ctx->stream));
-    if ((rc = ctx_step(ctx, dt, trial))) return rc;
-    CK(hipEventRecord(e1, ctx->stream));
-    CK(hipEventSynchronize(e1));
-    CK(hipEventElapsedTime(ms, e0, e1));
+    float best = 0.f;
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = restore(ctx, snap, hs))) return rc;
+        if ((rc = ctx_step(ctx, dt, 2))) return rc;
+        CK(hipEventRecord(e0, ctx->stream));
+        if ((rc = ctx_step(ctx, dt, trial))) return rc;
+        CK(hipEventRecord(e1, ctx->stream));
+        CK(hipEventSynchronize(e1));
+        float t = 0.f;
+        CK(hipEventElapsedTime(&t, e0, e1));
+        best = k == 0 ? t : std::min(best, t);
+    }
+    *ms = best;
     return SPFC_OK;
 }
 
 // Coordinate search over the values per thread (4, 8, 16) and workgroup size (128,
 // 256 threads) of each step kernel, one kernel at a time, keeping a change only if
-// it saves at least 1 %.  The run state is restored afterwards: tuning changes
+// it saves at least 2 %.  The run state is restored afterwards: tuning changes
 // nothing but the plan (and with it the rounding of the transforms).
 int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
     HostState hs;
@@ -1194,7 +1201,7 @@ int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
                 if (!plan_fits(ctx->sz, ctx->M, cand, lds_max)) continue;
                 float ms = 0.f;
                 if ((rc = time_plan(ctx, cand, dt, trial, snap, hs, e0, e1, &ms))) break;
-                if (ms < 0.99f * best_ms) {
+                if (ms < 0.98f * best_ms) {
                     best = cand;
                     best_ms = ms;
                 }

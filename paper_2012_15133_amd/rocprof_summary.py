@@ -37,12 +37,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _counter_means(d: str):
+def _counter_means(d: str, with_counts: bool = False):
     path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
     agg = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
         agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in agg.items()}
+    means = {k: sum(v) / len(v) for k, v in agg.items()}
+    if with_counts:
+        return means, {k: len(v) for k, v in agg.items()}
+    return means
 
 
 def _role(name: str):
@@ -68,7 +71,8 @@ def stats(src: str, out: str, command: str):
 
 
 def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, workload, F, dim, outdir, command):
-    fe, wr = _counter_means(fetch_dir), _counter_means(write_dir)
+    fe, counts = _counter_means(fetch_dir, with_counts=True)
+    wr = _counter_means(write_dir)
     cfe, cwr = _counter_means(cfetch_dir), _counter_means(cwrite_dir)
     copy_f = max(v for (k, c), v in cfe.items() if c == "FETCH_SIZE" and "copyBuffer" in k)
     copy_w = max(v for (k, c), v in cwr.items() if c == "WRITE_SIZE" and "copyBuffer" in k)
@@ -77,12 +81,19 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, workload, 
     alg = {"spec_inv": (4 + dim) * F, "real_pass": 2 * dim * F, "spec_fwd": (3 + dim) * F,
            "pass_y_inv": 6 * F, "pass_y_fwd": 6 * F}
     h = kernel_source_hash()
+    # per role, the launch-plan variant with the most dispatches (the one the run used after
+    # tuning; the tuner's trial variants appear a few times each)
+    pick = {}
+    for (name, c), v in fe.items():
+        role = _role(name)
+        if c == "FETCH_SIZE" and role in alg and (role not in pick or counts[(name, c)] > counts[(pick[role], c)]):
+            pick[role] = name
     summary = []
     for (name, c), v in fe.items():
         if c != "FETCH_SIZE":
             continue
         role = _role(name)
-        if role not in alg:
+        if role not in alg or pick.get(role) != name:
             continue
         w = wr.get((name, "WRITE_SIZE"))
         if w is None:
