@@ -533,3 +533,75 @@ def test_singular_initial_data_plain_vs_stabilized():
         for a, b in zip(recs, recs[1:]):
             assert b["energy"] <= a["energy"] * (1 + 1e-13)
         assert abs(recs[-1]["mean"] - np.mean(phi0)) <= 1e-13
+
+
+# ----------------------------------------------------------------- P5: one full step from a single mode
+
+def test_one_step_from_a_single_mode_closed_form():
+    """phi^n = phi^{n-1} = A cos(kappa x) (3m < N/2, so nothing aliases): N = n1 cos + n3 cos 3
+    (the P4 closed form), the solves act mode by mode, and every scalar of the step is a
+    closed expression in A, kappa, dt, a (derived by hand from eq. scheme-SAV-1:
+    A_k phi^{n+1} = psi + dt xi Delta N, a0 r^{n+1} - rho = <N, a0 phi^{n+1} - psi>/(2S)):
+    b1 = -k^2 n_k / A_k, b2 = 1.5 A / A_kappa on cos theta; p1, p2, p_psi are |Omega|/2 sums
+    of the mode products; xi = [rho + (a0 p2 - p_psi)/(2S)] / [a0 (S - dt p1/(2S))]."""
+    n, L, m, A, dt = 64, 8 * math.pi, 4, 0.3, 0.01
+    g = O.Grid((n, n), (L, L))
+    prm = O.Params(0.25)
+    kap = 2 * math.pi * m / L
+    X = np.tile(np.arange(n) * L / n, (n, 1))
+    phi = A * np.cos(kap * X)
+    S = math.sqrt(O.E1(g, prm, phi))
+    new, r_new, info = O.sav_step(g, prm, dt, phi, phi, S, S)
+    Om, a = L * L, prm.a
+    n1, n3 = 0.75 * A ** 3 * kap ** 4 - 2 * kap ** 2 * A, -0.75 * A ** 3 * kap ** 4
+    Ak = 1.5 + dt * kap ** 2 * (a + kap ** 4)
+    A3 = 1.5 + dt * 9 * kap ** 2 * (a + 81 * kap ** 4)
+    p1 = Om / 2 * (-kap ** 2 * n1 ** 2 / Ak - 9 * kap ** 2 * n3 ** 2 / A3)
+    p2 = Om / 2 * n1 * 1.5 * A / Ak
+    ppsi = Om / 2 * n1 * 1.5 * A
+    xi = (1.5 * S + (1.5 * p2 - ppsi) / (2 * S)) / (1.5 * (S - dt * p1 / (2 * S)))
+    ref = (dt * xi * (-kap ** 2 * n1 / Ak) + 1.5 * A / Ak) * np.cos(kap * X) \
+        + dt * xi * (-9 * kap ** 2 * n3 / A3) * np.cos(3 * kap * X)
+    assert np.max(np.abs(new - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert abs(info["p1"] - p1) <= 1e-13 * abs(p1)
+    assert abs(info["xi"] - xi) <= 1e-13
+    assert abs(r_new - xi * S) <= 1e-13 * S
+
+
+# ----------------------------------------------------------------- P15: self-convergence, r-consistency
+
+def _smooth(g, seed, amp=0.05, mmax=3):
+    rng = np.random.default_rng(seed)
+    xs = [np.arange(nj) * hj for nj, hj in zip(g.n, g.h)]
+    X, Y = np.meshgrid(xs[0], xs[1])
+    phi = np.full(g.shape, -0.2)
+    for _ in range(6):
+        th = 2 * np.pi * (int(rng.integers(-mmax, mmax + 1)) * X / g.L[0] + int(rng.integers(-mmax, mmax + 1)) * Y / g.L[1])
+        phi += amp * rng.uniform(-1, 1) * np.cos(th + rng.uniform(0, 2 * np.pi))
+    return phi
+
+
+@pytest.mark.parametrize("startup,order", [("sav1", 2), ("ghost", 2), ("copy", 1)])
+def test_self_convergence_and_r_consistency(startup, order):
+    """The 64^2 setup (L = 8 pi, epsilon = 0.25) to T = 1 with dt = 0.02, 0.01, 0.005, 0.0025
+    from smooth data (white noise is not in the asymptotic regime at these dt):
+    ||phi_dt - phi_dt/2|| / ||phi_dt/2 - phi_dt/4|| ~ 2^order, with order 2 for the
+    first-order SAV and the ghost start (Theorem 4.1) and 1 for the copy start (phi^{-1} =
+    phi^0 is an O(dt) change of the history: the restart rule of Section 5.2 costs one
+    order).  |r - sqrt(E_1(phi))| at T falls at least 3.6x per halving (second order or
+    better)."""
+    g = O.Grid((64, 64), (8 * math.pi,) * 2)
+    prm = O.Params(0.25)
+    phi0 = _smooth(g, 7)
+    dts = [0.02, 0.01, 0.005, 0.0025]
+    phis, gaps = [], []
+    for dt in dts:
+        out = O.run(g, prm, phi0, dt, int(round(1.0 / dt)), startup=startup, energies=False)
+        phis.append(out["phi"])
+        gaps.append(abs(out["r"] - math.sqrt(O.E1(g, prm, out["phi"]))))
+    lo, hi = (3.6, 4.4) if order == 2 else (1.8, 2.4)
+    for i in range(2):
+        ratio = np.linalg.norm(phis[i] - phis[i + 1]) / np.linalg.norm(phis[i + 1] - phis[i + 2])
+        assert lo <= ratio <= hi, (startup, ratio)
+    for i in range(3):
+        assert gaps[i] / gaps[i + 1] >= 3.6, (startup, gaps)
