@@ -207,3 +207,26 @@ def test_3d_full_size_properties():
     assert rel <= 1e-5
     a.close()
     b.close()
+
+
+def test_3d_512_fp32_largest_grid_properties():
+    """The largest 3-D grid of the FP32 path, 512^3 (h = pi/8): 30 steps; mass kept to FP32
+    round-off, modified energy not rising beyond FP32 noise, p1 <= 0, E_1 >= |Omega|, no flags
+    other than the energy-noise one."""
+    n = (512, 512, 512)
+    L = (64 * math.pi,) * 3
+    phi0 = noise_ic(n, -0.25, 5)
+    s = _solver(n, L, phi0, precision="fp32", history=31)
+    del phi0
+    s.step(0.005, 30)
+    hist = s.history(0, 31)
+    vol = (64 * math.pi) ** 3
+    m0 = hist[0]["mean"]
+    for k, h in enumerate(hist):
+        assert abs(h["mean"] - m0) <= 1e-6
+        if k > 0:
+            assert h["energy"] <= hist[k - 1]["energy"] * (1 + 1e-6)
+            assert h["p1"] <= 0.0
+            assert h["E1"] >= vol
+    assert s.status() & ~8 == 0
+    s.close()

@@ -169,3 +169,26 @@ def test_c2_full_length_properties():
             assert h["p1"] <= 0.0
             assert h["E1"] >= (128 * math.pi) ** 2
     s.close()
+
+
+@pytest.mark.parametrize("n", [(1024, 8), (8, 1024), (8, 8, 64), (64, 8, 8)])
+def test_extreme_aspect_ratios(n):
+    """The narrowest grids the transforms accept along one axis next to the widest."""
+    L = tuple(v * math.pi / 8 for v in n)
+    s, hist, ref = _compare_run(n, L, 0.25, 0.01, 20, 11, -0.15)
+    s.close()
+
+
+def test_zero_steps_change_nothing():
+    g = O.Grid((32, 32), (4 * math.pi,) * 2)
+    phi0 = noise_ic(g.shape, -0.2, 4)
+    s = _solver((32, 32), (4 * math.pi,) * 2, phi0, 0.25, history=8)
+    before = s.phi().cpu().numpy()
+    s.step(0.01, 0)
+    assert s.step_count() == 0
+    assert np.array_equal(s.phi().cpu().numpy(), before)
+    s.step(0.01, 3)
+    mid = s.phi().cpu().numpy()
+    s.step(0.01, 0)
+    assert s.step_count() == 3 and np.array_equal(s.phi().cpu().numpy(), mid)
+    s.close()
