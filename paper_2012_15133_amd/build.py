@@ -21,6 +21,8 @@ LIB = os.path.join(HERE, "libspfc.so")
 FNO_SRC = os.path.join(HERE, "fno")
 FNO_LIB = os.path.join(HERE, "libspfc_fno.so")
 FNO_SOURCES = ["fno_kernels.hip", "fno.cpp"]
+# roctx (ranges around the ABI calls) from the ROCm install
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 SOURCES = [f"kern_{p}_{k}.hip" for p in ("f64", "f32") for k in ("inv", "real", "fwd", "aux")] + [
     "finalize.hip", "solver.cpp"]
 
@@ -60,7 +62,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 print(out)
     for lib, ob in ((LIB, objs), (FNO_LIB, fobjs)):
         tmp = lib + ".tmp"
-        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *ob])
+        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *ob, *LINK])
         os.replace(tmp, lib)
     return LIB
 

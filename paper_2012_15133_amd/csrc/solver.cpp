@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "trace.hpp"
 #include "spfc.h"
 
 using namespace spfc;
@@ -1285,6 +1286,7 @@ int spfc_workspace_bytes(const spfc_grid* grid, const spfc_params* params, size_
 
 int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev, void* workspace_dev,
               size_t workspace_bytes, void* hip_stream, spfc_ctx** out) {
+    const TraceRange trace_("spfc_init");
     if (!out || !phi0_dev || !workspace_dev) return SPFC_E_INVAL;
     int rc = validate(grid, params);
     if (rc) return rc;
@@ -1298,6 +1300,7 @@ int spfc_init(const spfc_grid* grid, const spfc_params* params, const double* ph
 }
 
 int spfc_step(spfc_ctx* ctx, double dt, int64_t n) {
+    const TraceRange trace_("spfc_step");
     if (!ctx) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
     return ctx_step(ctx, dt, n);
@@ -1310,6 +1313,7 @@ int spfc_forcing_bytes(spfc_ctx* ctx, int terms, size_t* bytes) {
 }
 
 int spfc_set_forcing(spfc_ctx* ctx, int terms, const double* const* g_dev, void* buf_dev, size_t bytes) {
+    const TraceRange trace_("spfc_set_forcing");
     if (!ctx) return SPFC_E_INVAL;
     if (ctx->broken) return SPFC_E_DEVICE;
     if (terms == 0) {
@@ -1338,6 +1342,7 @@ int spfc_set_forcing(spfc_ctx* ctx, int terms, const double* const* g_dev, void*
 }
 
 int spfc_step_forced(spfc_ctx* ctx, double dt, int64_t n, const double* coef_dev) {
+    const TraceRange trace_("spfc_step_forced");
     if (!ctx || !coef_dev || !ctx->force_buf) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
     // the ghost start would need f^0 as well, and the forced kernels are the plain scheme's:
@@ -1372,16 +1377,19 @@ int spfc_mass(spfc_ctx* ctx, double* mean) {
 }
 
 int spfc_energy(spfc_ctx* ctx, spfc_energy_t* out) {
+    const TraceRange trace_("spfc_energy");
     if (!ctx || !out) return SPFC_E_INVAL;
     return ctx_energy(ctx, 0, out);
 }
 
 int spfc_history(spfc_ctx* ctx, int64_t first, int64_t count, spfc_record* out) {
+    const TraceRange trace_("spfc_history");
     if (!ctx || (!out && count > 0) || first < 0 || count < 0) return SPFC_E_INVAL;
     return ctx_history(ctx, 0, first, count, out);
 }
 
 int spfc_get_phi(spfc_ctx* ctx, void* out_dev, int dtype) {
+    const TraceRange trace_("spfc_get_phi");
     if (!ctx || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
     return ctx_get_phi(ctx, 0, out_dev, dtype);
 }
@@ -1393,6 +1401,7 @@ int spfc_state_bytes(spfc_ctx* ctx, size_t* bytes) {
 }
 
 int spfc_save_state(spfc_ctx* ctx, void* out_dev, size_t bytes) {
+    const TraceRange trace_("spfc_save_state");
     if (!ctx || !out_dev) return SPFC_E_INVAL;
     if (ctx->broken) return SPFC_E_DEVICE;
     size_t need = 0;
@@ -1422,6 +1431,7 @@ int spfc_save_state(spfc_ctx* ctx, void* out_dev, size_t bytes) {
 }
 
 int spfc_load_state(spfc_ctx* ctx, const void* in_dev, size_t bytes) {
+    const TraceRange trace_("spfc_load_state");
     if (!ctx || !in_dev) return SPFC_E_INVAL;
     if (ctx->broken) return SPFC_E_DEVICE;
     size_t need = 0;
@@ -1495,6 +1505,7 @@ int spfc_tune_bytes(spfc_ctx* ctx, size_t* bytes) {
 }
 
 int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes) {
+    const TraceRange trace_("spfc_tune");
     if (!ctx || !scratch_dev) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || trial_steps < 1) return SPFC_E_INVAL;
     if (scratch_bytes < snapshot_bytes(ctx)) return SPFC_E_NOMEM;
@@ -1503,6 +1514,7 @@ int spfc_tune(spfc_ctx* ctx, double dt, int64_t trial_steps, void* scratch_dev, 
 }
 
 int spfc_time_kernels(spfc_ctx* ctx, double dt, int reps, void* scratch_dev, size_t scratch_bytes) {
+    const TraceRange trace_("spfc_time_kernels");
     if (!ctx || !scratch_dev || reps < 1) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return SPFC_E_INVAL;
     if (scratch_bytes < snapshot_bytes(ctx)) return SPFC_E_NOMEM;
@@ -1534,6 +1546,7 @@ int spfc_batch_workspace_bytes(int count, const spfc_grid* grids, const spfc_par
 
 int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params, const double* const* phi0_dev,
                     void* workspace_dev, size_t workspace_bytes, void* hip_stream, spfc_batch** out) {
+    const TraceRange trace_("spfc_batch_init");
     if (!out || !phi0_dev || !workspace_dev) return SPFC_E_INVAL;
     int rc = validate_batch(count, grids, params);
     if (rc) return rc;
@@ -1580,6 +1593,7 @@ int spfc_batch_set_graph(spfc_batch* b, int enable) {
 }
 
 int spfc_batch_step(spfc_batch* b, double dt, int64_t n) {
+    const TraceRange trace_("spfc_batch_step");
     if (!b) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
     for (auto* c : b->cls) {
@@ -1671,6 +1685,7 @@ int spfc_batch_tune_bytes(spfc_batch* b, size_t* bytes) {
 }
 
 int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch_dev, size_t scratch_bytes) {
+    const TraceRange trace_("spfc_batch_tune");
     if (!b || !scratch_dev) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || trial_steps < 1) return SPFC_E_INVAL;
     for (auto* c : b->cls) {
@@ -1681,6 +1696,7 @@ int spfc_batch_tune(spfc_batch* b, double dt, int64_t trial_steps, void* scratch
 }
 
 int spfc_batch_time_kernels(spfc_batch* b, double dt, int reps, void* scratch_dev, size_t scratch_bytes) {
+    const TraceRange trace_("spfc_batch_time_kernels");
     if (!b) return SPFC_E_INVAL;
     for (auto* c : b->cls) {
         const int rc = spfc_time_kernels(c, dt, reps, scratch_dev, scratch_bytes);
@@ -1696,6 +1712,7 @@ int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8) {
 }
 
 int spfc_batch_reset(spfc_batch* b, const double* const* phi_dev, const double* r_shift) {
+    const TraceRange trace_("spfc_batch_reset");
     if (!b || !phi_dev) return SPFC_E_INVAL;
     for (size_t i = 0; i < b->npts.size(); ++i) {
         if (!phi_dev[i]) return SPFC_E_INVAL;
@@ -1727,6 +1744,7 @@ int spfc_batch_reset(spfc_batch* b, const double* const* phi_dev, const double* 
 }
 
 int spfc_batch_get_phi_all(spfc_batch* b, void* const* out_dev, int dtype) {
+    const TraceRange trace_("spfc_batch_get_phi_all");
     if (!b || !out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
     for (size_t i = 0; i < b->npts.size(); ++i)
         if (!out_dev[i]) return SPFC_E_INVAL;
@@ -1742,6 +1760,7 @@ int spfc_batch_get_phi_all(spfc_batch* b, void* const* out_dev, int dtype) {
 }
 
 int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out) {
+    const TraceRange trace_("spfc_batch_energies");
     if (!b || !out) return SPFC_E_INVAL;
     int worst = SPFC_OK;
     for (size_t c = 0; c < b->cls.size(); ++c) {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "fno_kernels.hpp"
+#include "trace.hpp"
 #include "spfc_fno.h"
 
 using namespace fno;
@@ -233,6 +234,7 @@ int spfc_fno_workspace_bytes(const spfc_fno_shape* shape, size_t* bytes) {
 
 int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* workspace_dev, size_t workspace_bytes,
                   void* hip_stream, spfc_fno** out) {
+    const spfc::TraceRange trace_("spfc_fno_init");
     if (!out || !params_dev || !workspace_dev || !shape_ok(shape)) return E_INVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) return E_INVAL;
     const Layout lay = layout_of(*shape);
@@ -275,6 +277,7 @@ int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* wo
 }
 
 int spfc_fno_forward(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, float* out_dev) {
+    const spfc::TraceRange trace_("spfc_fno_forward");
     int rc = check_call(f, batch);
     if (rc) return rc;
     if (!phi_dev || !eps_dev || !out_dev) return E_INVAL;
@@ -283,6 +286,7 @@ int spfc_fno_forward(spfc_fno* f, int batch, const float* phi_dev, const float* 
 
 int spfc_fno_grads(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, const float* target_dev,
                    float* loss_dev, float* grad_dev) {
+    const spfc::TraceRange trace_("spfc_fno_grads");
     int rc = check_call(f, batch);
     if (rc) return rc;
     if (!f->shape.train || !phi_dev || !eps_dev || !target_dev || !loss_dev || !grad_dev) return E_INVAL;
@@ -293,6 +297,7 @@ int spfc_fno_grads(spfc_fno* f, int batch, const float* phi_dev, const float* ep
 
 int spfc_fno_train_step(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, const float* target_dev,
                         float lr, float* loss_dev) {
+    const spfc::TraceRange trace_("spfc_fno_train_step");
     int rc = check_call(f, batch);
     if (rc) return rc;
     if (!f->shape.train || !phi_dev || !eps_dev || !target_dev || !loss_dev || !(lr > 0.f) || !std::isfinite(lr))

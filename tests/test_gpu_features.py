@@ -3,12 +3,15 @@ ring, error codes and full-size properties, all through the C ABI."""
 
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
 
 from oracle import spfc_oracle as O
 from paper_2012_15133_amd.inputs import noise_ic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -230,3 +233,58 @@ def test_3d_512_fp32_largest_grid_properties():
             assert h["E1"] >= vol
     assert s.status() & ~8 == 0
     s.close()
+
+
+def test_recovery_from_a_poisoned_state():
+    """Failure detection and recovery: a checkpoint is taken, a NaN is planted in one entry
+    of a copy of it (from the host, in the saved spectrum), loading that copy and stepping
+    sets NONFINITE; loading the good checkpoint clears the state (its flags are the saved
+    ones) and the run continues with a smaller dt (restart at the change) exactly as an
+    uninterrupted run from the checkpoint does."""
+    import torch
+    from paper_2012_15133_amd import binding as B
+    n, L = (32, 32), (4 * math.pi,) * 2
+    phi0 = noise_ic((32, 32), -0.2, 8)
+    s = _solver(n, L, phi0, history=64)
+    s.step(0.01, 20)
+    good = s.save_state().clone()
+    bad = good.clone()
+    # the checkpoint is an aligned header and two aligned half spectra (17 x 32 complex FP64
+    # each here); poison entry 5 of the newest one
+    F = 17 * 32 * 16
+    off = good.numel() - 2 * ((F + 255) // 256 * 256)
+    bad[off + 5 * 16: off + 5 * 16 + 8] = torch.tensor([float("nan")], dtype=torch.float64).view(torch.uint8).to("cuda")
+    s.load_state(bad)
+    s.step(0.01, 2)
+    assert s.status() & B.SPFC_FLAG_NONFINITE
+    s.load_state(good)
+    assert s.status() == 0
+    s.step(0.005, 10)
+    ref = _solver(n, L, phi0, history=64)
+    ref.load_state(good)
+    ref.step(0.005, 10)
+    assert s.status() == 0 and s.step_count() == ref.step_count() == 30
+    assert torch.equal(s.phi(), ref.phi())
+    s.close()
+    ref.close()
+
+
+def test_launch_blocking_debug_mode_gives_the_same_bits():
+    """HIP_LAUNCH_BLOCKING=1 (every launch synchronous, so an error is reported by the
+    launch that caused it; each launch's status is checked by the library) changes timing
+    only: a run in a child process under it equals the normal run bit for bit."""
+    import subprocess
+    import sys
+    code = ("import sys, math, hashlib; sys.path.insert(0, %r)\n"
+            "from paper_2012_15133_amd import Solver\n"
+            "from paper_2012_15133_amd.inputs import noise_ic\n"
+            "s = Solver((64, 64), (8 * math.pi,) * 2, noise_ic((64, 64), -0.2, 1), 0.25)\n"
+            "s.step(0.01, 30)\n"
+            "print(hashlib.sha256(s.phi().cpu().numpy().tobytes()).hexdigest())\n") % ROOT
+    outs = []
+    for blocking in ("0", "1"):
+        env = dict(os.environ, HIP_LAUNCH_BLOCKING=blocking)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(r.stdout.strip().splitlines()[-1])
+    assert outs[0] == outs[1]
