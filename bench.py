@@ -386,6 +386,8 @@ def main():
                    "launch": "graph" if args.graph else "direct", "plan": plan or "default"},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "achieved_from_traffic": (round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1)
+                                               if traffic else None),
                      "copy_GBps_measured": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
         "kernels": per_kernel,
         "sticky_flags": flags,
