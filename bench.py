@@ -251,7 +251,15 @@ def run_surrogate(args):
     phi32 = got.to(torch.float32)
     inf.forward(phi32, eps)
     t_fwd = R.timed(lambda: [inf.forward(phi32, eps) for _ in range(10)], inf.stream)
+    # per-kernel durations of the forward pass (each launch repeated back to back between
+    # HIP events on the network's stream); the roofline is taken for the kernel with the
+    # largest share of the pass
+    roles, _ = inf.time_forward(phi32, eps, reps=args.reps)
     inf.close()
+    dom = max(roles, key=lambda k: roles[k][0] * roles[k][2])
+    dom_ms, dom_bytes, _ = roles[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    copy_gbps = copy_bandwidth()
     for b in (plain, J.b, J.spare):
         b.close()
 
@@ -277,7 +285,12 @@ def run_surrogate(args):
                       "plain_ms_per_50_steps": t_plain[1] * 1e3 / jumps, "ms_per_jump": sec * 1e3 / jumps,
                       "speedup_vs_plain": t_plain[1] / sec, "forward_ms_batch64": t_fwd[0] * 1e3 / 10,
                       "train_ms_per_iter": t_train[0] * 1e3 / iters, "final_train_loss": loss},
-        "roofline": None,
+        "roofline": {"bound": "hbm", "kernel": "fno_" + dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": dom_bytes, "copy_GBps_measured": round(copy_gbps, 1),
+                     "frac_of_copy": round(achieved / copy_gbps, 4)},
+        "fno_kernels": {k: {"us_per_launch": round(v[0] * 1e3, 2), "launches_per_forward": v[2],
+                            "GBps": round(v[1] / (v[0] * 1e-3) / 1e9, 1)} for k, v in roles.items()},
     }
     print(json.dumps(out))
 

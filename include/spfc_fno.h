@@ -75,6 +75,20 @@ int spfc_fno_init(const spfc_fno_shape* shape, const float* params_dev, void* wo
  * longer needs phi). */
 int spfc_fno_forward(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, float* out_dev);
 
+/* Per-kernel timing of one forward pass (same inputs and output as spfc_fno_forward;
+ * out_dev must not alias phi_dev). Each launch of the pass is issued `reps` (1..1000)
+ * times back to back between two HIP events on the network's stream; the average
+ * duration of one launch is accumulated per kernel role. On return *count holds the
+ * number of roles that ran, and the first min(count, cap) entries of names (static
+ * strings owned by the library), avg_ms (mean duration of one launch of that role, over
+ * its launches in the pass), bytes (algorithmic HBM bytes of one launch: reads plus
+ * writes of activations, partial transforms and spectra) and launches (launches of the
+ * role in one pass) are filled. The output holds the forward result. Synchronises the
+ * stream. Returns SPFC_E_INVAL for bad arguments. */
+int spfc_fno_time_forward(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev,
+                          float* out_dev, int reps, int cap, const char** names, double* avg_ms,
+                          double* bytes, int* launches, int* count);
+
 /* Loss and gradient for `batch` samples with targets target_dev [batch][n][n]:
  * loss_dev (1 float) and grad_dev (param_count floats) receive the mean squared error
  * and its gradient with respect to the parameters (needs train = 1). */

@@ -75,6 +75,12 @@ Layout layout_of(const spfc_fno_shape& s) {
 
 }  // namespace
 
+// kernel roles of the forward pass (per-kernel timing)
+enum { FR_LIFT = 0, FR_COL_ANAL, FR_MIX, FR_COL_SYNTH, FR_LAYER, FR_LAST, FR_FILTER_ANAL, FR_FILTER_SYNTH, FR_FINISH,
+       FR_COUNT };
+const char* const kFnoRoles[FR_COUNT] = {"lift_row", "col_anal", "mix", "col_synth", "layer_row", "last_row",
+                                         "filter_anal", "filter_synth", "finish"};
+
 struct spfc_fno {
     spfc_fno_shape shape;
     Layout lay;
@@ -82,6 +88,11 @@ struct spfc_fno {
     hipStream_t stream;
     int64_t adam_t;
     bool broken;
+    // per-kernel timing of a forward pass (reps > 0 while spfc_fno_time_forward runs)
+    int reps = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double role_ms[FR_COUNT] = {}, role_bytes[FR_COUNT] = {};
+    int role_n[FR_COUNT] = {};
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -120,6 +131,26 @@ namespace {
         }                        \
     } while (0)
 
+// One launch of a forward-pass kernel; while timing, `reps` back-to-back launches between
+// two events on the stream (every launch of the pass is idempotent).
+template <class L>
+int run_role(spfc_fno* f, int role, double bytes, L&& launch) {
+    if (f->reps <= 0) {
+        CK(launch());
+        return OK;
+    }
+    CK(hipEventRecord(f->ev0, f->stream));
+    for (int r = 0; r < f->reps; ++r) CK(launch());
+    CK(hipEventRecord(f->ev1, f->stream));
+    CK(hipEventSynchronize(f->ev1));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, f->ev0, f->ev1));
+    f->role_ms[role] += (double)ms / f->reps;
+    f->role_bytes[role] = bytes;
+    f->role_n[role] += 1;
+    return OK;
+}
+
 int pack_all(spfc_fno* f) {
     for (int l = 0; l < LAYERS; ++l)
         CK(launch_pack_weights(f->prm() + p_wr(l), f->prm() + p_wi(l), f->wpk(l), f->stream));
@@ -132,6 +163,12 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     const float inv = 1.0f / ((float)n * (float)n);
     hipStream_t st = f->stream;
     const bool tr = f->shape.train != 0 && target;
+    int rc;
+    // algorithmic bytes of each role (reads + writes): activations bf16, X' and Z FP32
+    // [32][n][planes], spectra float2 [512][planes]
+    const double N = n, P = planes, B = batch;
+    const double act = P * N * N * 2, xz = 32.0 * N * P * 4, spec = (double)NMODE * P * 8;
+    const double xz1 = 32.0 * N * B * 4, spec1 = (double)NMODE * B * 8, fld = B * N * N * 4;
     // rows: lifting + x-analysis; per layer: y-analysis, mixing, y-synthesis, then the row
     // kernel (x-synthesis, pointwise layer, activation, next x-analysis; the last layer's
     // row kernel also projects and takes the x-analysis of the output)
@@ -144,29 +181,45 @@ int forward(spfc_fno* f, int batch, const float* phi, const float* eps, const fl
     in.tw = f->tw();
     in.vout = f->v(0);
     in.xout = f->xp();
-    CK(launch_row(n, batch, RK_LIFT, in, st));
+    if ((rc = run_role(f, FR_LIFT, fld + act + xz, [&] { return launch_row(n, batch, RK_LIFT, in, st); }))) return rc;
     // the output's x-analysis goes to out_raw's space (free during the forward pass)
     float* xo = f->at<float>(f->lay.out_raw);
     for (int l = 0; l < LAYERS; ++l) {
         const bool last = l == LAYERS - 1;
-        CK(launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->ta(), st));
-        CK(launch_mix(MIX_FWD, batch, f->vh(l), nullptr, f->wpk(l), f->uh(), nullptr, nullptr, st));
-        CK(launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, false, f->zz(), f->ts(), st));
+        if ((rc = run_role(f, FR_COL_ANAL, xz + spec,
+                           [&] { return launch_col_anal(n, planes, f->xp(), inv, f->vh(l), f->ta(), st); })))
+            return rc;
+        if ((rc = run_role(f, FR_MIX, 2 * spec + (double)NMODE * 64 * 64 * 2, [&] {
+                 return launch_mix(MIX_FWD, batch, f->vh(l), nullptr, f->wpk(l), f->uh(), nullptr, nullptr, st);
+             })))
+            return rc;
+        if ((rc = run_role(f, FR_COL_SYNTH, spec + xz,
+                           [&] { return launch_col_synth(n, planes, f->uh(), 1.0f, 2.0f, false, f->zz(), f->ts(), st); })))
+            return rc;
         in.layer = l;
         in.Z = f->zz();
         in.v = f->v(l);
         in.vout = (!last || tr) ? f->v(l + 1) : nullptr;
         in.uout = (tr && !last) ? f->u(l) : nullptr;
         in.xout = last ? xo : f->xp();
-        CK(launch_row(n, batch, last ? RK_LAST : RK_LAYER, in, st));
+        const double bytes = last ? act + xz + xz1 + (in.vout ? act : 0.0)
+                                  : 2 * act + 2 * xz + (in.uout ? act : 0.0);
+        if ((rc = run_role(f, last ? FR_LAST : FR_LAYER, bytes,
+                           [&] { return launch_row(n, batch, last ? RK_LAST : RK_LAYER, in, st); })))
+            return rc;
     }
     // the increment restricted to the retained modes, without its mean (the k = 0 mode
     // dropped), added to phi
-    CK(launch_col_anal(n, batch, xo, inv, f->uh(), f->ta(), st));
-    CK(launch_col_synth(n, batch, f->uh(), 1.0f, 2.0f, true, f->zz(), f->ts(), st));
-    CK(launch_finish(n, batch, phi, f->zz(), f->tw(), target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
-                     f->at<float>(f->lay.lpart), f->at<float>(f->lay.gpart), st));
-    return OK;
+    if ((rc = run_role(f, FR_FILTER_ANAL, xz1 + spec1,
+                       [&] { return launch_col_anal(n, batch, xo, inv, f->uh(), f->ta(), st); })))
+        return rc;
+    if ((rc = run_role(f, FR_FILTER_SYNTH, spec1 + xz1,
+                       [&] { return launch_col_synth(n, batch, f->uh(), 1.0f, 2.0f, true, f->zz(), f->ts(), st); })))
+        return rc;
+    return run_role(f, FR_FINISH, 2 * fld + xz1 + (target ? 2 * fld : 0.0), [&] {
+        return launch_finish(n, batch, phi, f->zz(), f->tw(), target, pred, tr ? f->at<float>(f->lay.gpred) : nullptr,
+                             f->at<float>(f->lay.lpart), f->at<float>(f->lay.gpart), st);
+    });
 }
 
 // Loss and gradient into the internal gradient buffer and loss_dev.
@@ -284,6 +337,41 @@ int spfc_fno_forward(spfc_fno* f, int batch, const float* phi_dev, const float* 
     return forward(f, batch, phi_dev, eps_dev, nullptr, out_dev);
 }
 
+int spfc_fno_time_forward(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, float* out_dev, int reps,
+                          int cap, const char** names, double* avg_ms, double* bytes, int* launches, int* count) {
+    const spfc::TraceRange trace_("spfc_fno_time_forward");
+    int rc = check_call(f, batch);
+    if (rc) return rc;
+    if (!phi_dev || !eps_dev || !out_dev || (const float*)out_dev == phi_dev || reps < 1 || reps > 1000 || !count || cap < 0 ||
+        (cap > 0 && (!names || !avg_ms || !bytes || !launches)))
+        return E_INVAL;
+    if (!f->ev0 && (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)) {
+        f->broken = true;
+        return E_DEVICE;
+    }
+    for (int i = 0; i < FR_COUNT; ++i) {
+        f->role_ms[i] = f->role_bytes[i] = 0.0;
+        f->role_n[i] = 0;
+    }
+    f->reps = reps;
+    rc = forward(f, batch, phi_dev, eps_dev, nullptr, out_dev);
+    f->reps = 0;
+    if (rc) return rc;
+    int k = 0;
+    for (int i = 0; i < FR_COUNT; ++i) {
+        if (f->role_n[i] == 0) continue;
+        if (k < cap) {
+            names[k] = kFnoRoles[i];
+            avg_ms[k] = f->role_ms[i] / f->role_n[i];
+            bytes[k] = f->role_bytes[i];
+            launches[k] = f->role_n[i];
+        }
+        ++k;
+    }
+    *count = k;
+    return OK;
+}
+
 int spfc_fno_grads(spfc_fno* f, int batch, const float* phi_dev, const float* eps_dev, const float* target_dev,
                    float* loss_dev, float* grad_dev) {
     const spfc::TraceRange trace_("spfc_fno_grads");
@@ -321,6 +409,8 @@ int spfc_fno_get_params(spfc_fno* f, float* params_dev) {
 int spfc_fno_destroy(spfc_fno* f) {
     if (!f) return E_INVAL;
     if (!f->broken) (void)hipStreamSynchronize(f->stream);
+    if (f->ev0) (void)hipEventDestroy(f->ev0);
+    if (f->ev1) (void)hipEventDestroy(f->ev1);
     delete f;
     return OK;
 }

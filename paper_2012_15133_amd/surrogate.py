@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 FNO_LIB_PATH = os.environ.get("SPFC_FNO_LIB", os.path.join(HERE, "libspfc_fno.so"))
 
 EXPORTS = ["spfc_fno_param_count", "spfc_fno_workspace_bytes", "spfc_fno_init", "spfc_fno_forward",
-           "spfc_fno_grads", "spfc_fno_train_step", "spfc_fno_get_params", "spfc_fno_destroy"]
+           "spfc_fno_time_forward", "spfc_fno_grads", "spfc_fno_train_step", "spfc_fno_get_params", "spfc_fno_destroy"]
 
 WIDTH, MODES, HIDDEN, LAYERS = 32, 512, 64, 4
 
@@ -44,6 +44,8 @@ def load_library(path: str | None = None):
         "spfc_fno_workspace_bytes": [P(spfc_fno_shape), P(sz)],
         "spfc_fno_init": [P(spfc_fno_shape), vp, vp, sz, vp, P(vp)],
         "spfc_fno_forward": [vp, i32, vp, vp, vp],
+        "spfc_fno_time_forward": [vp, i32, vp, vp, vp, i32, i32, P(ctypes.c_char_p), P(ctypes.c_double),
+                                  P(ctypes.c_double), P(i32), P(i32)],
         "spfc_fno_grads": [vp, i32, vp, vp, vp, vp, vp],
         "spfc_fno_train_step": [vp, i32, vp, vp, vp, f32, vp],
         "spfc_fno_get_params": [vp, vp],
@@ -86,6 +88,17 @@ def spfc_fno_init(shape, params_ptr: int, ws_ptr: int, ws_bytes: int, stream_ptr
 
 def spfc_fno_forward(h, batch: int, phi_ptr: int, eps_ptr: int, out_ptr: int):
     _check("spfc_fno_forward", load_library().spfc_fno_forward(h, int(batch), phi_ptr, eps_ptr, out_ptr))
+
+
+def spfc_fno_time_forward(h, batch: int, phi_ptr: int, eps_ptr: int, out_ptr: int, reps: int):
+    """Per-kernel timing of one forward pass: {role: (avg_ms, bytes, launches)}."""
+    cap = 16
+    names = (ctypes.c_char_p * cap)()
+    ms, nbytes = (ctypes.c_double * cap)(), (ctypes.c_double * cap)()
+    launches, count = (ctypes.c_int * cap)(), ctypes.c_int()
+    _check("spfc_fno_time_forward", load_library().spfc_fno_time_forward(
+        h, int(batch), phi_ptr, eps_ptr, out_ptr, int(reps), cap, names, ms, nbytes, launches, ctypes.byref(count)))
+    return {names[i].decode(): (ms[i], nbytes[i], launches[i]) for i in range(min(count.value, cap))}
 
 
 def spfc_fno_grads(h, batch: int, phi_ptr: int, eps_ptr: int, target_ptr: int, loss_ptr: int, grad_ptr: int):
@@ -188,6 +201,15 @@ class Surrogate:
         out = self.torch.empty_like(phi)
         spfc_fno_forward(self.h, phi.shape[0], phi.data_ptr(), eps.data_ptr(), out.data_ptr())
         return out
+
+    def time_forward(self, phi, eps, reps=20):
+        """Per-kernel timing of one forward pass (each launch repeated `reps` times back to
+        back between HIP events): {role: (avg_ms per launch, algorithmic bytes per launch,
+        launches per pass)}, and the forward result."""
+        phi, eps = self._inputs(phi, eps)
+        out = self.torch.empty_like(phi)
+        roles = spfc_fno_time_forward(self.h, phi.shape[0], phi.data_ptr(), eps.data_ptr(), out.data_ptr(), reps)
+        return roles, out
 
     def grads(self, phi, eps, target):
         phi, eps = self._inputs(phi, eps)

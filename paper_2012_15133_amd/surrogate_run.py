@@ -82,7 +82,8 @@ def train(net, traj, eps, iters: int, batch: int, lr: float, seed: int = 0, log_
 class Jumper:
     """Advance a SAV run of `batch` (members of one grid size) by jumps of JUMP steps;
     `spare` is a second batch of the same members.  The two swap roles on every accepted
-    jump: the running batch is always `self.b`."""
+    jump: the running batch is always `self.b`, and it is advanced only through jump() (the
+    energies of an accepted state are kept for the next jump)."""
 
     def __init__(self, batch, spare, net, eps, dt: float = DT, energy_tol: float = 0.0):
         import torch
@@ -98,6 +99,7 @@ class Jumper:
         self.pred = torch.empty((len(batch), n, n), dtype=torch.float64, device="cuda")
         self.accepted = 0
         self.rejected = 0
+        self._energies = None   # energies of the running batch's state, when known
 
     def decide(self, before, after):
         """Whether a restart `after` (made with r shifted by r - sqrt(E_1) of `before`)
@@ -112,9 +114,10 @@ class Jumper:
 
     def jump(self) -> bool:
         self.b.phi_all(self.phi)
-        before = self.b.energies()
+        before = self._energies if self._energies is not None else self.b.energies()
         self.pred.copy_(self.net.forward(self.phi, self.eps))
         shift = [p["r"] - math.sqrt(p["E1"]) for p in before]
+        after = None
         try:
             self.spare.reset(list(self.pred), shift)
         except SpfcError as e:
@@ -122,13 +125,16 @@ class Jumper:
                 raise
             ok = False       # a shifted r not positive: no jump
         else:
-            ok = self.decide(before, self.spare.energies())
+            after = self.spare.energies()
+            ok = self.decide(before, after)
         if ok:
             self.accepted += 1
             self.b, self.spare = self.spare, self.b
+            self._energies = after      # the new running state's, computed just now
             return True
         self.rejected += 1
         self.b.step(self.dt, JUMP)
+        self._energies = None
         return False
 
 

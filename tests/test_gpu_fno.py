@@ -136,3 +136,28 @@ def test_adam_steps_reduce_the_loss():
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.3 * losses[0]
     net.close()
+
+
+def test_per_kernel_timing_leaves_the_result_unchanged():
+    """The per-kernel timing call repeats each launch of a forward pass back to back; the
+    launches are idempotent, so its output equals the plain forward pass bit for bit, and
+    it reports each kernel role with its launch count per pass."""
+    from paper_2012_15133_amd.binding import SpfcError
+    from paper_2012_15133_amd.surrogate import Surrogate, spfc_fno_time_forward
+    p = _params(9)
+    phi, eps, _ = _batch(4, 10)
+    net = Surrogate(N, p, max_batch=4)
+    ref = net.forward(phi, eps)
+    roles, got = net.time_forward(phi, eps, reps=3)
+    assert torch.equal(got, ref)
+    counts = {k: v[2] for k, v in roles.items()}
+    assert counts == {"lift_row": 1, "col_anal": 4, "mix": 4, "col_synth": 4, "layer_row": 3, "last_row": 1,
+                      "filter_anal": 1, "filter_synth": 1, "finish": 1}
+    assert all(v[0] > 0 and v[1] > 0 for v in roles.values())
+    # the output must not alias the input (the last kernel adds the increment to phi)
+    x, e = net._inputs(phi, eps)
+    with pytest.raises(SpfcError):
+        spfc_fno_time_forward(net.h, 4, x.data_ptr(), e.data_ptr(), x.data_ptr(), 2)
+    with pytest.raises(SpfcError):
+        spfc_fno_time_forward(net.h, 4, x.data_ptr(), e.data_ptr(), ref.data_ptr(), 0)
+    net.close()
