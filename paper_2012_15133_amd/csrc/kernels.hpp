@@ -32,6 +32,9 @@ __device__ inline double hweight(int kx, int nx) { return (kx == 0 || 2 * kx == 
 
 // ------------------------------------------------------------------ reductions (FP64, fixed order)
 
+// Compiler barrier: no memory access is moved across it (issue order of loads).
+__device__ inline void issue_barrier() { asm volatile("" ::: "memory"); }
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -87,33 +90,80 @@ __device__ inline void block_tree(double (&acc)[NV], double (&out)[NV]) {
 
 // Sum two arrays of per-workgroup partials, a[j*NA + i] (j < na) and
 // b[j*NB + i] (j < nb), over the workgroup.  Each thread reads a fixed subset,
-// U indices per sweep with every load issued before any is added; the order of
-// the sums depends only on the workgroup size, so every workgroup of a launch gets
-// the same bits.  Result (NA sums of a, then NB sums of b) in every thread.
+// U indices per sweep with every load of a sweep issued before any is added; the
+// order of the sums depends only on the workgroup size, so every workgroup of a
+// launch gets the same bits.  Result (NA sums of a, then NB sums of b) in every thread.
+//
+// PairSweep holds one sweep's loads, so that a kernel can issue the first sweep
+// before its own loads and reduce while those are in flight (block_sum_pair_from).
 template <int NA, int NB>
-__device__ inline void block_sum_pair(const double* a, int na, const double* b, int nb,
-                                      double (&out)[NA + NB]) {
-    constexpr int U = 4;
-    double acc[NA + NB];
-#pragma unroll
-    for (int i = 0; i < NA + NB; ++i) acc[i] = 0.0;
-    const int n = na > nb ? na : nb;
-    for (int j0 = threadIdx.x; j0 < n; j0 += U * blockDim.x) {
-        double v[U][NA + NB];
+struct PairSweep {
+    static constexpr int U = 4;
+    double v[U][NA + NB];
+    int j0, na, nb;
+    // Every lane loads (entry 0 in place of an index past the end, zeroed when added),
+    // so no branch separates these loads from the ones a kernel issues after them and
+    // the wait for them does not include those.  Needs a[0..NA) and b[0..NB) readable.
+    __device__ inline void load(const double* a, int na_, const double* b, int nb_, int j0_) {
+        j0 = j0_;
+        na = na_;
+        nb = nb_;
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int jj = j0 + q * blockDim.x;
+            const int jj = j0 + q * (int)blockDim.x;
+            const size_t ja = jj < na ? jj : 0, jb = jj < nb ? jj : 0;
 #pragma unroll
-            for (int i = 0; i < NA; ++i) v[q][i] = jj < na ? a[(size_t)jj * NA + i] : 0.0;
+            for (int i = 0; i < NA; ++i) v[q][i] = a[ja * NA + i];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) v[q][NA + i] = jj < nb ? b[(size_t)jj * NB + i] : 0.0;
+            for (int i = 0; i < NB; ++i) v[q][NA + i] = b[jb * NB + i];
         }
+    }
+    // Pin the loaded values at this point of the program: their wait is placed here,
+    // and no use of them (the sums) is moved above it.
+    __device__ inline void settle() {
 #pragma unroll
         for (int q = 0; q < U; ++q)
 #pragma unroll
-            for (int i = 0; i < NA + NB; ++i) acc[i] += v[q][i];
+            for (int i = 0; i < NA + NB; ++i) asm volatile("" : "+v"(v[q][i]));
+    }
+    __device__ inline void add_to(double (&acc)[NA + NB]) const {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int jj = j0 + q * (int)blockDim.x;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) acc[i] += jj < na ? v[q][i] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) acc[NA + i] += jj < nb ? v[q][NA + i] : 0.0;
+        }
+    }
+};
+
+// block_sum_pair with its first sweep (j0 = threadIdx.x) already loaded into `first`.
+// A thread with no index below max(na, nb) adds the zeros of its first sweep, which
+// leaves its sums at +0 as the plain loop does.
+template <int NA, int NB>
+__device__ inline void block_sum_pair_from(const PairSweep<NA, NB>& first, const double* a, int na, const double* b,
+                                           int nb, double (&out)[NA + NB]) {
+    constexpr int U = PairSweep<NA, NB>::U;
+    double acc[NA + NB];
+#pragma unroll
+    for (int i = 0; i < NA + NB; ++i) acc[i] = 0.0;
+    first.add_to(acc);
+    const int n = na > nb ? na : nb;
+    for (int j0 = threadIdx.x + U * blockDim.x; j0 < n; j0 += U * blockDim.x) {
+        PairSweep<NA, NB> s;
+        s.load(a, na, b, nb, j0);
+        s.add_to(acc);
     }
     block_tree<NA + NB>(acc, out);
+}
+
+template <int NA, int NB>
+__device__ inline void block_sum_pair(const double* a, int na, const double* b, int nb,
+                                      double (&out)[NA + NB]) {
+    PairSweep<NA, NB> first;
+    first.load(a, na, b, nb, threadIdx.x);
+    block_sum_pair_from<NA, NB>(first, a, na, b, nb, out);
 }
 
 // Three arrays of per-workgroup partials in one sweep (as block_sum_pair), result
@@ -320,15 +370,35 @@ __device__ inline FinishIn member_fin(const FinishIn& f, int m) {
     return r;
 }
 
+// What a pending update needs for xi, loaded before a kernel's own loads: the r
+// pair and the xi a separate finish left, and (fin) the first sweep of the partial
+// sums that give xi (E_1 partials, then the three inner-product partials).
+struct XiInputs {
+    PairSweep<1, NPART_P> first;
+    double xi, rn, rnm1;
+    __device__ inline void load(const FinishIn& fi, bool fin) {
+        xi = fi.sc_in->xi;
+        rn = fi.sc_in->r_n;
+        rnm1 = fi.sc_in->r_nm1;
+        if (fin) first.load(fi.partB, fi.nB, fi.partP, fi.nPE, threadIdx.x);
+    }
+    // wait for them here (PairSweep::settle)
+    __device__ inline void settle(bool fin) {
+        asm volatile("" : "+v"(xi), "+v"(rn), "+v"(rnm1));
+        if (fin) first.settle();
+    }
+};
+
 // Every workgroup of a launch reduces the previous step's partial sums in the
 // same order and gets the same xi; workgroup 0 also closes the step (records,
-// new scalar block).  All threads of the workgroup must call it.
-__device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double a1, double a2, double dt,
-                                          const Geo& geo) {
+// new scalar block).  All threads of the workgroup must call it.  `in` holds the
+// r pair and the first sweep of the partials (XiInputs::load with fin).
+__device__ inline double finish_in_kernel(const FinishIn& fi, const XiInputs& in, double a0, double a1, double a2,
+                                          double dt, const Geo& geo) {
     double sBP[1 + NPART_P];
-    block_sum_pair<1, NPART_P>(fi.partB, fi.nB, fi.partP, fi.nPE, sBP);
-    const double xi = sav_xi(sBP[0], sBP[1], sBP[2], sBP[3], fi.sc_in->r_n, fi.sc_in->r_nm1, a0, a1, a2, dt,
-                             geo.cell, geo.e1_const, geo.pscale);
+    block_sum_pair_from<1, NPART_P>(in.first, fi.partB, fi.nB, fi.partP, fi.nPE, sBP);
+    const double xi = sav_xi(sBP[0], sBP[1], sBP[2], sBP[3], in.rn, in.rnm1, a0, a1, a2, dt, geo.cell,
+                             geo.e1_const, geo.pscale);
     if (blockIdx.x == 0) {
         double sE[NPART_E];
         block_sum_partials<NPART_E>(fi.partE, fi.nPE, sE);
@@ -338,6 +408,13 @@ __device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double 
         }
     }
     return xi;
+}
+
+__device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double a1, double a2, double dt,
+                                          const Geo& geo) {
+    XiInputs in;
+    in.load(fi, true);
+    return finish_in_kernel(fi, in, a0, a1, a2, dt, geo);
 }
 
 // ------------------------------------------------------------------ spectral inverse pass
@@ -364,19 +441,31 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     const size_t mbase = (size_t)mem * p.fs;
 
     // all loads first (the update writes in place over `prev`, so later loads
-    // must not wait behind earlier stores)
+    // must not wait behind earlier stores), the partial sums of xi before the
+    // field values so that their reduction overlaps the field loads
+    const FinishIn fi = member_fin(p.fi, mem);
+    const bool fin = p.update && p.fin;
+    XiInputs xin;
+    if (p.update) xin.load(fi, fin);
+    issue_barrier();
+    // (lanes past the last line load line 0 of the member: finite values that reach
+    // no output, their symbols being zero)
     cpx<T> cur[E], prv[E], nh[E];
+    if (p.update) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) nh[m] = p.nhat[lbase + t + P * m];
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const size_t i = lbase + t + P * m;
-        cur[m] = act ? p.cur[i] : mk<T>(0, 0);
-        prv[m] = act ? p.prev[i] : mk<T>(0, 0);
-        nh[m] = (act && p.update) ? p.nhat[i] : mk<T>(0, 0);
+        cur[m] = p.cur[i];
+        prv[m] = p.prev[i];
     }
+    issue_barrier();
     double xi = 0.0;
     if (p.update) {
-        const FinishIn fi = member_fin(p.fi, mem);
-        xi = p.fin ? finish_in_kernel(fi, p.ua0, p.ua1, p.ua2, p.udt, geo) : fi.sc_in->xi;
+        xin.settle(fin);
+        xi = fin ? finish_in_kernel(fi, xin, p.ua0, p.ua1, p.ua2, p.udt, geo) : xin.xi;
     }
 
     double acc[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -469,6 +558,15 @@ __device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e) 
     return mk<T>(a.x - b.y, a.y + b.x);
 }
 
+// Two neighbouring complex values in one store (dst aligned to twice the element).
+template <typename T>
+__device__ inline void store_pair(cpx<T>* dst, cpx<T> a, cpx<T> b) {
+    struct alignas(2 * sizeof(cpx<T>)) Pair {
+        cpx<T> a, b;
+    };
+    *reinterpret_cast<Pair*>(dst) = Pair{a, b};
+}
+
 // Gradient rows (half spectra along x) -> C2R -> s = |grad phihat|^2,
 // E_1 partial sum (c4/4) s^2 - s, q = c4 s grad phihat (eq. nonlinear chem pot-1) ->
 // R2C -> flux spectra written rotated [kx][rows].  FWD = false: E_1 only.
@@ -533,21 +631,42 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
         __syncthreads();
         if (act) {
             const T half = T(0.5);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                cpx<T>* o1 = p.out[PK::fa(c)] + mbase;
-                cpx<T>* o2 = p.out[PK::fb(c)] + mbase;
-                const int r1 = row0 + PK::ra(c), r2 = row0 + PK::rb(c);
+            auto split = [&](int c, int k, cpx<T>& q1, cpx<T>& q2) {
+                const cpx<T> Vk = lds[c * LdsLine<NX>::size + lds_pad<NX>(k)];
+                const cpx<T> Vm = lds[c * LdsLine<NX>::size + lds_pad<NX>((NX - k) & (NX - 1))];
+                q1 = mk<T>(half * (Vk.x + Vm.x), half * (Vk.y - Vm.y));
+                q2 = mk<T>(half * (Vk.y + Vm.y), half * (Vm.x - Vk.x));
+            };
+            if constexpr (DIM == 3) {
+                // the group's two rows are neighbours in every output: one store of the
+                // pair (rows row0, row0 + 1; row0 is even) per field and wavenumber
 #pragma unroll
                 for (int m = 0; m <= E / 2; ++m) {
                     const int k = t + P * m;
                     if (m == E / 2 && t != 0) break;
-                    const cpx<T> Vk = lds[c * LdsLine<NX>::size + lds_pad<NX>(k)];
-                    const cpx<T> Vm = lds[c * LdsLine<NX>::size + lds_pad<NX>((NX - k) & (NX - 1))];
-                    const cpx<T> q1 = mk<T>(half * (Vk.x + Vm.x), half * (Vk.y - Vm.y));
-                    const cpx<T> q2 = mk<T>(half * (Vk.y + Vm.y), half * (Vm.x - Vk.x));
-                    o1[(size_t)k * p.nrows + r1] = q1;
-                    o2[(size_t)k * p.nrows + r2] = q2;
+                    cpx<T> q1[C], q2[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) split(c, k, q1[c], q2[c]);
+                    const size_t o = mbase + (size_t)k * p.nrows + row0;
+                    store_pair(p.out[0] + o, q1[0], q1[1]);   // lines 0, 1: g_x of rows 0, 1
+                    store_pair(p.out[1] + o, q2[0], q2[1]);   // g_y of rows 0, 1
+                    store_pair(p.out[2] + o, q1[2], q2[2]);   // line 2: g_z of rows 0, 1
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    cpx<T>* o1 = p.out[PK::fa(c)] + mbase;
+                    cpx<T>* o2 = p.out[PK::fb(c)] + mbase;
+                    const int r1 = row0 + PK::ra(c), r2 = row0 + PK::rb(c);
+#pragma unroll
+                    for (int m = 0; m <= E / 2; ++m) {
+                        const int k = t + P * m;
+                        if (m == E / 2 && t != 0) break;
+                        cpx<T> q1, q2;
+                        split(c, k, q1, q2);
+                        o1[(size_t)k * p.nrows + r1] = q1;
+                        o2[(size_t)k * p.nrows + r2] = q2;
+                    }
                 }
             }
         }
@@ -616,20 +735,32 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     const Geo geo = p.geos[mem];
     const size_t lbase = (size_t)mem * p.fs + (size_t)(act ? line : 0) * NL;
 
-    cpx<T> v[C][E];
+    // The flux lines, then the pair (X, Y), which is needed only after the transform.
+    // 3-D: the pair's loads are issued before the transform and are in flight while it
+    // runs (lanes past the last line load line 0 of the member; nothing of theirs
+    // reaches an output).  2-D: after it; there the early loads compete with the flux
+    // loads the transform waits for and the step is slower (measured on 1024^2).
+    cpx<T> v[C][E], Xs[E], Ys[E];
+    auto load_pair = [&](bool all) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            Xs[m] = (all || act) ? p.X[lbase + t + P * m] : mk<T>(0, 0);
+            Ys[m] = (all || act) ? p.Y[lbase + t + P * m] : mk<T>(0, 0);
+        }
+    };
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[j][m] = act ? p.in[j][lbase + t + P * m] : mk<T>(0, 0);
+        for (int m = 0; m < E; ++m)
+            v[j][m] = (DIM == 3 || act) ? p.in[j][lbase + t + P * m] : mk<T>(0, 0);
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
-    fft_run<T, PL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
-
-    cpx<T> Xs[E], Ys[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        Xs[m] = act ? p.X[lbase + t + P * m] : mk<T>(0, 0);
-        Ys[m] = act ? p.Y[lbase + t + P * m] : mk<T>(0, 0);
+    if constexpr (DIM == 3) {
+        load_pair(true);
+        issue_barrier();
     }
+    fft_run<T, PL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
+    if constexpr (DIM == 2) load_pair(false);
+
     double acc[NPART_P] = {0.0, 0.0, 0.0};
     double accE[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
