@@ -234,6 +234,17 @@ struct LdsLine {
     static constexpr int size = N + N / 16;
 };
 
+// LDS index of element i of a line in the exchanges between passes.  With 4 or 8 values
+// per thread (lines of 64 or more) an XOR swizzle of the low five bits by the bits above
+// log2(E), which puts the strided stores and loads of every pass on distinct banks (both
+// for 32 and for 64 four-byte banks, bank by bank over each wave's access); with 16 the
+// padded index already does.  Each map is a bijection of [0, N).
+template <int N, int E>
+__host__ __device__ constexpr int xch_index(int i) {
+    if constexpr ((E == 4 || E == 8) && N >= 64) return i ^ ((i >> ilog2(E)) & 31);
+    else return lds_pad<N>(i);
+}
+
 template <typename T, typename PL, int C, int PASS>
 __host__ __device__ inline void pass_store(const cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t) {
     constexpr int N = PL::Nl, E = PL::E, P = PL::P;
@@ -245,7 +256,7 @@ __host__ __device__ inline void pass_store(const cpx<T> (&v)[C][PL::E], cpx<T>* 
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[c * LdsLine<N>::size + lds_pad<N>(base + r * Ns)] = v[c][u + r * NB];
+            for (int r = 0; r < R; ++r) lds[c * LdsLine<N>::size + xch_index<N, E>(base + r * Ns)] = v[c][u + r * NB];
         }
     }
 }
@@ -260,7 +271,7 @@ __host__ __device__ inline void pass_load(cpx<T> (&v)[C][PL::E], const cpx<T>* l
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[c][u + r * NB] = lds[c * LdsLine<N>::size + lds_pad<N>(b + r * (N / R))];
+            for (int r = 0; r < R; ++r) v[c][u + r * NB] = lds[c * LdsLine<N>::size + xch_index<N, E>(b + r * (N / R))];
         }
     }
 }
