@@ -463,6 +463,23 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 vq[xt] = *reinterpret_cast<const uint4*>(a.v + ro + act_in_row(N, 8 * g, (wave * XPW + xt) * 16 + col));
     };
     if constexpr (KIND != RK_LIFT) load_row(blockIdx.x * RROWS);
+    // LAST: the operands of one x-tile (basis rows hi / lo, activations), loaded one tile
+    // ahead (the next row's first tile after a row's last) so that their loads overlap
+    // the current tile's products; the last prefetch of the workgroup re-reads its own row
+    struct TileOps {
+        bf16x8 bh, bl, vt;
+    };
+    auto load_tile = [&](int yy, int xt) {
+        const int x0 = (wave * XPW + xt) * 16;
+        const size_t ro = ((size_t)b * N + yy) * (size_t)(C * N);
+        TileOps o;
+        o.bh = ld_bf8(a.bx + (x0 + col) * 32 + 8 * g);
+        o.bl = ld_bf8(a.bx + N * 32 + (x0 + col) * 32 + 8 * g);
+        o.vt = ld_bf8(a.v + ro + act_in_row(N, 8 * g, x0 + col));
+        return o;
+    };
+    TileOps ahead{};
+    if constexpr (KIND == RK_LAST) ahead = load_tile(blockIdx.x * RROWS, 0);
 
     for (int r = 0; r < RROWS; ++r) {
         const int y = blockIdx.x * RROWS + r;
@@ -524,9 +541,11 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                     bl = bxl[xt];
                     vt = vx[xt];
                 } else {
-                    bh = ld_bf8(a.bx + (x0 + col) * 32 + 8 * g);
-                    bl = ld_bf8(a.bx + N * 32 + (x0 + col) * 32 + 8 * g);
-                    vt = ld_bf8(a.v + rowo + act_in_row(N, 8 * g, x0 + col));
+                    bh = ahead.bh;
+                    bl = ahead.bl;
+                    vt = ahead.vt;
+                    const bool row_end = xt + 1 == XPW;
+                    ahead = load_tile(row_end ? (r + 1 < RROWS ? y + 1 : y) : y, row_end ? 0 : xt + 1);
                 }
 #pragma unroll
                 for (int ot = 0; ot < 2; ++ot) {
@@ -670,31 +689,34 @@ __global__ void __launch_bounds__(TPB) k_trig(int n, uint16_t* ta, uint16_t* ts)
     }
 }
 
-template <int N>
+template <int N, int PT>
 __global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float* xp, float s, float2* out,
                                                   const uint16_t* ta) {
+    // A workgroup takes PT units (kx, 16 planes), consecutive in the planes.
+    // PT = 4 (many planes): one wave per unit walks all rows y, loading each 16-row step
+    // inside the loop.  PT = 1 (few planes: more workgroups): the four waves split the
+    // rows of one unit, issue all of their loads before their products, and their
+    // partial sums are added in wave order through LDS.
+    constexpr int YS = 4 / PT, IT = N / 16 / YS;   // row ranges per unit, 16-row steps per wave
+    __shared__ f32x4 part[YS > 1 ? YS - 1 : 1][6][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int tile = wave % PT, ys = wave / PT;
     const int ptiles = (planes + 15) / 16;
-    const int unit = blockIdx.x * 4 + wave;
-    if (unit >= MX * ptiles) return;
-    const int kx = unit / ptiles, p = (unit - kx * ptiles) * 16 + col;
-    const bool pin = p < planes;
+    const int unit = blockIdx.x * PT + tile;
+    const bool live = unit < MX * ptiles;
+    if (YS == 1 && !live) return;
+    const int un = live ? unit : 0;
+    const int kx = un / ptiles, p = (un - kx * ptiles) * 16 + col;
+    const bool pin = live && p < planes;
     const size_t tsz = (size_t)2 * MY * N;
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     f32x4 are[2], aim[2], asr[2];   // [jt]: C X're + S X'im, C X'im, S X're
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) are[jt] = aim[jt] = asr[jt] = zero4;
-    for (int y0 = 0; y0 < N; y0 += 16) {
-        float xr[4], xi[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int y = y0 + 4 * g + i;
-            xr[i] = pin ? xp[((size_t)kx * N + y) * planes + p] : 0.f;
-            xi[i] = pin ? xp[((size_t)(16 + kx) * N + y) * planes + p] : 0.f;
-        }
+    auto step = [&](const float (&fr)[4], const float (&fi)[4], int y0) {
         i16x4 rh, rl, ih, il;
-        split4(xr, rh, rl);
-        split4(xi, ih, il);
+        split4(fr, rh, rl);
+        split4(fi, ih, il);
 #pragma unroll
         for (int jt = 0; jt < 2; ++jt) {
             const int o = (16 * jt + col) * N + y0 + 4 * g;
@@ -712,6 +734,64 @@ __global__ void __launch_bounds__(TPB) k_col_anal(int planes, const float* xp, f
             asr[jt] = mfma16(sh, rh, asr[jt]);
             asr[jt] = mfma16(sl, rh, asr[jt]);
             asr[jt] = mfma16(sh, rl, asr[jt]);
+        }
+    };
+    if constexpr (YS == 1) {
+        for (int y0 = 0; y0 < N; y0 += 16) {
+            float fr[4], fi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = y0 + 4 * g + i;
+                fr[i] = pin ? xp[((size_t)kx * N + y) * planes + p] : 0.f;
+                fi[i] = pin ? xp[((size_t)(16 + kx) * N + y) * planes + p] : 0.f;
+            }
+            step(fr, fi, y0);
+        }
+    } else {
+        // lanes past the last plane read plane 0 and add zeros
+        const int pc = p < planes ? p : 0;
+        float xr[IT][4], xi[IT][4];
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = ys * (N / YS) + 16 * it + 4 * g + i;
+                xr[it][i] = xp[((size_t)kx * N + y) * planes + pc];
+                xi[it][i] = xp[((size_t)(16 + kx) * N + y) * planes + pc];
+            }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            float fr[4], fi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                fr[i] = pin ? xr[it][i] : 0.f;
+                fi[i] = pin ? xi[it][i] : 0.f;
+            }
+            step(fr, fi, ys * (N / YS) + 16 * it);
+        }
+        if (ys > 0) {
+            f32x4* d = &part[ys - 1][0][lane];
+            d[0] = are[0];
+            d[64] = are[1];
+            d[128] = aim[0];
+            d[192] = aim[1];
+            d[256] = asr[0];
+            d[320] = asr[1];
+        }
+        __syncthreads();
+        if (ys != 0) return;
+#pragma unroll
+        for (int w = 0; w < YS - 1; ++w) {
+            const f32x4* q = &part[w][0][lane];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                are[0][i] += q[0][i];
+                are[1][i] += q[64][i];
+                aim[0][i] += q[128][i];
+                aim[1][i] += q[192][i];
+                asr[0][i] += q[256][i];
+                asr[1][i] += q[320][i];
+            }
         }
     }
     if (!pin) return;
@@ -1133,8 +1213,25 @@ hipError_t launch_trig(int n, uint16_t* ta, uint16_t* ts, hipStream_t st) {
 
 hipError_t launch_col_anal(int n, int planes, const float* xp, float s, float2* out, const uint16_t* ta,
                            hipStream_t st) {
+    // four units per workgroup when that still gives two or more workgroups per CU, else
+    // one (few planes: the rows of a unit split over four waves); measured at batch 64
+    // (2048 and 64 planes) on 256^2
     const int units = MX * ((planes + 15) / 16);
-    FNO_LAUNCH_N(k_col_anal, dim3((units + 3) / 4), dim3(TPB), 0, st, planes, xp, s, out, ta)
+    if (units >= 2048) {
+        switch (n) {
+            case 64: hipLaunchKernelGGL((k_col_anal<64, 4>), dim3((units + 3) / 4), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            case 128: hipLaunchKernelGGL((k_col_anal<128, 4>), dim3((units + 3) / 4), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            case 256: hipLaunchKernelGGL((k_col_anal<256, 4>), dim3((units + 3) / 4), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (n) {
+            case 64: hipLaunchKernelGGL((k_col_anal<64, 1>), dim3(units), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            case 128: hipLaunchKernelGGL((k_col_anal<128, 1>), dim3(units), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            case 256: hipLaunchKernelGGL((k_col_anal<256, 1>), dim3(units), dim3(TPB), 0, st, planes, xp, s, out, ta); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 
