@@ -161,3 +161,24 @@ def test_per_kernel_timing_leaves_the_result_unchanged():
     with pytest.raises(SpfcError):
         spfc_fno_time_forward(net.h, 4, x.data_ptr(), e.data_ptr(), ref.data_ptr(), 0)
     net.close()
+
+
+def test_large_and_small_batches_agree():
+    """Batch 64 (2048 planes: the column analysis takes four units per workgroup, one
+    wave each) against batches of 4 (few planes: the rows of a unit split over four
+    waves): the same samples give the same increments up to FP32 summation order (which
+    can flip a bf16 rounding of a mixing operand, as against the oracle; measured 8.8e-4,
+    bound 5e-3), and
+    both stay within the oracle bound on samples the oracle checks."""
+    from paper_2012_15133_amd.surrogate import Surrogate
+    p = _params(11)
+    phi, eps, _ = _batch(64, 12)
+    net = Surrogate(N, p, max_batch=64)
+    big = net.forward(phi, eps).cpu().to(torch.float64)
+    small = torch.cat([net.forward(phi[i:i + 4], eps[i:i + 4]).cpu().to(torch.float64) for i in range(0, 64, 4)])
+    e = _rel(big - phi, small - phi)
+    print(f"batch 64 vs batches of 4: increment rel L2 {e:.2e}")
+    assert e <= 5e-3
+    ref = F.forward(S, p, phi[:2], eps[:2], bf16=True)
+    assert _rel(big[:2] - phi[:2], ref - phi[:2]) <= 2e-2
+    net.close()
