@@ -636,10 +636,17 @@ class Batch:
         return spfc_batch_history(self.b, m, first, count)
 
     def reset(self, fields, r_shift=None):
-        """Start every member again from new fields (sequence of arrays or tensors); the
-        SAV variable is sqrt(E_1(field)) plus r_shift[m] when given."""
+        """Start every member again from new fields (sequence of arrays or tensors, or one
+        contiguous float64 device tensor [members, n_y, n_x] when all members have one grid
+        size); the SAV variable is sqrt(E_1(field)) plus r_shift[m] when given."""
         import numpy as np
         torch = self.torch
+        if isinstance(fields, torch.Tensor) and fields.is_cuda and fields.dtype == torch.float64 \
+                and fields.is_contiguous() and fields.dim() == len(self.ns[0]) + 1 and fields.shape[0] == len(self.ns) \
+                and all(tuple(reversed(n)) == tuple(fields.shape[1:]) for n in self.ns):
+            step = fields[0].numel() * fields.element_size()
+            spfc_batch_reset(self.b, [fields.data_ptr() + m * step for m in range(len(self.ns))], r_shift)
+            return
         dev = [_device_field(torch, np, f, tuple(reversed(n))) for f, n in zip(fields, self.ns)]
         spfc_batch_reset(self.b, [d.data_ptr() for d in dev], r_shift)
         del dev

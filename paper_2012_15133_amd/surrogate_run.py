@@ -119,7 +119,7 @@ class Jumper:
         shift = [p["r"] - math.sqrt(p["E1"]) for p in before]
         after = None
         try:
-            self.spare.reset(list(self.pred), shift)
+            self.spare.reset(self.pred, shift)
         except SpfcError as e:
             if e.status != SPFC_E_INVAL:
                 raise

@@ -266,6 +266,27 @@ def test_phi_all_equals_per_member_fields_bitwise():
     b.close()
 
 
+def test_reset_from_one_tensor_equals_reset_from_a_list():
+    """Batch.reset takes either a sequence of fields or one contiguous [members, n_y, n_x]
+    float64 device tensor (pointers computed from its stride): same restart, same bits."""
+    import torch
+    from paper_2012_15133_amd import Batch
+    specs = [((64, 64), (8 * math.pi,) * 2, 0.1 + 0.05 * k, -0.2, 60 + k, "fp64") for k in range(4)]
+    members = _members(specs)
+    a, b = Batch(members, history=8), Batch(members, history=8)
+    a.step(0.01, 30)
+    fields = a.phi_all(torch.empty((4, 64, 64), dtype=torch.float64, device="cuda")).clone()
+    shift = [0.001 * (k + 1) for k in range(4)]
+    a.reset(fields, shift)
+    b.reset([fields[m].clone() for m in range(4)], shift)
+    for x, y in zip(a.energies(), b.energies()):
+        assert x["r"] == y["r"] and x["E1"] == y["E1"]
+    a.step(0.01, 10)
+    b.step(0.01, 10)
+    for m in range(4):
+        assert torch.equal(a.phi(m), b.phi(m))
+
+
 def test_reset_restarts_like_init_and_shifts_r():
     import torch
     from paper_2012_15133_amd import Batch
