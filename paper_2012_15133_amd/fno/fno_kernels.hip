@@ -349,6 +349,9 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int ZP = 36;   // floats per (row, channel) of the staged Z rows
     __shared__ __align__(16) float lds[LDS_F];
     __shared__ __align__(16) float zs[KIND == RK_LIFT ? 4 : RROWS * C * ZP];   // Z[r][o][k]
+    // LIFT: the input rows, double buffered; the next row is loaded (one value per thread)
+    // while the current one is lifted
+    __shared__ __align__(16) float phis[KIND == RK_LIFT ? 2 * N : 4];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, col = lane & 15, g = lane >> 4;
     const int b = blockIdx.y;
     const int planes = gridDim.y * C;   // plane stride of Z and X' (LAST's output analysis: gridDim.y)
@@ -463,6 +466,11 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
                 vq[xt] = *reinterpret_cast<const uint4*>(a.v + ro + act_in_row(N, 8 * g, (wave * XPW + xt) * 16 + col));
     };
     if constexpr (KIND != RK_LIFT) load_row(blockIdx.x * RROWS);
+    float phi_next = 0.f;
+    if constexpr (KIND == RK_LIFT) {
+        if (t < N) phis[t] = a.phi[((size_t)b * N + blockIdx.x * RROWS) * N + t];
+        __syncthreads();
+    }
     // LAST: the operands of one x-tile (basis rows hi / lo, activations), loaded one tile
     // ahead (the next row's first tile after a row's last) so that their loads overlap
     // the current tile's products; the last prefetch of the workgroup re-reads its own row
@@ -492,7 +500,8 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
 
         if constexpr (KIND == RK_LIFT) {
             const float e = a.eps[b];
-            const float* frow = a.phi + ((size_t)b * N + y) * N;
+            if (r + 1 < RROWS && t < N) phi_next = a.phi[((size_t)b * N + y + 1) * N + t];
+            const float* frow = phis + (r & 1) * N;
 #pragma unroll
             for (int xt = 0; xt < XPW; ++xt) {
                 const int x0 = (wave * XPW + xt) * 16;
@@ -620,6 +629,10 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         xp[(wave * C + 16 * ct + col) * XPITCH + 16 * nt + 4 * g + j] = xa[ct][nt][j];
+            // LIFT: the next input row into the other buffer (its last readers, the tiles of
+            // row r - 1, are behind the previous barrier); read after the barrier below
+            if constexpr (KIND == RK_LIFT)
+                if (r + 1 < RROWS && t < N) phis[((r + 1) & 1) * N + t] = phi_next;
             __syncthreads();
             const int c = t & 31, n0 = (t >> 5) * 4;
             float4 sum = *reinterpret_cast<const float4*>(xp + c * XPITCH + n0);
