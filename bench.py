@@ -95,9 +95,11 @@ def cpu_baseline(workload: str, steps: int):
     n, L, eps, mean, seed, dt, _ = WORKLOADS[workload]
     g = O.Grid(n, L)
     phi0 = noise_ic(g.shape, mean, seed)
-    t0 = time.perf_counter()
-    O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
-    sec = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):   # the single thread `cores` reports, whatever the host has
+        t0 = time.perf_counter()
+        O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
+        sec = time.perf_counter() - t0
     npts = int(np.prod(n))
     return {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps (first-order start + BDF2) of {workload} from the same seeded input, "
@@ -307,7 +309,7 @@ def main():
                          "before the timed steps (0: the built-in plan)")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--reps", type=int, default=20, help="back-to-back launches per kernel for kernel durations")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="1: replay the steady steps from a captured HIP graph")
     ap.add_argument("--copy-bytes", type=int, default=0,
