@@ -76,13 +76,6 @@ struct Plan {
         for (int q = 0; q < p; ++q) s *= radix(q);
         return s;
     }
-    // start of pass p in the pass-major twiddle table (entries Ns (R - 1) per pass,
-    // N - 1 in total)
-    static constexpr int tw_off(int p) {
-        int o = 0;
-        for (int q = 0; q < p; ++q) o += span(q) * (radix(q) - 1);
-        return o;
-    }
 };
 
 // ------------------------------------------------------------------ small DFTs
@@ -171,25 +164,28 @@ __host__ __device__ inline void dftR(cpx<T> (&a)[R]) {
 }
 
 // ------------------------------------------------------------------ passes
-// Twiddles are read from a pass-major table: for pass p (span Ns, radix R) the
-// entry at tw_off(p) + k (R - 1) + (r - 1) is exp(-2 pi i r k / (Ns R)),
-// k < Ns, 1 <= r < R.  Lanes of one butterfly slot then read consecutive
-// entries (R - 1 apart), which keeps LDS reads free of bank conflicts; a table
-// in natural order would put every lane at a multiple of N / (Ns R).
-//
-// build_pass_twiddles fills it from a natural table tw[j] = exp(-2 pi i j / (N tws)).
-template <typename T, typename PL, int PASS = 0>
-__host__ __device__ inline void build_pass_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ tw, int tws, int tid,
-                                                    int nthreads) {
-    constexpr int N = PL::Nl, R = PL::radix(PASS), Ns = PL::span(PASS);
-    if constexpr (Ns > 1) {
-        constexpr int cnt = Ns * (R - 1);
-        for (int j = tid; j < cnt; j += nthreads) {
-            const int k = j / (R - 1), r = j - k * (R - 1) + 1;
-            dst[PL::tw_off(PASS) + j] = tw[(size_t)r * k * (N / (Ns * R)) * tws];
-        }
-    }
-    if constexpr (PASS + 1 < PL::NP) build_pass_twiddles<T, PL, PASS + 1>(dst, tw, tws, tid, nthreads);
+// Twiddles: pass p (span Ns, radix R) scales input r of butterfly k by
+// w^j, j = r k N / (Ns R) < N, w = exp(-2 pi i / N) (conjugated for DIR = +1).
+// A workgroup stages two short tables in LDS, T2[b] = w^b (b < M) and
+// T1[a] = w^(a M) (a < N / M), M = 2^floor(log2(N) / 2), and forms
+// w^j = T1[j / M] T2[j mod M] with one complex product: about 2 sqrt(N) staged values
+// per workgroup instead of a full table of N - 1 (at 1024 points in FP64 that table was
+// 16 KB of loads per workgroup, as much as the line data of the real-space pass).
+template <int N>
+struct TwSplit {
+    static constexpr int S = ilog2(N) / 2;
+    static constexpr int M = 1 << S;       // entries of T2 (stored first)
+    static constexpr int A = N / M;        // entries of T1 (stored after T2)
+    static constexpr int size = M + A;     // <= N for N >= 4
+};
+
+// build_twiddles fills [T2 | T1] from a natural table tw[j] = exp(-2 pi i j / (N tws)).
+template <typename T, typename PL>
+__host__ __device__ inline void build_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ tw, int tws, int tid,
+                                               int nthreads) {
+    using TS = TwSplit<PL::Nl>;
+    for (int j = tid; j < TS::size; j += nthreads)
+        dst[j] = j < TS::M ? tw[(size_t)j * tws] : tw[(size_t)(j - TS::M) * TS::M * tws];
 }
 
 template <typename T, typename PL, int DIR, int C, int PASS>
@@ -200,11 +196,12 @@ __host__ __device__ inline void pass_compute(cpx<T> (&v)[C][PL::E], int t, const
     for (int u = 0; u < NB; ++u) {
         cpx<T> w[R];
         if constexpr (Ns > 1) {
+            using TS = TwSplit<PL::Nl>;
             const int k = (t + P * u) & (Ns - 1);
-            const cpx<T>* row = ptw + PL::tw_off(PASS) + k * (R - 1) - 1;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cpx<T> q = row[r];
+                const int j = r * k * (PL::Nl / (Ns * R));
+                const cpx<T> q = ptw[TS::M + (j >> TS::S)] * ptw[j & (TS::M - 1)];
                 w[r] = DIR > 0 ? conj(q) : q;
             }
         }
@@ -289,7 +286,7 @@ __host__ __device__ inline void line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* 
 // Whole transform on the device: all threads of the workgroup must call it
 // (it contains workgroup barriers).  lds points at this thread group's
 // C * LdsLine<N>::size elements.
-// ptw: the pass-major twiddle table of this plan (in LDS).
+// ptw: the two twiddle tables of this line length (TwSplit, in LDS).
 template <typename T, typename PL, int DIR, int C, int PASS = 0>
 __device__ inline void fft_run(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ ptw) {
     if constexpr (PASS == 0) {
@@ -305,12 +302,12 @@ __device__ inline void fft_run(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t, const 
     }
 }
 
-// Build this plan's pass-major twiddle table in LDS from the global natural table
+// Stage this line length's two twiddle tables in LDS from the global natural table
 // (spacing tws); every thread of the workgroup takes part.  The first pass reads
 // no twiddles and the barrier before the second pass orders these writes.
 template <typename T, typename PL>
 __device__ inline void stage_twiddles(cpx<T>* lds_tw, const cpx<T>* __restrict__ tw, int tws) {
-    build_pass_twiddles<T, PL>(lds_tw, tw, tws, threadIdx.x, blockDim.x);
+    build_twiddles<T, PL>(lds_tw, tw, tws, threadIdx.x, blockDim.x);
 }
 
 // Workgroup index remapped so that consecutive line blocks run on the same XCD

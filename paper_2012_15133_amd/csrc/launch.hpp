@@ -18,16 +18,22 @@ struct LaunchShape {
     int members;    // batch members (grid y)
 };
 
+// Entries of the two staged twiddle tables of a line of length n (TwSplit<n>::size).
+constexpr int tw_split_size(int n) { return (1 << (ilog2(n) / 2)) + n / (1 << (ilog2(n) / 2)); }
+static_assert(tw_split_size(8) == TwSplit<8>::size && tw_split_size(256) == TwSplit<256>::size &&
+                  tw_split_size(512) == TwSplit<512>::size && tw_split_size(1024) == TwSplit<1024>::size,
+              "host LDS size of the twiddle tables");
+
 // E values per thread (clamped to the line length), P = N / E threads per group,
 // C complex lines per group, ngroups groups in total.  LDS: the groups' line
-// buffers plus the twiddle table of length N.
+// buffers plus the two twiddle tables (about 2 sqrt(N) entries).
 inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int E = 16, int want_threads = 256,
                               size_t lds_cap = 65536) {
     E = std::min(E, N);
     if (N < 16) E = N;
     const int P = N / E;
     const size_t per = (size_t)C * (size_t)(N + N / 16) * elem;
-    const size_t twb = (size_t)N * elem;
+    const size_t twb = (size_t)tw_split_size(N) * elem;
     int G = std::max(1, want_threads / P);
     while (G > 1 && (size_t)G * per + twb > lds_cap) --G;
     G = std::max(1, std::min(G, ngroups));

@@ -41,7 +41,7 @@ static void emu(const double* in, double* out) {
             }
     std::vector<cpx<T>> lds(C * LdsLine<N>::size);
     std::vector<cpx<T>> ptw(N);
-    build_pass_twiddles<T, PL>(ptw.data(), tw.data(), 1, 0, 1);
+    build_twiddles<T, PL>(ptw.data(), tw.data(), 1, 0, 1);
     emu_passes<T, PL, DIR, C, 0>(regs, lds.data(), ptw.data());
     for (int t = 0; t < P; ++t)
         for (int c = 0; c < C; ++c)
