@@ -168,7 +168,8 @@ __host__ __device__ inline void dftR(cpx<T> (&a)[R]) {
 // w^j, j = r k N / (Ns R) < N, w = exp(-2 pi i / N) (conjugated for DIR = +1).
 // A workgroup stages two short tables in LDS, T2[b] = w^b (b < M) and
 // T1[a] = w^(a M) (a < N / M), M = 2^floor(log2(N) / 2), and forms
-// w^j = T1[j / M] T2[j mod M] with one complex product: about 2 sqrt(N) staged values
+// w^j = T1[j / M] T2[j mod M] with one complex product (for r = 1; the other inputs'
+// twiddles are its powers): about 2 sqrt(N) staged values
 // per workgroup instead of a full table of N - 1 (at 1024 points in FP64 that table was
 // 16 KB of loads per workgroup, as much as the line data of the real-space pass).
 template <int N>
@@ -196,14 +197,16 @@ __host__ __device__ inline void pass_compute(cpx<T> (&v)[C][PL::E], int t, const
     for (int u = 0; u < NB; ++u) {
         cpx<T> w[R];
         if constexpr (Ns > 1) {
+            // w^(r j1), j1 = k N / (Ns R): the first from the tables, the others as powers
+            // of it (R - 2 more complex products, about r ulp each, instead of R - 2 more
+            // pairs of LDS reads)
             using TS = TwSplit<PL::Nl>;
             const int k = (t + P * u) & (Ns - 1);
+            const int j = k * (PL::Nl / (Ns * R));
+            const cpx<T> q = ptw[TS::M + (j >> TS::S)] * ptw[j & (TS::M - 1)];
+            w[1] = DIR > 0 ? conj(q) : q;
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const int j = r * k * (PL::Nl / (Ns * R));
-                const cpx<T> q = ptw[TS::M + (j >> TS::S)] * ptw[j & (TS::M - 1)];
-                w[r] = DIR > 0 ? conj(q) : q;
-            }
+            for (int r = 2; r < R; ++r) w[r] = w[r - 1] * w[1];
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
