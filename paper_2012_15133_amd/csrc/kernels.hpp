@@ -35,7 +35,35 @@ __device__ inline double hweight(int kx, int nx) { return (kx == 0 || 2 * kx == 
 // Compiler barrier: no memory access is moved across it (issue order of loads).
 __device__ inline void issue_barrier() { asm volatile("" ::: "memory"); }
 
+// Cross-lane moves of a double (two 32-bit halves): a DPP move within rows of 16 lanes
+// (CTRL: quad permutation or row mirror) and a read of one lane.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ inline double lane_value(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the wave, the same bits in every lane.  Full waves (workgroups of a multiple
+// of 64 threads): DPP within each row of 16 lanes (lanes i ^ 1, i ^ 2, then the mirror
+// images within 8 and within 16, each step adding a commutative pair), then the four row
+// sums in a fixed order.  Otherwise (lanes past the end of the workgroup hold no data) the
+// xor butterfly through ds_bpermute.
 __device__ inline double wave_sum(double v) {
+    if ((blockDim.x & 63) == 0) {
+        v += dpp_move<0xB1>(v);    // quad permutation (1, 0, 3, 2)
+        v += dpp_move<0x4E>(v);    // quad permutation (2, 3, 0, 1)
+        v += dpp_move<0x141>(v);   // row half mirror
+        v += dpp_move<0x140>(v);   // row mirror
+        return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
