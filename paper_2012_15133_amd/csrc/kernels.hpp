@@ -445,6 +445,35 @@ __device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double 
     return finish_in_kernel(fi, in, a0, a1, a2, dt, geo);
 }
 
+// Store of transform results held in registers (element t + P m of each of C lines of
+// the group) to outputs in which, for each element e, the workgroup's G lines are
+// neighbours: through an LDS tile [c][e][g] (the line buffers, free once the transform is
+// done: C NL G <= G C LdsLine entries) so that consecutive threads store consecutive
+// lines.  The line index is swizzled by e when G is a power of two (bank spread).
+// idx(c, e, gi) gives the element's position in output c, or a negative value for a line
+// past the end.  All threads of the workgroup must call it.
+template <typename T, typename PL, int C, class Idx>
+__device__ inline void tiled_line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* tile, int G, int g, int t,
+                                        cpx<T>* const* out, size_t mbase, Idx idx) {
+    constexpr int NL = PL::Nl, E = PL::E, P = PL::P;
+    const int sw = (G & (G - 1)) == 0 ? G - 1 : 0;
+    __syncthreads();   // the transform's last reads of the line buffers are done
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = t + P * m;
+            tile[(c * NL + e) * G + (g ^ (e & sw))] = v[c][m];
+        }
+    __syncthreads();
+    const int gi = threadIdx.x % G, step = blockDim.x / G;
+    for (int ce = threadIdx.x / G; ce < C * NL; ce += step) {
+        const int c = ce / NL, e = ce - c * NL;
+        const long long i = idx(c, e, gi);
+        if (i >= 0) out[c][mbase + (size_t)i] = tile[(c * NL + e) * G + (gi ^ (e & sw))];
+    }
+}
+
 // ------------------------------------------------------------------ spectral inverse pass
 
 // One group of P threads per spectral line.  Optional pending update
@@ -539,7 +568,14 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     if (p.want_grad) {
         stage_twiddles<T, PL>(ltw, p.tw, p.tws);
         fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
-        if (act) {
+        if constexpr (DIM == 3) {
+            // rotated output [e][lines]: the workgroup's lines are neighbours for each e
+            const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
+            tiled_line_store<T, PL, C>(v, lds, p.G, g, t, p.out, mbase, [&](int, int e, int gi) -> long long {
+                const int ln = line0 + gi;
+                return ln < p.nlines ? (long long)e * p.nlines + ln : -1;
+            });
+        } else if (act) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 cpx<T>* o = p.out[j] + mbase;
@@ -787,6 +823,21 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
         for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][mbase + lbase + t + P * m] : mk<T>(0, 0);
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
     fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
+    if constexpr (C == 3 && OMODE != OUT_KEEP) {
+        // the step's y passes: for each e the workgroup's lines are (mostly) neighbours
+        const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
+        tiled_line_store<T, PL, C>(v, lds, p.G, g, t, p.out, mbase, [&](int, int e, int gi) -> long long {
+            const int ln = line0 + gi;
+            if (ln >= p.nlines) return -1;
+            if constexpr (OMODE == OUT_SWAP) {
+                const int a = ln / p.B, b = ln - a * p.B;
+                return ((long long)a * NL + e) * p.B + b;
+            } else {
+                return (long long)e * p.nlines + ln;
+            }
+        });
+        return;
+    }
     if (!act) return;
     const int a = line / p.B, b = line - a * p.B;
 #pragma unroll
