@@ -154,8 +154,10 @@ def test_line_fft_schedule_matches_dft(fp32, n, e):
                                      out.ctypes.data) == 0
             ref = x @ W.T
             err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
-            # FFT rounding grows like eps * log2(n)
-            assert err <= (4e-7 if fp32 else 2e-15 * np.log2(n)), (n, sign, c, err)
+            # FFT rounding grows like u log2(n) (u the unit roundoff; twiddles taken as powers
+            # of a table entry add a few u each): measured up to 1.1 u log2(n) in both precisions
+            bound = 8 * 2.0 ** -24 * np.log2(n) if fp32 else 2e-15 * np.log2(n)
+            assert err <= bound, (n, sign, c, err)
 
 
 def test_fno_header_declares_and_library_exports_all():
