@@ -88,22 +88,31 @@ def load_traffic(workload: str, kernel: str):
 
 
 def cpu_baseline(workload: str, steps: int):
-    """The oracle, as it is, on the first `steps` steps of the same run (host cores)."""
+    """The oracle, as it is, on the first `steps` steps of the same run (host cores).  Grids
+    above 2^20 points are sampled on a smaller grid of the same spacing and parameters
+    (every axis halved, L with it, same input recipe): one oracle step of 256^3 takes
+    minutes, and the rate is per grid point."""
     import numpy as np
     from oracle import spfc_oracle as O
     from paper_2012_15133_amd.inputs import noise_ic
     n, L, eps, mean, seed, dt, _ = WORKLOADS[workload]
-    g = O.Grid(n, L)
+    ns, Ls = tuple(n), tuple(L)
+    while int(np.prod(ns)) > 1 << 20:
+        ns, Ls = tuple(v // 2 for v in ns), tuple(v / 2 for v in Ls)
+    g = O.Grid(ns, Ls)
     phi0 = noise_ic(g.shape, mean, seed)
+    grid = "x".join(str(v) for v in ns)
+    print(f"cpu baseline: {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):   # the single thread `cores` reports, whatever the host has
         t0 = time.perf_counter()
         O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
         sec = time.perf_counter() - t0
-    npts = int(np.prod(n))
+    npts = int(np.prod(ns))
+    where = "" if ns == tuple(n) else f" on a {grid} grid of the same spacing and parameters"
     return {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps (first-order start + BDF2) of {workload} from the same seeded input, "
-                      f"{sec:.1f} s wall, numpy single thread"}
+            "sample": f"{steps} steps (first-order start + BDF2) of {workload}{where} from the same seeded "
+                      f"input recipe, {sec:.1f} s wall, numpy single thread"}
 
 
 ENSEMBLES = {
