@@ -104,10 +104,18 @@ def cpu_baseline(workload: str, steps: int):
     grid = "x".join(str(v) for v in ns)
     print(f"cpu baseline: {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):   # the single thread `cores` reports, whatever the host has
-        t0 = time.perf_counter()
-        O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
-        sec = time.perf_counter() - t0
+
+    def timed(k):
+        with threadpool_limits(limits=1):   # the single thread `cores` reports, whatever the host has
+            t0 = time.perf_counter()
+            O.run(g, O.Params(eps), phi0, dt, k, energies=False)
+            return time.perf_counter() - t0
+
+    sec = timed(steps)
+    if sec < 8.0:   # too short a sample on a fast host: about 15 s of steps instead
+        steps = min(int(steps * 15.0 / max(sec, 1e-3)), 50 * steps)
+        print(f"cpu baseline: {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
+        sec = timed(steps)
     npts = int(np.prod(ns))
     where = "" if ns == tuple(n) else f" on a {grid} grid of the same spacing and parameters"
     return {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
