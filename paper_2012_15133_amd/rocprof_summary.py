@@ -4,6 +4,7 @@ Usage:
   python -m paper_2012_15133_amd.rocprof_summary stats <kernel_stats.csv> <out.md> --command "<cmd>"
   python -m paper_2012_15133_amd.rocprof_summary traffic <fetch_dir> <write_dir> <copy_fetch_dir>
          <copy_write_dir> <copy_bytes> <workload> <F_bytes> <dim> <profiles_dir> --command "<cmd>"
+  python -m paper_2012_15133_amd.rocprof_summary counters <c1_dir> <c2_dir> <label>
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into HBM bytes per
 launch, each scaled by the factor that makes a device copy of known size read and
@@ -109,6 +110,42 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, workload, 
     return summary
 
 
+STEP_KERNELS = ("k_spec_inv", "k_real_pass", "k_spec_fwd", "k_pass")
+
+
+def counters(c1: str, c2: str, label: str):
+    """Table rows of the SQ counter sets C1 (cycles, waits) and C2 (instructions, LDS
+    conflicts, waves): per step-kernel variant the mean per dispatch.  Variants with fewer
+    than 8 dispatches (start-up, energy-only passes) are left out."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for k, d in ((1, c1), (2, c2)):
+        for path in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for row in csv.DictReader(open(path)):
+                name = row["Kernel_Name"]
+                if not any(x in name for x in STEP_KERNELS):
+                    continue
+                if "k_real_pass" in name and name.split(",")[-1].strip().startswith("false"):
+                    continue
+                agg[name][row["Counter_Name"]] += float(row["Counter_Value"])
+                disp[(name, k)].add(row["Dispatch_Id"])
+    rows = []
+    for name in sorted(agg, key=lambda n: -len(disp[(n, 1)])):
+        c = agg[name]
+        n1, n2 = len(disp[(name, 1)]), len(disp[(name, 2)]) or 1
+        if n1 < 8:
+            continue
+        role = name.split("<")[0].replace("void spfc::", "")
+        tmpl = [x.strip() for x in name.split("<")[1].split(">")[0].split(",")]
+        if role == "k_pass":
+            role += " (y, " + ("inverse" if tmpl[3] == "1" else "forward") + ")"
+        rows.append(f"| {label} | `{role}` | {tmpl[2]} | {c['SQ_WAVES'] / n2:.0f} | "
+                    f"{c['SQ_WAVE_CYCLES'] / n1 / 1e6:.2f}M | {c['SQ_WAIT_ANY'] / n1 / 1e6:.2f}M | "
+                    f"{c['SQ_WAIT_INST_LDS'] / n1 / 1e6:.2f}M | {c['SQ_INSTS_VALU'] / n2 / 1e6:.2f}M | "
+                    f"{c['SQ_INSTS_LDS'] / n2 / 1e6:.3f}M | {c['SQ_LDS_BANK_CONFLICT'] / n2 / 1e6:.3f}M |")
+    return rows
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd")
@@ -125,9 +162,15 @@ if __name__ == "__main__":
     s2.add_argument("dim", type=int)
     s2.add_argument("outdir")
     s2.add_argument("--command", default="")
+    s3 = sub.add_parser("counters")
+    s3.add_argument("c1")
+    s3.add_argument("c2")
+    s3.add_argument("label")
     a = ap.parse_args()
     if a.cmd == "stats":
         stats(a.src, a.out, a.command)
+    elif a.cmd == "counters":
+        print("\n".join(counters(a.c1, a.c2, a.label)))
     elif a.cmd == "traffic":
         for d in traffic(a.fetch, a.write, a.cfetch, a.cwrite, a.copy_bytes, a.workload, a.F, a.dim, a.outdir,
                          a.command):
