@@ -1,19 +1,23 @@
 """Benchmark of the SAV-BDF2 time stepper for the square phase field crystal equation.
 
-Workload (default): the large single 2-D run, 1024 x 1024 points, L = 128 pi,
-epsilon = 0.25, c4 = 1, phi0 = -0.2 + 0.05 U(-1,1) (SplitMix64 seed 2), dt = 0.01,
-FP64, first step first-order SAV then BDF2.  One "step" is one full SAV-BDF2
+Workload (default): the 3-D run, 256^3 points, L = 32 pi per side, epsilon = 0.25,
+c4 = 1, phi0 = -0.25 + 0.05 U(-1,1) (SplitMix64 seed 3), dt = 0.005, FP32 fields,
+transforms and pointwise work with FP64 reductions and SAV scalar, first step
+first-order SAV then BDF2.  Its working set (about 0.5 GB) is larger than the
+Infinity Cache, so the kernel rates are HBM rates.  One "step" is one full SAV-BDF2
 step (all transforms, the pointwise flux, the reductions, the SAV scalar and both
 Fourier solves).  Warm-up steps continue the same run; the launch plan (values per
 thread and threads per workgroup of each step kernel) is then tuned on the run
 itself (--tune trial steps, state kept); then K steps are timed with HIP events on
-the solver's stream, inputs resident in HBM.
+the solver's stream, inputs resident in HBM.  Other workloads: --workload.
 
 Prints one JSON line: grid-point-steps/s, the roofline of the dominant kernel
 (algorithmic bytes / its average launch duration, from HIP events around
 back-to-back launches of each kernel of a steady step on the solver stream,
-against 8 TB/s and against a device copy measured on the same box) and the CPU oracle
-timed on a bounded sample of the same workload.
+against 8 TB/s and against a device copy measured on the same box), the error of
+a fresh run under the tuned plan against the stored FP64 oracle trajectory of the
+same workload (tests/golden), and the CPU oracle timed on a bounded sample of the
+same workload, on one thread and on all host cores.
 """
 
 from __future__ import annotations
@@ -87,40 +91,125 @@ def load_traffic(workload: str, kernel: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(workload: str, steps: int):
-    """The oracle, as it is, on the first `steps` steps of the same run (host cores).  Grids
-    above 2^20 points are sampled on a smaller grid of the same spacing and parameters
-    (every axis halved, L with it, same input recipe): one oracle step of 256^3 takes
-    minutes, and the rate is per grid point."""
+def _cpu_sample(workload: str):
+    """The grid of the CPU sample: the workload's own, or for grids above 2^20 points a
+    smaller grid of the same spacing and parameters (every axis halved, L with it, same
+    input recipe): one oracle step of 256^3 takes minutes, and the rate is per grid point."""
     import numpy as np
-    from oracle import spfc_oracle as O
-    from paper_2012_15133_amd.inputs import noise_ic
     n, L, eps, mean, seed, dt, _ = WORKLOADS[workload]
     ns, Ls = tuple(n), tuple(L)
     while int(np.prod(ns)) > 1 << 20:
         ns, Ls = tuple(v // 2 for v in ns), tuple(v / 2 for v in Ls)
+    return ns, Ls, eps, mean, seed, dt
+
+
+def _oracle_seconds(workload: str, steps: int) -> float:
+    """Wall seconds of `steps` oracle steps of the workload's CPU sample on one thread."""
+    from oracle import spfc_oracle as O
+    from paper_2012_15133_amd.inputs import noise_ic
+    from threadpoolctl import threadpool_limits
+    ns, Ls, eps, mean, seed, dt = _cpu_sample(workload)
     g = O.Grid(ns, Ls)
     phi0 = noise_ic(g.shape, mean, seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.run(g, O.Params(eps), phi0, dt, steps, energies=False)
+        return time.perf_counter() - t0
+
+
+def host_cores() -> int:
+    """CPUs this process may run on, at most 16 (a one-GPU machine's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(workload: str, steps: int):
+    """The oracle, as it is, on the first `steps` steps of the same run: once on one thread
+    (the oracle is one sequential numpy run), and as one independent copy of the same
+    sample per host core at once (the rate the host's cores give over an ensemble of such
+    runs).  Must run before the process touches the GPU (the copies are forked)."""
+    import multiprocessing as mp
+    import numpy as np
+    ns, _, _, _, _, _ = _cpu_sample(workload)
     grid = "x".join(str(v) for v in ns)
     print(f"cpu baseline: {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
-    from threadpoolctl import threadpool_limits
-
-    def timed(k):
-        with threadpool_limits(limits=1):   # the single thread `cores` reports, whatever the host has
-            t0 = time.perf_counter()
-            O.run(g, O.Params(eps), phi0, dt, k, energies=False)
-            return time.perf_counter() - t0
-
-    sec = timed(steps)
+    sec = _oracle_seconds(workload, steps)
     if sec < 8.0:   # too short a sample on a fast host: about 15 s of steps instead
         steps = min(int(steps * 15.0 / max(sec, 1e-3)), 50 * steps)
         print(f"cpu baseline: {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
-        sec = timed(steps)
+        sec = _oracle_seconds(workload, steps)
     npts = int(np.prod(ns))
-    where = "" if ns == tuple(n) else f" on a {grid} grid of the same spacing and parameters"
-    return {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps (first-order start + BDF2) of {workload}{where} from the same seeded "
-                      f"input recipe, {sec:.1f} s wall, numpy single thread"}
+    where = "" if ns == tuple(WORKLOADS[workload][0]) else f" on a {grid} grid of the same spacing and parameters"
+    out = {"value": npts * steps / sec, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} steps (first-order start + BDF2) of {workload}{where} from the same seeded "
+                     f"input recipe, {sec:.1f} s wall, numpy single thread"}
+    cores = host_cores()
+    if cores > 1:
+        print(f"cpu baseline: {cores} copies of {steps} oracle steps on {grid}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(cores) as pool:
+            pool.starmap(_oracle_seconds, [(workload, steps)] * cores)
+        wall = time.perf_counter() - t0
+        out["all_cores"] = {"value": cores * npts * steps / wall, "unit": "grid-point-steps/s", "cores": cores,
+                            "sample": f"{cores} independent copies of the same sample at once (one per core), "
+                                      f"{wall:.1f} s wall"}
+    return out
+
+
+GOLDEN = {
+    # workload: stored FP64 oracle trajectory of the same run (tests/golden/make_golden.py)
+    "spfc2d_1024_fp64": "spfc2d_1024_seed2.npz",
+    "spfc2d_1024_fp32": "spfc2d_1024_seed2.npz",
+    "spfc3d_256_fp32": "spfc3d_256_seed3.npz",
+}
+
+
+def plan_env(plan) -> str:
+    return ",".join(f"{k}={e}/{t}" for k, (e, t) in plan.items())
+
+
+def accuracy_vs_oracle(workload: str, plan):
+    """A fresh run of the workload under the launch plan the timed steps used, against the
+    stored FP64 oracle trajectory: phi on the stored sub-lattice at each stored step, the
+    modified energy, r and the mean at every step.  Flags as in the error report: relative
+    L-inf above 1e-3 or modified energy above 1e-5 (FP32), 1e-9 / 1e-11 (FP64)."""
+    import numpy as np
+    from paper_2012_15133_amd import Solver
+    from paper_2012_15133_amd.inputs import noise_ic
+    name = GOLDEN.get(workload)
+    path = os.path.join(ROOT, "tests", "golden", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    n, L, eps, mean, seed, dt, prec = WORKLOADS[workload]
+    if tuple(meta["n"]) != tuple(n) or meta["seed"] != seed or meta["dt"] != dt:
+        return None
+    if plan:
+        os.environ["SPFC_PLAN"] = plan_env(plan)
+    steps = int(meta["steps"])
+    s = Solver(n, L, noise_ic(tuple(reversed(n)), mean, seed), eps, precision=prec, history=steps + 1)
+    sl = tuple(slice(None, None, meta["stride"]) for _ in n)
+    linf, done = 0.0, 0
+    for k in (int(v) for v in d["steps_kept"]):
+        s.step(dt, k - done)
+        done = k
+        ref = d[f"phi_{k}"]
+        linf = max(linf, float(np.max(np.abs(s.phi().cpu().numpy()[sl] - ref)) / np.max(np.abs(ref))))
+    hist = s.history(0, steps + 1)
+    used = s.plan()
+    s.close()
+    os.environ.pop("SPFC_PLAN", None)
+    e_rel = float(np.max(np.abs(np.array([h["energy"] for h in hist]) - d["energy"]) / d["energy"]))
+    r_rel = float(np.max(np.abs(np.array([h["r"] for h in hist]) - d["r"]) / d["r"]))
+    m_abs = float(np.max(np.abs(np.array([h["mean"] for h in hist]) - d["mean"])))
+    lim = (1e-3, 1e-5) if prec == "fp32" else (1e-9, 1e-11)
+    return {"vs": f"FP64 oracle trajectory tests/golden/{name}", "steps": steps, "plan": used,
+            "rel_linf": linf, "energy_rel_max": e_rel, "r_rel_max": r_rel, "mean_abs_max": m_abs,
+            "flagged": bool(linf > lim[0] or e_rel > lim[1])}
 
 
 ENSEMBLES = {
@@ -317,17 +406,18 @@ def run_surrogate(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="spfc2d_1024_fp64", choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(SURROGATES))
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="spfc3d_256_fp32", choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(SURROGATES))
     ap.add_argument("--no-seq", action="store_true", help="ensembles: skip the one-after-another comparison")
     ap.add_argument("--tune", type=int, default=10,
                     help="tune the launch plan (each size class of an ensemble) with this many trial steps "
                          "before the timed steps (0: the built-in plan)")
-    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--reps", type=int, default=20, help="back-to-back launches per kernel for kernel durations")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the run against the stored oracle trajectory")
     ap.add_argument("--graph", type=int, default=0, help="1: replay the steady steps from a captured HIP graph")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes 5 times (counter calibration)")
@@ -355,6 +445,9 @@ def main():
     if args.workload in SURROGATES:
         run_surrogate(args)
         return
+
+    # the CPU baseline first: its copies are forked, which must happen before any GPU use
+    cpu = None if args.no_cpu else cpu_baseline(args.workload, args.cpu_steps)
 
     import numpy as np
     import torch
@@ -424,8 +517,12 @@ def main():
         "kernels": per_kernel,
         "sticky_flags": flags,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+    if not args.no_accuracy:
+        acc = accuracy_vs_oracle(args.workload, plan)
+        if acc is not None:
+            out["accuracy"] = acc
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -33,6 +33,7 @@ activations v_l and the operands of the complex mixing (V and W).
 
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass
 
@@ -92,6 +93,7 @@ def mode_indices(s: FnoShape):
     return kx, ky
 
 
+@functools.lru_cache(maxsize=4)
 def _phase(s: FnoShape, sign: float):
     """exp(sign 2 pi i (kx x + ky y) / N) as a [modes, N(y), N(x)] complex tensor."""
     kx, ky = mode_indices(s)

@@ -28,3 +28,21 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+# Error reports of the GPU path against the oracle (L-inf, energy): collected by the tests
+# that call `error_report`, printed as one section at the end of the run whether they pass.
+_REPORTS = []
+
+
+def error_report(name: str, **metrics):
+    _REPORTS.append((name, metrics))
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    if not _REPORTS:
+        return
+    terminalreporter.section("GPU vs oracle error report")
+    for name, m in _REPORTS:
+        terminalreporter.write_line(name + ": " + ", ".join(
+            f"{k} {v:.3e}" if isinstance(v, float) else f"{k} {v}" for k, v in m.items()))

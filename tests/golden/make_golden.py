@@ -1,0 +1,87 @@
+"""Write the oracle trajectories that the GPU tests compare against at full size.
+
+Calls only the CPU oracle (oracle/spfc_oracle.py) and the seeded input generator
+(paper_2012_15133_amd/inputs.py, random numbers only).  Nothing here reads or runs
+the GPU path.
+
+  python tests/golden/make_golden.py --which c2   # 1024^2, 2000 steps (about 40 min, one core)
+  python tests/golden/make_golden.py --which c3   # 256^3, 3 steps (several minutes)
+
+Each file is an .npz holding, for the run it names:
+  meta          JSON text: grid, box, epsilon, dt, steps, seed, mean, start-up, sample stride
+  energy, mean, r           per step n = 0..steps: modified energy of Theorem 3.1
+                            (eq. discrete energy), mean of phi^n, r^n
+  xi, E1, p1                per step (0 at n = 0): the step that produced phi^n
+  steps_kept                the step indices whose phi^n is sampled
+  phi_<k>                   phi^k on the sub-lattice taking every `stride`-th point per axis
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import spfc_oracle as O  # noqa: E402
+from paper_2012_15133_amd.inputs import noise_ic  # noqa: E402
+
+# The two large workloads: the 2-D single run (1024^2, side 128 pi) and the 3-D run
+# (256^3, side 32 pi), both at epsilon 0.25 with the noise initial data of Section 5.2's shape.
+RUNS = {
+    "c2": dict(file="spfc2d_1024_seed2.npz", n=(1024, 1024), L=(128 * math.pi,) * 2, epsilon=0.25, dt=0.01,
+               steps=2000, seed=2, mean=-0.2, startup="sav1", stride=8, keep=(1, 3, 200, 1000, 2000)),
+    "c3": dict(file="spfc3d_256_seed3.npz", n=(256, 256, 256), L=(32 * math.pi,) * 3, epsilon=0.25, dt=0.005,
+               steps=3, seed=3, mean=-0.25, startup="sav1", stride=8, keep=(1, 2, 3)),
+}
+
+
+def sample(phi: np.ndarray, stride: int) -> np.ndarray:
+    sl = tuple(slice(None, None, stride) for _ in range(phi.ndim))
+    return np.ascontiguousarray(phi[sl])
+
+
+def make(which: str) -> str:
+    spec = RUNS[which]
+    g = O.Grid(spec["n"], spec["L"])
+    prm = O.Params(spec["epsilon"])
+    phi0 = noise_ic(g.shape, spec["mean"], spec["seed"])
+    t0 = time.time()
+    ref = O.run(g, prm, phi0, spec["dt"], spec["steps"], startup=spec["startup"], keep=set(spec["keep"]))
+    wall = time.time() - t0
+    recs = ref["records"]
+    out = {
+        "energy": np.array([r["energy"] for r in recs]),
+        "mean": np.array([r["mean"] for r in recs]),
+        "r": np.array([r["r"] for r in recs]),
+        "xi": np.array([r.get("xi", 0.0) for r in recs]),
+        "E1": np.array([r.get("E1", 0.0) for r in recs]),
+        "p1": np.array([r.get("p1", 0.0) for r in recs]),
+        "steps_kept": np.array(sorted(spec["keep"]), dtype=np.int64),
+    }
+    for k in spec["keep"]:
+        out[f"phi_{k}"] = sample(ref["kept"][k], spec["stride"])
+    meta = {k: v for k, v in spec.items() if k != "file"}
+    meta["generator"] = "tests/golden/make_golden.py (oracle/spfc_oracle.py, FP64)"
+    meta["oracle_wall_s"] = round(wall, 1)
+    out["meta"] = np.array(json.dumps(meta))
+    path = os.path.join(HERE, spec["file"])
+    np.savez_compressed(path, **out)
+    return path
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--which", choices=sorted(RUNS) + ["all"], default="all")
+    a = ap.parse_args()
+    for w in (sorted(RUNS) if a.which == "all" else [a.which]):
+        print(w, "->", make(w), flush=True)

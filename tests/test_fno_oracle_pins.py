@@ -54,10 +54,29 @@ def test_synthesis_inverts_analysis_on_band_limited_fields():
     assert np.max(np.abs(back - v)) <= 1e-14
 
 
-def test_gelu_closed_form():
-    z = torch.tensor([-3.0, -1.0, -0.25, 0.0, 0.5, 2.0], dtype=torch.float64)
-    ref = [x * 0.5 * (1 + math.erf(x / math.sqrt(2))) for x in z.tolist()]
-    assert np.allclose(F.gelu(z).numpy(), ref, rtol=0, atol=1e-16)
+# Standard normal distribution function at a few points, from printed tables of Phi
+# (e.g. Abramowitz and Stegun, Table 26.1): gelu(z) = z Phi(z).
+PHI_TABLE = [(-3.0, 0.0013498980316301), (-1.0, 0.15865525393145705), (-0.5, 0.30853753872598688),
+             (0.0, 0.5), (0.5, 0.69146246127401312), (1.0, 0.84134474606854295),
+             (1.96, 0.97500210485177952), (2.0, 0.97724986805182079)]
+
+
+def test_gelu_against_normal_table_and_independent_routines():
+    """The oracle's gelu against z Phi(z) with Phi taken from a table, from scipy's ndtr
+    (Cephes, an implementation independent of torch.erf) and torch's own exact gelu."""
+    from scipy.special import ndtr
+    z = torch.tensor([t[0] for t in PHI_TABLE], dtype=torch.float64)
+    ref = torch.tensor([t[0] * t[1] for t in PHI_TABLE], dtype=torch.float64)
+    assert torch.max(torch.abs(F.gelu(z) - ref)) <= 1e-15
+    w = torch.linspace(-8.0, 8.0, 4001, dtype=torch.float64)
+    assert torch.max(torch.abs(F.gelu(w) - w * torch.from_numpy(ndtr(w.numpy())))) <= 4e-16 * 8
+    assert torch.max(torch.abs(F.gelu(w) - torch.nn.functional.gelu(w, approximate="none"))) <= 4e-16 * 8
+    # limits: gelu(z) -> z for large z, -> 0 for very negative z; gelu'(0) = 1/2
+    assert abs(float(F.gelu(torch.tensor(40.0, dtype=torch.float64))) - 40.0) == 0.0
+    assert abs(float(F.gelu(torch.tensor(-40.0, dtype=torch.float64)))) <= 1e-300
+    h = 1e-6
+    d0 = (F.gelu(torch.tensor(h, dtype=torch.float64)) - F.gelu(torch.tensor(-h, dtype=torch.float64))) / (2 * h)
+    assert abs(float(d0) - 0.5) <= 1e-10
 
 
 def _batch(s, b=2, seed=5):

@@ -1,0 +1,205 @@
+"""The kernel instances and launch plans that the benchmark times, against the FP64 oracle.
+
+* Thin 3-D grids with one 256-point axis each, (256, 16, 16), (16, 256, 16) and
+  (16, 16, 256) with L = n pi / 8 (the spacing of the 256^3 run): every 256-point
+  instance of the 256^3 step (the real-space pass along x, the middle passes along y,
+  the spectral passes along z) meets the oracle, under the built-in plan, the plan
+  the tuner picks at 256^3, every values-per-thread x workgroup-size choice the tuner
+  can make for each kernel role, and with each step closed in a separate kernel
+  (as 256^3 does).  Element by element, FP64 to the trajectory bounds (1e-11 on phi,
+  1e-12 on the modified energy at every step), FP32 to the report bounds.
+* 1024^2 (side 128 pi, seed 2, dt 0.01) and 256^3 (side 32 pi, seed 3, dt 0.005)
+  against the oracle trajectories stored by tests/golden/make_golden.py: per-step
+  modified energy, mean and r, and phi^k on a sub-lattice, under the built-in plan and
+  the plan the benchmark's tuner picks.  The 1024^2 run covers the full 2000 steps.
+
+Tolerances.  FP64: the bounds of the parity trajectories while t is short; over the
+2000 steps of 1024^2 (t = 20) round-off differences can grow by up to exp(0.264 t) ~ 200
+(0.264 the largest linear growth rate at epsilon = 0.25), so there phi is held to 1e-9
+relative and the energy to 1e-11.  FP32 fields: the paper fixes no FP32 accuracy (parity
+unpinned); the bounds are the flags of the error report, relative L-inf 1e-3 and
+modified energy 1e-5, and every run prints its errors in the report section.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from conftest import error_report
+from oracle import spfc_oracle as O
+from paper_2012_15133_amd.inputs import noise_ic
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# The plans the benchmark's tuner has picked (values per thread / threads per workgroup).
+PLAN_C3 = "inv=8/256,mid=8/256,real=4/256,fwd=8/256"
+PLAN_C2 = "inv=4/256,real=4/256,fwd=8/128"
+
+FP64_PHI, FP64_E = 1e-11, 1e-12
+FP32_PHI, FP32_E = 1e-3, 1e-5
+
+
+def _solver(n, L, phi0, eps, **kw):
+    from paper_2012_15133_amd import Solver
+    return Solver(n, L, phi0, eps, **kw)
+
+
+def _with_plan(monkeypatch, plan):
+    if plan:
+        monkeypatch.setenv("SPFC_PLAN", plan)
+    else:
+        monkeypatch.delenv("SPFC_PLAN", raising=False)
+
+
+# ----------------------------------------------------------------- thin grids, one 256-point axis
+
+THIN = [(256, 16, 16), (16, 256, 16), (16, 16, 256)]
+THIN_STEPS, THIN_DT = 20, 0.005
+
+
+def _role_plans():
+    """Every values-per-thread x workgroup-size choice of the tuner, one role at a time."""
+    out = []
+    for role in ("inv", "mid", "real", "fwd"):
+        for e in (4, 8, 16):
+            for t in (128, 256):
+                out.append(f"{role}={e}/{t}")
+    return out
+
+
+_ORACLE = {}
+
+
+def _thin_reference(n):
+    if n not in _ORACLE:
+        L = tuple(v * math.pi / 8 for v in n)
+        g = O.Grid(n, L)
+        phi0 = noise_ic(g.shape, -0.25, 3)
+        _ORACLE[n] = (L, phi0, O.run(g, O.Params(0.25), phi0, THIN_DT, THIN_STEPS))
+    return _ORACLE[n]
+
+
+def _thin_errors(n, precision):
+    L, phi0, ref = _thin_reference(n)
+    s = _solver(n, L, phi0, 0.25, precision=precision, history=THIN_STEPS + 1)
+    s.step(THIN_DT, THIN_STEPS)
+    hist = s.history(0, THIN_STEPS + 1)
+    phi = s.phi().cpu().numpy()
+    flags = s.status()
+    plan = s.plan()
+    s.close()
+    linf = float(np.max(np.abs(phi - ref["phi"])) / np.max(np.abs(ref["phi"])))
+    e_err = max(abs(h["energy"] - r["energy"]) / r["energy"] for h, r in zip(hist, ref["records"]))
+    r_err = max(abs(h["r"] - r["r"]) / r["r"] for h, r in zip(hist, ref["records"]))
+    m_err = max(abs(h["mean"] - r["mean"]) for h, r in zip(hist, ref["records"]))
+    return linf, e_err, r_err, m_err, flags, plan
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", THIN, ids=["x256", "y256", "z256"])
+def test_thin_3d_256_axis_every_plan(monkeypatch, n, precision):
+    tol_phi, tol_e = (FP64_PHI, FP64_E) if precision == "fp64" else (FP32_PHI, FP32_E)
+    plans = ["", "finsep", PLAN_C3, PLAN_C3 + ",finsep"] + _role_plans()
+    worst = [0.0, 0.0]
+    for plan in plans:
+        _with_plan(monkeypatch, plan)
+        linf, e_err, r_err, m_err, flags, used = _thin_errors(n, precision)
+        case = f"{n} {precision} plan '{plan}' -> {used}"
+        assert linf <= tol_phi, (case, linf)
+        assert e_err <= tol_e and r_err <= tol_e, (case, e_err, r_err)
+        assert m_err <= (5e-14 if precision == "fp64" else 1e-6), (case, m_err)
+        assert flags & (~8 if precision == "fp32" else ~0) == 0, (case, flags)
+        worst = [max(worst[0], linf), max(worst[1], e_err)]
+    error_report(f"thin {n} {precision}, {THIN_STEPS} steps, {len(plans)} plans (worst)",
+                 rel_linf=worst[0], energy_rel=worst[1])
+
+
+# ----------------------------------------------------------------- full size against stored oracle runs
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"oracle trajectory {name} not written (tests/golden/make_golden.py)")
+    d = np.load(path, allow_pickle=False)
+    return json.loads(str(d["meta"])), d
+
+
+def _against_golden(monkeypatch, name, precision, plan, steps=None):
+    meta, d = _golden(name)
+    _with_plan(monkeypatch, plan)
+    n, L = tuple(meta["n"]), tuple(meta["L"])
+    steps = meta["steps"] if steps is None else steps
+    stride = meta["stride"]
+    kept = [int(k) for k in d["steps_kept"] if k <= steps]
+    phi0 = noise_ic(tuple(reversed(n)), meta["mean"], meta["seed"])
+    s = _solver(n, L, phi0, meta["epsilon"], precision=precision, history=steps + 1)
+    sl = tuple(slice(None, None, stride) for _ in n)
+    phi_err = {}
+    done = 0
+    for k in kept:
+        s.step(meta["dt"], k - done)
+        done = k
+        got = s.phi().cpu().numpy()[sl]
+        ref = d[f"phi_{k}"]
+        phi_err[k] = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    if done < steps:
+        s.step(meta["dt"], steps - done)
+    hist = s.history(0, steps + 1)
+    flags = s.status()
+    used = s.plan()
+    s.close()
+    e = np.array([h["energy"] for h in hist])
+    e_rel = np.abs(e - d["energy"][:steps + 1]) / d["energy"][:steps + 1]
+    r_rel = np.abs(np.array([h["r"] for h in hist]) - d["r"][:steps + 1]) / d["r"][:steps + 1]
+    m_abs = np.abs(np.array([h["mean"] for h in hist]) - d["mean"][:steps + 1])
+    return phi_err, e_rel, r_rel, m_abs, flags, used
+
+
+@pytest.mark.parametrize("plan", ["", PLAN_C2], ids=["builtin", "tuned"])
+def test_c2_2000_steps_fp64_against_oracle(monkeypatch, plan):
+    phi_err, e_rel, r_rel, m_abs, flags, used = _against_golden(monkeypatch, "spfc2d_1024_seed2.npz", "fp64", plan)
+    error_report(f"1024^2 fp64 plan {used}, 2000 steps",
+                 rel_linf_step3=phi_err[3], rel_linf_step2000=phi_err[2000],
+                 energy_rel_max=float(e_rel.max()), mean_abs_max=float(m_abs.max()))
+    assert phi_err[1] <= 1e-12 and phi_err[3] <= 1e-12, phi_err
+    assert max(phi_err.values()) <= 1e-9, phi_err
+    assert e_rel[:4].max() <= 1e-12 and e_rel.max() <= 1e-11
+    assert r_rel.max() <= 1e-11
+    assert m_abs.max() <= 1e-13
+    assert flags == 0
+
+
+@pytest.mark.parametrize("plan", ["", PLAN_C2], ids=["builtin", "tuned"])
+def test_c2_2000_steps_fp32_error_report(monkeypatch, plan):
+    phi_err, e_rel, r_rel, m_abs, flags, used = _against_golden(monkeypatch, "spfc2d_1024_seed2.npz", "fp32", plan)
+    error_report(f"1024^2 fp32 plan {used}, 2000 steps",
+                 rel_linf_step3=phi_err[3], rel_linf_step2000=phi_err[2000],
+                 energy_rel_max=float(e_rel.max()), mean_abs_max=float(m_abs.max()))
+    assert max(phi_err.values()) <= FP32_PHI, phi_err
+    assert e_rel.max() <= FP32_E
+    assert m_abs.max() <= 1e-6
+    assert flags & ~8 == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("plan", ["", PLAN_C3], ids=["builtin", "tuned"])
+def test_c3_first_steps_against_oracle(monkeypatch, plan, precision):
+    phi_err, e_rel, r_rel, m_abs, flags, used = _against_golden(monkeypatch, "spfc3d_256_seed3.npz", precision, plan)
+    error_report(f"256^3 {precision} plan {used}, 3 steps",
+                 rel_linf=max(phi_err.values()), energy_rel_max=float(e_rel.max()),
+                 mean_abs_max=float(m_abs.max()))
+    if precision == "fp64":
+        assert max(phi_err.values()) <= FP64_PHI, phi_err
+        assert e_rel.max() <= FP64_E and r_rel.max() <= FP64_E
+        assert m_abs.max() <= 2e-14
+        assert flags == 0
+    else:
+        assert max(phi_err.values()) <= FP32_PHI, phi_err
+        assert e_rel.max() <= FP32_E
+        assert m_abs.max() <= 1e-6
+        assert flags & ~8 == 0

@@ -143,8 +143,9 @@ def test_3d_trajectory(n):
 
 
 def test_c2_full_size_sampled_fp64():
-    """1024^2, L = 128 pi, dt 0.01 (the large 2-D run) in the launch shape the benchmark uses:
-    the first 3 steps against the oracle, element by element."""
+    """1024^2, L = 128 pi, dt 0.01 (the large 2-D run) under the built-in launch plan: the first
+    3 steps against the oracle, element by element.  The tuned plan that the benchmark times,
+    and the full 2000 steps, are compared in test_gpu_full_size.py."""
     n = (1024, 1024)
     L = (128 * math.pi,) * 2
     s, hist, ref = _compare_run(n, L, 0.25, 0.01, 3, 2, -0.2, tol_phi=1e-12, tol_e=1e-12)

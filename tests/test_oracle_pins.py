@@ -142,6 +142,28 @@ def test_N_single_mode_closed_form():
     assert np.max(np.abs(O.N_nl(g, O.Params(0.25), phi) - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sav_energy_two_mode_closed_form(dim):
+    """The SAV energy of Section 5.2, a/2 ||phi||^2 + 1/2 ||Delta_N phi||^2 + r^2, on
+    phi = b0 + A cos(k x) + B sin(l y) (k, l below the Nyquist mode, k != 1 != l):
+    ||phi||^2 = |Omega| (b0^2 + A^2/2 + B^2/2) and ||Delta phi||^2 = |Omega| (k^4 A^2 + l^4 B^2)/2
+    by orthogonality, so the value is |Omega| [a (b0^2 + (A^2 + B^2)/2) + (k^4 A^2 + l^4 B^2)/2] / 2
+    + r^2.  A wrong weight on either norm, a Laplacian taken as a gradient, r in place of
+    r^2 or a dropped mean all change it."""
+    n = (32, 16) if dim == 2 else (16, 8, 8)
+    L = (6.0, 2.5) if dim == 2 else (6.0, 2.5, 3.0)
+    g = O.Grid(n, L)
+    prm = O.Params(0.3)
+    b0, A, B, r = -0.3, 0.7, 0.45, 1.9
+    k, l = 2 * np.pi * 3 / L[0], 2 * np.pi * 2 / L[1]
+    axes = [np.arange(nj) * hj for nj, hj in zip(g.n, g.h)]
+    x = axes[0].reshape((1,) * (dim - 1) + (-1,))
+    y = axes[1].reshape((1,) * (dim - 2) + (-1, 1))
+    phi = (b0 + A * np.cos(k * x) + B * np.sin(l * y)) * np.ones(g.shape)
+    ref = 0.5 * g.volume * (prm.a * (b0 ** 2 + 0.5 * (A * A + B * B)) + 0.5 * (k ** 4 * A * A + l ** 4 * B * B)) + r * r
+    assert abs(O.sav_energy(g, prm, phi, r) - ref) <= 1e-13 * ref
+
+
 def _sympy_fields(dim, L, expr_fn, c4):
     xs = sp.symbols("x y z")[:dim]
     phi = expr_fn(*xs)
