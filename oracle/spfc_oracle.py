@@ -160,10 +160,16 @@ class Params:
 
     stab = A >= 0 selects the stabilized scheme of the closing remarks of Section 5:
     the regularization -A dt Delta_N (phi^{n+1} - phi^n) is added to the chemical
-    potential of the step (A = 0: the scheme eq. scheme-SAV-1 itself)."""
+    potential of the step (A = 0: the scheme eq. scheme-SAV-1 itself).
+
+    beta >= 0 adds (beta/4) phi^4 to the energy density, the quartic term of the
+    standard PFC energy (Section 1, eq. energy-PFC), beside the 4-Laplacian term of
+    the SPFC energy (paper: 0).  It is convex and nonnegative, so it joins the
+    nonlinear part E_1 (which keeps E_1 >= |Omega|) and adds beta phi^3 to N."""
     epsilon: float
     c4: float = 1.0
     stab: float = 0.0
+    beta: float = 0.0
 
     @property
     def a(self) -> float:
@@ -216,26 +222,36 @@ def _grad_sq(g: Grid, phi: np.ndarray):
 
 
 def E1(g: Grid, prm: Params, phi: np.ndarray) -> float:
-    """E_{1,N}(phi) = (c4/4)||nabla_N phi||_4^4 - ||nabla_N phi||_2^2 + (1 + 1/c4)|Omega|.
+    """E_{1,N}(phi) = (c4/4)||nabla_N phi||_4^4 - ||nabla_N phi||_2^2 + (beta/4)||phi||_4^4
+    + (1 + 1/c4)|Omega|.
 
-    Section 2.2 (definition after eq. scheme-SAV-1); c4 = 1 gives the paper's form.
+    Section 2.2 (definition after eq. scheme-SAV-1); c4 = 1, beta = 0 gives the paper's form.
     """
     _, s = _grad_sq(g, phi)
-    return g.cell * float(np.sum(0.25 * prm.c4 * s * s - s)) + prm.e1_constant(g.volume)
+    dens = 0.25 * prm.c4 * s * s - s
+    if prm.beta != 0.0:
+        dens = dens + 0.25 * prm.beta * phi ** 4
+    return g.cell * float(np.sum(dens)) + prm.e1_constant(g.volume)
 
 
 def N_nl(g: Grid, prm: Params, phi: np.ndarray) -> np.ndarray:
-    """N_N(phi) = -c4 nabla_N.(|nabla_N phi|^2 nabla_N phi) + 2 Delta_N phi  (Section 2.2, after eq. scheme-SAV-1)."""
+    """N_N(phi) = -c4 nabla_N.(|nabla_N phi|^2 nabla_N phi) + 2 Delta_N phi + beta phi^3
+    (Section 2.2, after eq. scheme-SAV-1; the variational derivative of E_1)."""
     gr, s = _grad_sq(g, phi)
-    return -prm.c4 * div(g, [s * d for d in gr]) + 2.0 * lap(g, phi)
+    out = -prm.c4 * div(g, [s * d for d in gr]) + 2.0 * lap(g, phi)
+    if prm.beta != 0.0:
+        out = out + prm.beta * phi ** 3
+    return out
 
 
 def E_N(g: Grid, prm: Params, phi: np.ndarray) -> float:
     """Discrete SPFC energy (eq. energy-discrete-spectral):
-    (c4/4)||nabla phi||_4^4 + a/2 ||phi||^2 - ||nabla phi||^2 + 1/2 ||Delta_N phi||^2."""
+    (c4/4)||nabla phi||_4^4 + a/2 ||phi||^2 - ||nabla phi||^2 + 1/2 ||Delta_N phi||^2
+    (+ (beta/4)||phi||_4^4)."""
     _, s = _grad_sq(g, phi)
     lp = lap(g, phi)
-    return (g.cell * float(np.sum(0.25 * prm.c4 * s * s - s))
+    quartic = 0.25 * prm.beta * float(np.sum(phi ** 4)) if prm.beta != 0.0 else 0.0
+    return (g.cell * (float(np.sum(0.25 * prm.c4 * s * s - s)) + quartic)
             + 0.5 * prm.a * inner(g, phi, phi) + 0.5 * inner(g, lp, lp))
 
 

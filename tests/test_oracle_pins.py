@@ -452,6 +452,87 @@ def test_second_order_temporal_convergence():
         assert 1.9 <= slope <= 2.1, (slope, errs)
 
 
+# ----------------------------------------------------------------- quartic term (beta/4) phi^4 (standard PFC, Section 1)
+
+def test_beta_uniform_state():
+    """phi = b0 everywhere: every derivative vanishes, so N = beta b0^3, E_1 = |Omega| (beta b0^4 / 4
+    + 1 + 1/c4) >= |Omega|, E_N = |Omega| (beta b0^4 / 4 + a b0^2 / 2), and the state is a fixed
+    point of the scheme with r constant."""
+    g = O.Grid((16, 8), (5.0, 3.0))
+    b0, beta, c4 = -0.3, 0.7, 1.3
+    prm = O.Params(0.25, c4=c4, beta=beta)
+    phi = np.full(g.shape, b0)
+    assert np.max(np.abs(O.N_nl(g, prm, phi) - beta * b0 ** 3)) <= 1e-15
+    E1 = g.volume * (0.25 * beta * b0 ** 4 + 1.0 + 1.0 / c4)
+    assert abs(O.E1(g, prm, phi) - E1) <= 1e-14 * E1 and E1 >= g.volume
+    EN = g.volume * (0.25 * beta * b0 ** 4 + 0.5 * prm.a * b0 ** 2)
+    assert abs(O.E_N(g, prm, phi) - EN) <= 1e-14 * EN
+    out = O.run(g, prm, phi, 0.1, 6)
+    assert np.max(np.abs(out["phi"] - b0)) < 1e-15
+    for rec in out["records"]:
+        assert abs(rec["r"] - math.sqrt(E1)) < 1e-12 * math.sqrt(E1)
+
+
+def test_beta_single_mode_closed_form():
+    """phi = b0 + A cos t (t = k x, 4m < n so phi^4 is resolved): the quartic term adds
+    |Omega| beta/4 (b0^4 + 3 b0^2 A^2 + 3 A^4 / 8) to E_1 and
+    beta [b0^3 + 3 b0 A^2 / 2 + (3 b0^2 A + 3 A^3 / 4) cos t + (3 b0 A^2 / 2) cos 2t + (A^3 / 4) cos 3t]
+    to N (powers of cos t reduced to multiple angles)."""
+    L, n, m = 8 * np.pi, 64, 3
+    b0, A, beta = -0.25, 0.6, 1.7
+    g = O.Grid((n, n), (L, L))
+    k = 2 * np.pi * m / L
+    t = (k * np.arange(n) * g.h[0])[None, :] * np.ones((n, 1))
+    phi = b0 + A * np.cos(t)
+    p0, pb = O.Params(0.25), O.Params(0.25, beta=beta)
+    dE = g.volume * 0.25 * beta * (b0 ** 4 + 3 * b0 ** 2 * A ** 2 + 3 * A ** 4 / 8)
+    assert abs((O.E1(g, pb, phi) - O.E1(g, p0, phi)) - dE) <= 1e-12 * dE
+    dN = beta * (b0 ** 3 + 1.5 * b0 * A * A + (3 * b0 * b0 * A + 0.75 * A ** 3) * np.cos(t)
+                 + 1.5 * b0 * A * A * np.cos(2 * t) + 0.25 * A ** 3 * np.cos(3 * t))
+    assert np.max(np.abs((O.N_nl(g, pb, phi) - O.N_nl(g, p0, phi)) - dN)) <= 1e-13 * np.max(np.abs(dN))
+    assert abs((O.E_N(g, pb, phi) - O.E_N(g, p0, phi)) - dE) <= 1e-12 * dE
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.9])
+def test_N_is_the_variation_of_E1(beta):
+    """N_N = delta E_1 / delta phi: d/dh E_1(phi + h q) at h = 0 equals <N_N(phi), q> on fields
+    without Nyquist content (where nabla.nabla = Delta).  E_1(phi + h q) is a quartic polynomial
+    in h, so the central difference carries only an h^2 term and one Richardson step makes it
+    exact: a wrong weight between the terms of E_1 and of N fails."""
+    g = O.Grid((16, 16), (5.0, 4.0))
+    f, _, _ = _trig_poly(g, 6, np.random.default_rng(21))
+    q, _, _ = _trig_poly(g, 6, np.random.default_rng(22))
+    phi, q = 0.3 * f, 0.2 * q
+    prm = O.Params(0.25, c4=1.4, beta=beta)
+    D = lambda h: (O.E1(g, prm, phi + h * q) - O.E1(g, prm, phi - h * q)) / (2 * h)
+    h = 1e-2
+    dE = (4 * D(h / 2) - D(h)) / 3
+    ref = O.inner(g, O.N_nl(g, prm, phi), q)
+    assert abs(dE - ref) <= 1e-9 * (abs(ref) + 1e-3)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_beta_energy_identity_exact(dim):
+    """Theorem 3.1 as an identity with the quartic term in E_1 (the algebra of the proof does
+    not depend on the form of E_1), from the first-order start and then BDF2."""
+    if dim == 2:
+        g = O.Grid((32, 32), (8 * np.pi,) * 2)
+    else:
+        g = O.Grid((8, 8, 8), (4 * np.pi,) * 3)
+    prm = O.Params(0.25, beta=1.2)
+    phi0 = noise_ic(g.shape, -0.3, 31) + 0.2 * np.cos(2 * np.pi * np.arange(g.n[0]) / g.n[0] * 2)
+    dt = 0.01
+    phi_n, phi_nm1, r_n, r_nm1 = O.initial_state(g, prm, dt, phi0, "sav1")
+    phi1, r1, info, res, lhs = _identity_residual(g, prm, dt, phi_n, phi_nm1, r_n, r_nm1, O.BDF1, False)
+    assert abs(res) <= 1e-12 and lhs <= 0
+    phi_nm1, phi_n, r_nm1, r_n = phi_n, phi1, r_n, r1
+    for _ in range(5):
+        phi1, r1, info, res, lhs = _identity_residual(g, prm, dt, phi_n, phi_nm1, r_n, r_nm1, O.BDF2, True)
+        assert abs(res) <= 1e-12 and lhs <= 0
+        assert info["p1"] <= 0.0 and info["E1"] >= g.volume
+        phi_nm1, phi_n, r_nm1, r_n = phi_n, phi1, r_n, r1
+
+
 # ----------------------------------------------------------------- stabilized scheme (end of Section 5)
 
 def _stab_identity_residual(g, prm, dt, phi_n, phi_nm1, r_n, r_nm1, first_order):
