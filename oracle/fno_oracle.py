@@ -28,7 +28,9 @@ synth(anal(v)) = v for a real field band-limited to the retained modes except
 tests).  gelu(z) = z Phi(z) with the normal distribution function Phi.
 
 `bf16=True` rounds (to nearest even) where the GPU path stores bfloat16: the
-activations v_l and the operands of the complex mixing (V and W).
+activations v_l and the operands of the complex mixing (V and W), and, in the
+backward pass, the pre-activation u_l of a Fourier layer at which gelu' is taken
+(the GPU keeps u_l for the backward pass only as a bf16 copy).
 """
 
 from __future__ import annotations
@@ -129,6 +131,30 @@ def gelu(z):
     return 0.5 * z * (1.0 + torch.erf(z / math.sqrt(2.0)))
 
 
+def gelu_prime(z):
+    """d/dz [z Phi(z)] = Phi(z) + z phi(z), phi the standard normal density."""
+    return 0.5 * (1.0 + torch.erf(z / math.sqrt(2.0))) + z * torch.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+class _GeluKeptBf16(torch.autograd.Function):
+    """gelu(u) whose derivative in the backward pass is taken at u rounded to bf16: the GPU
+    keeps the pre-activation of a Fourier layer for its backward pass only as a bf16 copy."""
+
+    @staticmethod
+    def forward(ctx, u):
+        ctx.save_for_backward(round_bf16(u))
+        return gelu(u)
+
+    @staticmethod
+    def backward(ctx, g):
+        (uq,) = ctx.saved_tensors
+        return g * gelu_prime(uq)
+
+
+def _layer_gelu(u, bf16: bool):
+    return _GeluKeptBf16.apply(u) if bf16 else gelu(u)
+
+
 def init_params(s: FnoShape, seed: int = 0) -> dict:
     """Seeded initial weights (uniform, fan-in scaled); float64 tensors."""
     g = torch.Generator().manual_seed(seed)
@@ -163,7 +189,7 @@ def forward(s: FnoShape, p: dict, phi: torch.Tensor, eps: torch.Tensor, bf16: bo
         U = torch.einsum("bim,mio->bom", Vq, W)
         w = synthesis(s, U)
         u = w + torch.einsum("oi,biyx->boyx", p[f"Pw{l}"], v) + p[f"Pb{l}"][None, :, None, None]
-        v = gelu(u) if l < s.layers - 1 else u
+        v = _layer_gelu(u, bf16) if l < s.layers - 1 else u
         v = _q(v, bf16)
     hpre = torch.einsum("kc,bcyx->bkyx", p["Q1"], v) + p["q1"][None, :, None, None]
     out = torch.einsum("k,bkyx->byx", p["Q2"], gelu(hpre)) + p["q2"][0]

@@ -79,6 +79,25 @@ def test_gelu_against_normal_table_and_independent_routines():
     assert abs(float(d0) - 0.5) <= 1e-10
 
 
+def test_gelu_prime_and_the_bf16_kept_backward():
+    """gelu' against torch's own gelu backward (an implementation independent of the oracle's
+    closed form) and a central difference; the layer GELU of the bf16 network differentiates
+    at u rounded to bf16 (equal to gelu'(u) where u is a bf16 value, else at the rounded u)."""
+    z = torch.linspace(-6.0, 6.0, 2001, dtype=torch.float64, requires_grad=True)
+    torch.nn.functional.gelu(z, approximate="none").sum().backward()
+    assert torch.max(torch.abs(F.gelu_prime(z.detach()) - z.grad)) <= 1e-15
+    h = 1e-5
+    fd = (F.gelu(z.detach() + h) - F.gelu(z.detach() - h)) / (2 * h)
+    assert torch.max(torch.abs(F.gelu_prime(z.detach()) - fd)) <= 1e-9
+    u = torch.tensor([0.1234567, -1.7654321, 2.5, 0.0], dtype=torch.float64, requires_grad=True)
+    F._layer_gelu(u, True).sum().backward()
+    uq = F.round_bf16(u.detach())
+    assert torch.equal(u.grad, F.gelu_prime(uq))
+    assert u.grad[2] == F.gelu_prime(torch.tensor(2.5, dtype=torch.float64))   # 2.5 is a bf16 value
+    assert u.grad[0] != F.gelu_prime(u.detach()[0])                              # 0.1234567 is not
+    assert torch.equal(F._layer_gelu(u.detach(), True), F.gelu(u.detach()))     # forward unchanged
+
+
 def _batch(s, b=2, seed=5):
     rng = np.random.default_rng(seed)
     phi = torch.from_numpy(-0.2 + 0.05 * rng.standard_normal((b, s.n, s.n)))

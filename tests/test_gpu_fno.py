@@ -254,12 +254,14 @@ def test_gradients_n256(regime):
     ref_loss, ref = F.loss_and_grads(S256, p, phi, eps, tgt, bf16=True)
     _, ref64 = F.loss_and_grads(S256, p, phi, eps, tgt, bf16=False)
     assert abs(loss - ref_loss) <= 1e-3 * ref_loss
-    worst = 0.0
+    worst, bad = 0.0, []
     for k, r in ref.items():
         if k == "q2":
             continue
         e, sens = _rel(gg[k], r), _rel(ref64[k], r)
         print(f"  grad {k:5s} rel L2 {e:.2e}  (bf16 vs float64 oracle {sens:.2e})")
         worst = max(worst, e / sens)
-        assert e <= 0.5 * sens or (regime == "unit" and e <= 2e-2), k
+        if not (e <= 0.5 * sens or (regime == "unit" and e <= 2e-2)):
+            bad.append((k, e, sens))
     error_report(f"fno n=256 gradients ({regime})", worst_block_gap_over_bf16_gap=worst)
+    assert not bad, bad
