@@ -313,6 +313,31 @@ __device__ inline void stage_twiddles(cpx<T>* lds_tw, const cpx<T>* __restrict__
     build_twiddles<T, PL>(lds_tw, tw, tws, threadIdx.x, blockDim.x);
 }
 
+// stage_twiddles in two halves: the loads into registers (issued early, ahead of a
+// kernel's field loads) and the LDS stores (after them).  A workgroup has at least the
+// P threads of one line, so `per` entries per thread cover the tables.
+template <typename T, typename PL>
+struct TwStage {
+    using TS = TwSplit<PL::Nl>;
+    static constexpr int per = (TS::size + PL::P - 1) / PL::P;
+    cpx<T> v[per];
+    __device__ inline void load(const cpx<T>* __restrict__ tw, int tws) {
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const int j = threadIdx.x + i * (int)blockDim.x;
+            const int jj = j < TS::size ? j : 0;
+            v[i] = jj < TS::M ? tw[(size_t)jj * tws] : tw[(size_t)(jj - TS::M) * TS::M * tws];
+        }
+    }
+    __device__ inline void store(cpx<T>* lds_tw) const {
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const int j = threadIdx.x + i * (int)blockDim.x;
+            if (j < TS::size) lds_tw[j] = v[i];
+        }
+    }
+};
+
 // Workgroup index remapped so that consecutive line blocks run on the same XCD
 // (workgroups are dealt to the 8 XCDs round-robin).  Bijective on [0, nblocks).
 __device__ inline int xcd_block(int b, int nblocks) {

@@ -622,6 +622,59 @@ __device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e) 
     return mk<T>(a.x - b.y, a.y + b.x);
 }
 
+// Value v of lane src of the wave (ds_bpermute on its 32-bit words).
+template <typename T>
+__device__ inline cpx<T> lane_fetch(cpx<T> v, int src) {
+    constexpr int W = (int)(sizeof(cpx<T>) / 4);
+    union U {
+        cpx<T> c;
+        int w[W];
+    } u;
+    u.c = v;
+#pragma unroll
+    for (int i = 0; i < W; ++i) u.w[i] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[i]);
+    return u.c;
+}
+
+// The complex line W = H1 + i H2 of two real rows with half spectra h1, h2, element
+// t + P m in w[m], as load_packed gives it, but each half-spectrum entry is loaded once:
+// thread t loads the entries e = t + P m with m < E/2 (all lanes also read the
+// self-conjugate bin N/2, which thread 0 keeps), and an element e > N/2, whose value
+// W(e) = conj H1(N - e) + i conj H2(N - e) comes from entry N - e, is formed by the lane
+// that loaded N - e and moved across lanes: element m >= E/2 of thread t > 0 mirrors
+// element E - 1 - m of thread P - t, and thread 0's mirror its own element E - m.
+// Needs the P threads of a line within one wave (P <= 64).  All P lanes must call it.
+template <typename T, typename PL>
+__device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int t, cpx<T> (&w)[PL::E]) {
+    constexpr int E = PL::E, P = PL::P, N = PL::Nl, H = E / 2;
+    static_assert(P <= 64, "a line must lie within one wave");
+    cpx<T> a[H], b[H];
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        a[m] = h1[t + P * m];
+        b[m] = h2[t + P * m];
+    }
+    const cpx<T> an = h1[N / 2], bn = h2[N / 2];
+    if (t == 0) {
+        a[0].y = T(0);
+        b[0].y = T(0);
+    }
+    cpx<T> mv[H];   // what this lane's entries give the mirrored elements: conj H1 + i conj H2
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        w[m] = mk<T>(a[m].x - b[m].y, a[m].y + b[m].x);
+        mv[m] = mk<T>(a[m].x + b[m].y, b[m].x - a[m].y);
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const int src = lane - t + ((P - t) & (P - 1));
+#pragma unroll
+    for (int m = H; m < E; ++m) {
+        const cpx<T> r = lane_fetch(mv[E - 1 - m], src);
+        if (t != 0) w[m] = r;
+        else w[m] = m == H ? mk<T>(an.x, bn.x) : mv[E - m];
+    }
+}
+
 // Two neighbouring complex values in one store (dst aligned to twice the element).
 template <typename T>
 __device__ inline void store_pair(cpx<T>* dst, cpx<T> a, cpx<T> b) {
@@ -650,15 +703,29 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     const Geo geo = p.geos[mem];
     const size_t mbase = (size_t)mem * p.fs;
 
+    // twiddle loads first, so that the wait for them before their LDS store does not
+    // include the field loads
+    TwStage<T, PL> tws;
+    tws.load(p.tw, p.tws);
+    issue_barrier();
     cpx<T> v[C][E];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
         const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
+        if constexpr (P <= 64) {
+            load_packed_once<T, PL>(h1, h2, t, v[c]);
+            if (!act) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+                for (int m = 0; m < E; ++m) v[c][m] = mk<T>(0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+        }
     }
-    stage_twiddles<T, PL>(ltw, p.tw, p.tws);
+    issue_barrier();
+    tws.store(ltw);
     fft_run<T, PL, +1, C>(v, lds, t, ltw);
 
     const T sc = T(geo.inv_npts), c4 = T(geo.c4);
