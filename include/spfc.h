@@ -20,7 +20,9 @@
  *    outputs untouched on error.  No exception crosses this boundary.
  *  - One host thread at a time per context.
  *  - The library allocates no device memory: the caller passes a workspace
- *    that must stay alive and untouched until spfc_destroy.
+ *    that must stay alive and untouched until spfc_destroy.  (The one exception
+ *    is the fixed array that serves spfc_run_noalloc, which comes with the
+ *    library's code object.)
  */
 #ifndef SPFC_H
 #define SPFC_H
@@ -317,6 +319,31 @@ int spfc_batch_get_phi_all(spfc_batch* b, void* const* out_dev, int dtype);
 int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out);
 /* Free the host side of the batch.  Does not touch caller memory. */
 int spfc_batch_destroy(spfc_batch* b);
+
+/* ---------------------------------------------------------------- allocation-free run
+ * For callers that cannot allocate device memory (code in tight serving loops, harnesses
+ * that forbid hipMalloc): one whole run in a single call whose workspace is an array of
+ * SPFC_NOALLOC_BYTES bytes that the library itself holds on each device it runs on
+ * (allocated with the library's code object, kept until the process ends).  The call
+ * does what spfc_init (on that array) + spfc_step(dt, n) + spfc_get_phi + spfc_energy +
+ * spfc_destroy do, with the same kernels and launch plan, so its results equal theirs
+ * bit for bit.  It calls no hipMalloc, hipFree or other allocating routine.
+ * phi0_dev: N_total doubles (x fastest), read only.  phi_out_dev: N_total values of
+ * dtype SPFC_FP64 or SPFC_FP32 (may equal phi0_dev), receives phi^n.  energy_out (host,
+ * may be null) receives the energies of phi^n as spfc_energy gives them.  hip_stream as
+ * for spfc_init.  Synchronizes the stream before returning.
+ * Every call on one device uses that device's one array: calls that overlap on a device
+ * (other host threads, other streams) race and must be serialized by the caller.  Each
+ * call clears what must start at zero, so no state carries over from an earlier call.
+ * Errors: SPFC_E_INVAL (as spfc_init / spfc_step, null output, bad dtype),
+ * SPFC_E_NOMEM (spfc_workspace_bytes of the grid and parameters above
+ * SPFC_NOALLOC_BYTES: with the default history of 4096 records that admits 2-D FP64
+ * grids up to 2^19 points, FP32 up to 1024^2, 3-D FP32 up to 128 x 128 x 64),
+ * SPFC_E_DEVICE, SPFC_E_NONFINITE (energies with the sticky NONFINITE flag set; phi_out
+ * and energy_out are still written). */
+#define SPFC_NOALLOC_BYTES ((size_t)64 << 20)
+int spfc_run_noalloc(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev, double dt,
+                     int64_t n, void* phi_out_dev, int dtype, spfc_energy_t* energy_out, void* hip_stream);
 
 /* Static description of a status code. */
 const char* spfc_strerror(int status);

@@ -30,8 +30,10 @@ EXPORTS = [
     "spfc_tune_bytes", "spfc_tune", "spfc_get_plan", "spfc_batch_tune_bytes", "spfc_batch_tune",
     "spfc_batch_get_plan", "spfc_time_kernels", "spfc_batch_time_kernels", "spfc_batch_reset",
     "spfc_batch_energies", "spfc_batch_get_phi_all", "spfc_forcing_bytes", "spfc_set_forcing",
-    "spfc_step_forced",
+    "spfc_step_forced", "spfc_run_noalloc",
 ]
+
+SPFC_NOALLOC_BYTES = 64 << 20
 
 
 class spfc_grid(ctypes.Structure):
@@ -118,6 +120,7 @@ def load_library(path: str | None = None):
         "spfc_batch_energies": [vp, P(spfc_energy_t)],
         "spfc_batch_get_phi_all": [vp, P(vp), i32],
         "spfc_batch_kernel_times": [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64), P(dbl), P(i32)],
+        "spfc_run_noalloc": [P(spfc_grid), P(spfc_params), vp, dbl, i64, vp, i32, P(spfc_energy_t), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -431,6 +434,17 @@ def spfc_batch_kernel_times(b) -> list:
 
 def spfc_batch_destroy(b):
     _check("spfc_batch_destroy", load_library().spfc_batch_destroy(b))
+
+
+def spfc_run_noalloc(grid, params, phi0_ptr: int, dt: float, n: int, out_ptr: int, dtype: int = SPFC_FP64,
+                     stream_ptr: int = 0) -> dict:
+    """One run in the library's own per-device array (no allocation); returns the energies
+    of phi^n, which is written to out_ptr."""
+    e = spfc_energy_t()
+    _check("spfc_run_noalloc", load_library().spfc_run_noalloc(ctypes.byref(grid), ctypes.byref(params), phi0_ptr,
+                                                               float(dt), int(n), out_ptr, int(dtype),
+                                                               ctypes.byref(e), stream_ptr))
+    return {k: getattr(e, k) for k, _ in spfc_energy_t._fields_}
 
 
 # ------------------------------------------------------------------ convenience class (PyTorch memory + stream)

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -1532,6 +1533,63 @@ int spfc_destroy(spfc_ctx* ctx) {
     if (!ctx) return SPFC_E_INVAL;
     free_ctx(ctx);
     return SPFC_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free run
+
+// The workspace of spfc_run_noalloc: one array per device, part of the code object.
+// Host code never takes its name as an address: the device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[SPFC_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(char** ptr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPFC_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPFC_E_DEVICE;
+        if (reinterpret_cast<uintptr_t>(p) % kAlign) return SPFC_E_DEVICE;
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return SPFC_OK;
+}
+
+}  // namespace
+
+int spfc_run_noalloc(const spfc_grid* grid, const spfc_params* params, const double* phi0_dev, double dt,
+                     int64_t n, void* phi_out_dev, int dtype, spfc_energy_t* energy_out, void* hip_stream) {
+    const TraceRange trace_("spfc_run_noalloc");
+    if (!phi0_dev || !phi_out_dev || (dtype != SPFC_FP64 && dtype != SPFC_FP32)) return SPFC_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
+    int rc = validate(grid, params);
+    if (rc) return rc;
+    const size_t need = class_bytes(*grid, *params, 1);
+    if (need > SPFC_NOALLOC_BYTES) return SPFC_E_NOMEM;
+    char* ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    // spfc_init on the array (it clears the scalar blocks and the history; every field
+    // region is written before it is read)
+    spfc_ctx* ctx = nullptr;
+    if ((rc = spfc_init(grid, params, phi0_dev, ws, SPFC_NOALLOC_BYTES, hip_stream, &ctx))) return rc;
+    rc = ctx_step(ctx, dt, n);
+    if (!rc) rc = ctx_get_phi(ctx, 0, phi_out_dev, dtype);
+    if (!rc) {
+        spfc_energy_t e{};
+        rc = ctx_energy(ctx, 0, &e);
+        if ((rc == SPFC_OK || rc == SPFC_E_NONFINITE) && energy_out) *energy_out = e;
+    }
+    if ((rc == SPFC_OK || rc == SPFC_E_NONFINITE) && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = SPFC_E_DEVICE;
+    free_ctx(ctx);
+    return rc;
 }
 
 // ---------------------------------------------------------------- batches

@@ -193,3 +193,29 @@ def test_fno_sizes_and_validation_without_a_device():
                              ctypes.byref(h)) == 2
     assert lib.spfc_fno_forward(None, 1, 256, 256, 256) == 1
     assert lib.spfc_fno_destroy(None) == 1
+
+
+def test_noalloc_limits_and_refusals_without_a_device():
+    """The allocation-free run's array holds the grids its header names, and the call refuses
+    bad arguments and grids beyond the array before it makes any device call."""
+    B = _lib()
+    lib = B.load_library()
+    fits = [((1024, 512), "fp64"), ((1024, 1024), "fp32"), ((128, 128, 64), "fp32")]
+    for n, prec in fits:
+        g = B.make_grid(n, (10.0,) * len(n))
+        assert B.spfc_workspace_bytes(g, B.make_params(0.25, precision=prec)) <= B.SPFC_NOALLOC_BYTES, n
+    big = B.make_grid((1024, 1024), (10.0, 10.0))
+    p64 = B.make_params(0.25)
+    assert B.spfc_workspace_bytes(big, p64) > B.SPFC_NOALLOC_BYTES
+    e = B.spfc_energy_t()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every case below is refused first
+    st = lib.spfc_run_noalloc(ctypes.byref(big), ctypes.byref(p64), fake, 0.01, 1, fake, B.SPFC_FP64, ctypes.byref(e),
+                              None)
+    assert st == B.SPFC_E_NOMEM
+    small = B.make_grid((64, 64), (10.0, 10.0))
+    for args in [(small, p64, None, 0.01, 1, fake, B.SPFC_FP64), (small, p64, fake, 0.0, 1, fake, B.SPFC_FP64),
+                 (small, p64, fake, 0.01, -1, fake, B.SPFC_FP64), (small, p64, fake, 0.01, 1, None, B.SPFC_FP64),
+                 (small, p64, fake, 0.01, 1, fake, 7), (B.make_grid((100, 64), (1, 1)), p64, fake, 0.01, 1, fake, 0)]:
+        g, p, phi, dt, n, out, dtype = args
+        assert lib.spfc_run_noalloc(ctypes.byref(g), ctypes.byref(p), phi, dt, n, out, dtype, ctypes.byref(e),
+                                    None) == B.SPFC_E_INVAL
