@@ -95,7 +95,7 @@ struct SpecInvArgs {
     const cpx<T>* prev;     // Y of the pair (or phi^{n-1} before the update)
     const cpx<T>* nhat;     // N of the previous step (update only)
     cpx<T>* out_new;        // where the updated state goes (update only)
-    cpx<T>* out[3];         // d gradient fields
+    cpx<T>* out[3];         // phihat and i kappa1 phihat of the line's axis, transformed
     const cpx<T>* tw;
     int tws;
     int nlines, B;          // lines = A * B, b fastest
@@ -159,6 +159,7 @@ struct PassArgs {
     int tws;
     int nlines, B, G;
     size_t fs;
+    const Geo* geos;        // the 3-D y passes of a step (their y symbols); else unused
 };
 
 // Real rows <-> half-spectrum rows (set-up and queries), for up to ROW_TAB members in

@@ -111,11 +111,20 @@ hipError_t Kern<T>::pass(int nl, int dir, int omode, int c, const PassArgs<T>& a
         SPFC_PASS_CASE(-1, OUT_SWAP, 1)
         SPFC_PASS_CASE(+1, OUT_ROTATE, 1)
         SPFC_PASS_CASE(+1, OUT_SWAP, 1)
-        SPFC_PASS_CASE(+1, OUT_SWAP, 3)
-        SPFC_PASS_CASE(-1, OUT_SWAP, 3)
         return hipErrorInvalidValue;
     });
 #undef SPFC_PASS_CASE
+}
+
+template <typename T>
+hipError_t Kern<T>::ypass(int nl, int dir, const PassArgs<T>& a, const LaunchShape& s, hipStream_t st) {
+    return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
+        SPFC_NE_CONSTS
+        const dim3 g(s.grid, s.members), b(s.block);
+        if (dir > 0) hipLaunchKernelGGL((k_ypass<T, NN, EE, +1>), g, b, s.shmem, st, a);
+        else hipLaunchKernelGGL((k_ypass<T, NN, EE, -1>), g, b, s.shmem, st, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>

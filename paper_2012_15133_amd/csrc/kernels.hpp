@@ -480,12 +480,15 @@ __device__ inline void tiled_line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* til
 //   X = (udt xi (-|k|^2) N + ua1 C + ua2 P) / (ua0 + udt |k|^2 (a + |k|^4)),  Y = C
 // (eq. scheme-SAV-1 solved for phi^{n+1}), else X = C, Y = P.  Partials of
 // ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2, ||Delta X||^2 (modified energy,
-// eq. discrete energy; E_N, eq. energy-discrete-spectral).  Then
-// Z_j = i kappa1_j (e1 X + e2 Y) and the inverse transform along the line.
+// eq. discrete energy; E_N, eq. energy-discrete-spectral).  Then the inverse
+// transform along the line of phihat = e1 X + e2 Y and of i kappa1 phihat for the
+// line's own axis.  The symbols of the other axes are constant along the line, so
+// the later passes apply them (i kappa1_y before the y transform in 3-D, i kappa1_x
+// as the real-space pass loads its rows): two fields out instead of d.
 template <typename T, int NL, int EE, int DIM, bool STAB>
 __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     using PL = Plan<NL, EE>;
-    constexpr int E = PL::E, P = PL::P, C = DIM;
+    constexpr int E = PL::E, P = PL::P, C = 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
@@ -558,11 +561,9 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
             }
         }
         const cpx<T> ph = mk<T>(h1 * X.x + h2 * Y.x, h1 * X.y + h2 * Y.y);
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const T kk = T(k1[j]);
-            v[j][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1_j phihat
-        }
+        const T kk = T(k1[DIM - 1]);
+        v[0][m] = ph;
+        v[1][m] = mk<T>(-kk * ph.y, kk * ph.x);   // i kappa1 phihat along the line's axis
     }
     if (!p.update) store_energy_partials<STAB>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
     if (p.want_grad) {
@@ -588,9 +589,12 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
 
 // ------------------------------------------------------------------ real-space pass
 
-// Packing of real rows into complex lines.  2-D: one row per group, line 0 =
+// Packing of real rows into complex lines.  The input fields are the rows of
+// phihat (field 0, its x half spectrum; i kappa1_x times it is that of g_x), of g_y
+// (field 1) and, in 3-D, of g_z (field 2).  2-D: one row per group, line 0 =
 // g_x + i g_y.  3-D: two rows per group, lines (g_x + i g_y)(row 0),
-// (g_x + i g_y)(row 1), g_z(row 0) + i g_z(row 1).
+// (g_x + i g_y)(row 1), g_z(row 0) + i g_z(row 1).  kx(c): the real part of line c
+// is g_x, whose half row is i kappa1_x times the row of field 0.
 template <int DIM>
 struct RealPack {
     static constexpr int C = DIM == 2 ? 1 : 3;
@@ -599,25 +603,42 @@ struct RealPack {
     __device__ static constexpr int fb(int c) { return DIM == 2 ? 1 : (c < 2 ? 1 : 2); }
     __device__ static constexpr int ra(int c) { return DIM == 2 ? 0 : (c == 1 ? 1 : 0); }
     __device__ static constexpr int rb(int c) { return DIM == 2 ? 0 : (c == 0 ? 0 : 1); }
+    __device__ static constexpr bool kx(int c) { return fa(c) == 0; }
 };
 
+// i kappa1_x(k) z and -i kappa1_x(k) z for x wavenumber k <= N/2 (the odd-order symbol
+// drops Nyquist)
+template <typename T>
+__device__ inline cpx<T> mul_ikx(cpx<T> z, int k, int n, double k0) {
+    const T kk = T(sym1(k, n, k0));
+    return mk<T>(-kk * z.y, kk * z.x);
+}
+template <typename T>
+__device__ inline cpx<T> mul_mikx(cpx<T> z, int k, int n, double k0) {
+    const T kk = T(sym1(k, n, k0));
+    return mk<T>(kk * z.y, -kk * z.x);
+}
+
 // Load element e (0..N-1) of the complex line whose real part is the real row
-// with half spectrum h1 and whose imaginary part has half spectrum h2:
+// with half spectrum H1 and whose imaginary part has half spectrum H2:
 // W(e) = H1(e) + i H2(e), H(e) = conj(H(N - e)) above N/2; the self-conjugate
-// bins 0 and N/2 keep their real parts only.
-template <typename T, int N>
-__device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e) {
+// bins 0 and N/2 keep their real parts only.  H2 = h2; H1 = h1, or with KX
+// H1 = i kappa1_x h1 (symbol k0).
+template <typename T, int N, bool KX>
+__device__ inline cpx<T> load_packed(const cpx<T>* h1, const cpx<T>* h2, int e, double k0) {
     cpx<T> a, b;
+    const int k = 2 * e <= N ? e : N - e;
+    a = h1[k];
+    b = h2[k];
+    if constexpr (KX) a = mul_ikx(a, k, N, k0);
     if (2 * e <= N) {
-        a = h1[e];
-        b = h2[e];
         if (e == 0 || 2 * e == N) {
             a.y = T(0);
             b.y = T(0);
         }
     } else {
-        a = conj(h1[N - e]);
-        b = conj(h2[N - e]);
+        a = conj(a);
+        b = conj(b);
     }
     return mk<T>(a.x - b.y, a.y + b.x);
 }
@@ -644,8 +665,9 @@ __device__ inline cpx<T> lane_fetch(cpx<T> v, int src) {
 // that loaded N - e and moved across lanes: element m >= E/2 of thread t > 0 mirrors
 // element E - 1 - m of thread P - t, and thread 0's mirror its own element E - m.
 // Needs the P threads of a line within one wave (P <= 64).  All P lanes must call it.
-template <typename T, typename PL>
-__device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int t, cpx<T> (&w)[PL::E]) {
+// With KX, H1 = i kappa1_x h1 (its Nyquist bin is zero).
+template <typename T, typename PL, bool KX>
+__device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int t, cpx<T> (&w)[PL::E], double k0) {
     constexpr int E = PL::E, P = PL::P, N = PL::Nl, H = E / 2;
     static_assert(P <= 64, "a line must lie within one wave");
     cpx<T> a[H], b[H];
@@ -653,8 +675,11 @@ __device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int 
     for (int m = 0; m < H; ++m) {
         a[m] = h1[t + P * m];
         b[m] = h2[t + P * m];
+        if constexpr (KX) a[m] = mul_ikx(a[m], t + P * m, N, k0);
     }
-    const cpx<T> an = h1[N / 2], bn = h2[N / 2];
+    cpx<T> an = h1[N / 2];
+    const cpx<T> bn = h2[N / 2];
+    if constexpr (KX) an = mk<T>(T(0), T(0));
     if (t == 0) {
         a[0].y = T(0);
         b[0].y = T(0);
@@ -686,7 +711,9 @@ __device__ inline void store_pair(cpx<T>* dst, cpx<T> a, cpx<T> b) {
 
 // Gradient rows (half spectra along x) -> C2R -> s = |grad phihat|^2,
 // E_1 partial sum (c4/4) s^2 - s, q = c4 s grad phihat (eq. nonlinear chem pot-1) ->
-// R2C -> flux spectra written rotated [kx][rows].  FWD = false: E_1 only.
+// R2C -> flux spectra written rotated [kx][rows]: -i kappa1_x Q_x (the x term of the
+// divergence in N, applied here where kx is known), Q_y and (3-D) Q_z.  FWD = false:
+// E_1 only.
 template <typename T, int NX, int EE, int DIM, bool FWD>
 __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     using PK = RealPack<DIM>;
@@ -714,14 +741,19 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
         const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
         const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
         if constexpr (P <= 64) {
-            load_packed_once<T, PL>(h1, h2, t, v[c]);
+            // (c is a constant once the loop is unrolled)
+            if (PK::kx(c)) load_packed_once<T, PL, true>(h1, h2, t, v[c], geo.k0x);
+            else load_packed_once<T, PL, false>(h1, h2, t, v[c], 0.0);
             if (!act) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) v[c][m] = mk<T>(0, 0);
             }
         } else {
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[c][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+            for (int m = 0; m < E; ++m)
+                v[c][m] = !act ? mk<T>(0, 0)
+                               : PK::kx(c) ? load_packed<T, NX, true>(h1, h2, t + P * m, geo.k0x)
+                                           : load_packed<T, NX, false>(h1, h2, t + P * m, 0.0);
         }
     }
     issue_barrier();
@@ -799,6 +831,8 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                     } else if (f == 0) {
                         split(0, k, ra[m], x);
                         split(1, k, rb[m], y);
+                        ra[m] = mul_mikx(ra[m], k, NX, geo.k0x);
+                        rb[m] = mul_mikx(rb[m], k, NX, geo.k0x);
                     } else {
                         split(0, k, x, ra[m]);
                         split(1, k, y, rb[m]);
@@ -842,7 +876,8 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
 #pragma unroll
                         for (int c = 0; c < C; ++c) split(c, k, q1[c], q2[c]);
                         const size_t o = mbase + (size_t)k * p.nrows + row0;
-                        store_pair(p.out[0] + o, q1[0], q1[1]);   // lines 0, 1: g_x of rows 0, 1
+                        store_pair(p.out[0] + o, mul_mikx(q1[0], k, NX, geo.k0x),
+                                   mul_mikx(q1[1], k, NX, geo.k0x));   // lines 0, 1: g_x of rows 0, 1
                         store_pair(p.out[1] + o, q2[0], q2[1]);   // g_y of rows 0, 1
                         store_pair(p.out[2] + o, q1[2], q2[2]);   // line 2: g_z of rows 0, 1
                     }
@@ -858,6 +893,7 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                             if (m == E / 2 && t != 0) break;
                             cpx<T> q1, q2;
                             split(c, k, q1, q2);
+                            if (PK::kx(c)) q1 = mul_mikx(q1, k, NX, geo.k0x);
                             o1[(size_t)k * p.nrows + r1] = q1;
                             o2[(size_t)k * p.nrows + r2] = q2;
                         }
@@ -922,19 +958,93 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
     }
 }
 
+// ------------------------------------------------------------------ 3-D y passes of a step
+
+// Lines along y, [a][b][Y] with b the faster line index (inverse: a = z, b = kx;
+// forward: a = kx, b = z), written [a][Y][b] through the LDS tile.
+// Inverse (DIR = +1): in[0] = Psi, in[1] = Psi_z, the z transforms of phihat and of
+// i kappa1_z phihat; out[0..2] = the y transforms of Psi (i kappa1_x times it is the
+// x half spectrum of g_x, applied by the real-space pass), of i kappa1_y Psi (g_y) and
+// of Psi_z (g_z).  Forward (DIR = -1): in[0..2] = -i kappa1_x Q_x, Q_y, Q_z after the
+// x transform; out[0] = V0 - i kappa1_y V1 and out[1] = V2 of their y transforms V0..V2,
+// so that only the z term of the divergence is left for the last pass.
+template <typename T, int NL, int EE, int DIR>
+__global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
+    using PL = Plan<NL, EE>;
+    constexpr int E = PL::E, P = PL::P, C = 3;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
+    const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
+    const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
+    const bool act = line < p.nlines;
+    const int mem = blockIdx.y;
+    const Geo geo = p.geos[mem];
+    const size_t mbase = (size_t)mem * p.fs;
+    const size_t lbase = mbase + (size_t)(act ? line : 0) * NL;
+    TwStage<T, PL> tws;
+    tws.load(p.tw, p.tws);
+    issue_barrier();
+    cpx<T> v[C][E];
+    if constexpr (DIR > 0) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = t + P * m;
+            const cpx<T> a = p.in[0][lbase + e], b = p.in[1][lbase + e];
+            const T ky = T(sym1(e, geo.ny, geo.k0y));
+            v[0][m] = a;
+            v[1][m] = mk<T>(-ky * a.y, ky * a.x);   // i kappa1_y Psi
+            v[2][m] = b;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[c][m] = p.in[c][lbase + t + P * m];
+    }
+    // (lanes past the last line loaded line 0 of the member; they store nothing)
+    issue_barrier();
+    tws.store(ltw);
+    fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
+    const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
+    auto idx = [&](int, int e, int gi) -> long long {
+        const int ln = line0 + gi;
+        if (ln >= p.nlines) return -1;
+        const int a = ln / p.B, b = ln - a * p.B;
+        return ((long long)a * NL + e) * p.B + b;
+    };
+    if constexpr (DIR > 0) {
+        tiled_line_store<T, PL, 3>(v, lds, p.G, g, t, p.out, mbase, idx);
+    } else {
+        cpx<T> w[2][E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const T ky = T(sym1(t + P * m, geo.ny, geo.k0y));
+            w[0][m] = mk<T>(v[0][m].x + ky * v[1][m].y, v[0][m].y - ky * v[1][m].x);   // V0 - i kappa1_y V1
+            w[1][m] = v[2][m];
+        }
+        tiled_line_store<T, PL, 2>(w, lds, p.G, g, t, p.out, mbase, idx);
+    }
+}
+
 // ------------------------------------------------------------------ spectral forward pass + solve
 
-// Finish one step from the reduced sums (one lane).  Follows Section 2.3 in the
-// form xi = r^{n+1} / sqrt(E_1): with phi^{n+1} = dt xi b1 + b2, b1 = A^-1 Delta N,
+// Forward transform along the last axis of the two flux fields the earlier passes
+// leave: V0, in which every divergence term but the last axis's is already applied
+// (2-D: -i kappa1_x Q_x; 3-D: -i kappa1_x Q_x - i kappa1_y Q_y), and V1 = Q of the last
+// axis.  Then N = V0 - i kappa1 V1 - 2 |k|^2 phihat (eq. nonlinear chem pot-1, divergence
+// and the Laplacian part of N), the two solves and the inner products.  In terms of
+// xi = r^{n+1} / sqrt(E_1): with phi^{n+1} = dt xi b1 + b2, b1 = A^-1 Delta N,
 // b2 = A^-1 psi, the r equation (eq. scheme-SAV-1, second line) gives
 //   xi = [rho + (a0 p2 - p_psi) / (2S)] / [a0 (S - dt p1 / (2S))],
-// p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1).
+// p1 = <N, b1> <= 0 (eq. solver-5), p2 = <N, b2>, p_psi = <N, psi>, S = sqrt(E_1); this
+// kernel forms the partial sums of p1, p2 and p_psi.
 // Stabilized scheme: A gains stab dt^2 |k|^4 and b2 = A^-1 (psi + stab dt^2 |k|^4 phi^n);
 // the r equation, and so p_psi, keeps psi.
 template <typename T, int NL, int EE, int DIM, int MODE, bool STAB>
 __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     using PL = Plan<NL, EE>;
-    constexpr int E = PL::E, P = PL::P, C = DIM;
+    constexpr int E = PL::E, P = PL::P, C = 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
@@ -983,15 +1093,10 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
             spec_symbols<DIM>(geo, kx, ky, kz, k2, k1);
             const cpx<T> X = Xs[m], Y = Ys[m];
             const double phx = p.e1 * X.x + p.e2 * Y.x, phy = p.e1 * X.y + p.e2 * Y.y;
-            // div of the flux: sum_j i kappa1_j Q_j; N = -div - 2 |k|^2 phihat
-            double dx = 0.0, dy = 0.0;
-#pragma unroll
-            for (int j = 0; j < C; ++j) {
-                dx += k1[j] * (double)v[j][m].x;
-                dy += k1[j] * (double)v[j][m].y;
-            }
-            const double Nx = dy - 2.0 * k2 * phx;
-            const double Ny = -dx - 2.0 * k2 * phy;
+            // N = V0 - i kappa1 V1 - 2 |k|^2 phihat (kappa1 of the line's axis)
+            const double kl = k1[DIM - 1];
+            const double Nx = (double)v[0][m].x + kl * (double)v[1][m].y - 2.0 * k2 * phx;
+            const double Ny = (double)v[0][m].y - kl * (double)v[1][m].x - 2.0 * k2 * phy;
             if constexpr (MODE != FWD_GHOST) {
                 const double psx = p.a1 * X.x + p.a2 * Y.x, psy = p.a1 * X.y + p.a2 * Y.y;
                 const double st = stab_sym<STAB>(geo, p.dt, k2);
@@ -1126,7 +1231,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows(RowArgs<T> p) {
     const cpx<T>* h2 = in + (size_t)(act ? row0 + 1 : 0) * NXH;
     cpx<T> v[1][E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[0][m] = act ? load_packed<T, NX>(h1, h2, t + P * m) : mk<T>(0, 0);
+    for (int m = 0; m < E; ++m) v[0][m] = act ? load_packed<T, NX, false>(h1, h2, t + P * m, 0.0) : mk<T>(0, 0);
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
     fft_run<T, PL, +1, 1>(v, lds, t, ltw);
     if (!act) return;

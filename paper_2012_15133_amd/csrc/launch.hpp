@@ -58,6 +58,8 @@ struct Kern {
                                const LaunchShape& s, hipStream_t st);
     static hipError_t pass(int nl, int dir, int omode, int c, const PassArgs<T>& a, const LaunchShape& s,
                            hipStream_t st);
+    // the 3-D y passes of a step (k_ypass): dir +1 inverse (2 fields in, 3 out), -1 forward (3 in, 2 out)
+    static hipError_t ypass(int nl, int dir, const PassArgs<T>& a, const LaunchShape& s, hipStream_t st);
     static hipError_t update(int dim, bool stab, const UpdateArgs<T>& a, int grid, int members, int block,
                              hipStream_t st);
     static hipError_t r2c_rows(int nx, const RowArgs<T>& a, const LaunchShape& s, hipStream_t st);

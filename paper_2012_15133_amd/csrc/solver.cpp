@@ -103,8 +103,9 @@ Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
     const int d = s.dim;
     const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
     const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines per member
-    h.A = line_shape(nl, d, s.elem, nlines, tp.inv.E, tp.inv.T);
-    h.Cf = line_shape(nl, d, s.elem, nlines, tp.fwd.E, tp.fwd.T);
+    // the spectral passes carry two lines each (phihat and one derivative; two flux fields)
+    h.A = line_shape(nl, 2, s.elem, nlines, tp.inv.E, tp.inv.T);
+    h.Cf = line_shape(nl, 2, s.elem, nlines, tp.fwd.E, tp.fwd.T);
     const int rowgroups = d == 2 ? s.ny : s.nz * s.ny / 2;
     h.B = line_shape(s.nx, d == 2 ? 1 : 3, s.elem, rowgroups, tp.real.E, tp.real.T);
     if (d == 3) {
@@ -446,10 +447,12 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    // 3-D middle pass along y: in -> out, [a][b][Y] -> [a][Y][b]
+    // 3-D middle pass along y: in -> out, [a][b][Y] -> [a][Y][b]; inverse 2 fields in, 3
+    // out; forward 3 in, 2 out
     int mid(int dir, char* const* in, char* const* out, const LaunchShape& s, int nlines, int B, int role,
             bool timed) {
         PassArgs<T> a{};
+        a.geos = ctx->dgeos();
         for (int j = 0; j < 3; ++j) {
             a.in[j] = (const C*)in[j];
             a.out[j] = (C*)out[j];
@@ -461,7 +464,7 @@ struct Pipe {
         a.G = s.G;
         a.fs = ctx->lay.fs;
         Timed tm(ctx, role, timed);
-        for (int r = 0; r < tm.reps(); ++r) CK(Kern<T>::pass(ctx->sz.ny, dir, OUT_SWAP, 3, a, s, ctx->stream));
+        for (int r = 0; r < tm.reps(); ++r) CK(Kern<T>::ypass(ctx->sz.ny, dir, a, s, ctx->stream));
         return SPFC_OK;
     }
 
@@ -1483,7 +1486,7 @@ int spfc_kernel_times(spfc_ctx* ctx, int cap, const char** names, double* avg_ms
     if (rc) return rc;
     const double F = (double)ctx->lay.F * ctx->M;
     const int d = ctx->sz.dim;
-    const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F, 0.0};
+    const double bytes[R_COUNT] = {6.0 * F, 5.0 * F, 2.0 * d * F, 5.0 * F, 5.0 * F, 0.0};
     int k = 0;
     for (int i = 0; i < R_COUNT; ++i) {
         if (ctx->role_n[i] == 0) continue;
@@ -1711,7 +1714,7 @@ int spfc_batch_kernel_times(spfc_batch* b, int cap, const char** names, double* 
         if (rc) return rc;
         const double F = (double)ctx->lay.F * ctx->M;
         const int d = ctx->sz.dim;
-        const double bytes[R_COUNT] = {(4.0 + d) * F, 6.0 * F, 2.0 * d * F, 6.0 * F, (3.0 + d) * F, 0.0};
+        const double bytes[R_COUNT] = {6.0 * F, 5.0 * F, 2.0 * d * F, 5.0 * F, 5.0 * F, 0.0};
         for (int i = 0; i < R_COUNT; ++i) {
             if (ctx->role_n[i] == 0) continue;
             ms[i] += ctx->role_ms[i] / (double)ctx->role_n[i];
