@@ -87,7 +87,13 @@ typedef struct {
  *             the chemical potential of every step (the step operator gains A dt^2 |k|^4,
  *             its right-hand side A dt^2 |k|^4 phi^n), and the modified energy gains
  *             (A dt / 4) <phi^n - phi^{n-1}, -Delta_N (phi^n - phi^{n-1})>, with which it
- *             is again non-increasing.  0 = the scheme eq. scheme-SAV-1. */
+ *             is again non-increasing.  0 = the scheme eq. scheme-SAV-1.
+ *  beta     : >= 0.  Adds (beta/4) phi^4 to the energy density, the quartic term of the
+ *             standard PFC energy (Section 1, eq. energy-PFC), beside the 4-Laplacian term
+ *             (0 = the SPFC energy of the paper).  Being convex and nonnegative it joins the
+ *             nonlinear part: E_1 gains (beta/4)||phi||_4^4 (E_1 >= |Omega| still holds),
+ *             N gains beta phi^3, E_N gains (beta/4)||phi||_4^4.  Any beta > 0 in a batch
+ *             class runs the class on the kernels that carry phi to real space. */
 typedef struct {
     double epsilon;
     double c4;
@@ -96,6 +102,7 @@ typedef struct {
     int64_t history;
     double energy_tol;
     double stab;
+    double beta;
 } spfc_params;
 
 /* Per-step record (index n = state phi^n).  energy is the modified energy

@@ -43,7 +43,7 @@ class spfc_grid(ctypes.Structure):
 class spfc_params(ctypes.Structure):
     _fields_ = [("epsilon", ctypes.c_double), ("c4", ctypes.c_double), ("startup", ctypes.c_int),
                 ("precision", ctypes.c_int), ("history", ctypes.c_int64), ("energy_tol", ctypes.c_double),
-                ("stab", ctypes.c_double)]
+                ("stab", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class spfc_record(ctypes.Structure):
@@ -157,9 +157,10 @@ def make_grid(n, L) -> spfc_grid:
 
 
 def make_params(epsilon, c4=1.0, startup="sav1", precision="fp64", history=4096, energy_tol=0.0,
-                stab=0.0) -> spfc_params:
+                stab=0.0, beta=0.0) -> spfc_params:
     p = spfc_params()
     p.stab = float(stab)
+    p.beta = float(beta)
     p.epsilon = float(epsilon)
     p.c4 = float(c4)
     p.startup = STARTUPS[startup] if isinstance(startup, str) else int(startup)
@@ -474,7 +475,7 @@ class Solver:
     (n_z, n_y, n_x) (x fastest), copied to the device as float64."""
 
     def __init__(self, n, L, phi0, epsilon, c4=1.0, startup="sav1", precision="fp64", history=4096,
-                 energy_tol=0.0, stream=None, graph=False, stab=0.0):
+                 energy_tol=0.0, stream=None, graph=False, stab=0.0, beta=0.0):
         import numpy as np
         import torch
         if not torch.cuda.is_available():
@@ -483,7 +484,7 @@ class Solver:
         self.torch = torch
         self.n = tuple(int(v) for v in n)
         self.grid = make_grid(n, L)
-        self.params = make_params(epsilon, c4, startup, precision, history, energy_tol, stab)
+        self.params = make_params(epsilon, c4, startup, precision, history, energy_tol, stab, beta)
         self.stream = _stream_for(torch, stream, graph)
         nbytes = spfc_workspace_bytes(self.grid, self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -602,7 +603,7 @@ class Solver:
 
 class Batch:
     """Independent runs advanced together on the current HIP device.  members: list of
-    dicts with keys n, L, phi0, epsilon and optionally c4, stab and precision; startup,
+    dicts with keys n, L, phi0, epsilon and optionally c4, stab, beta and precision; startup,
     history and energy_tol are shared."""
 
     def __init__(self, members, startup="sav1", history=4096, energy_tol=0.0, stream=None, graph=False):
@@ -616,7 +617,7 @@ class Batch:
         self.precisions = [m.get("precision", "fp64") for m in members]
         grids = [make_grid(m["n"], m["L"]) for m in members]
         params = [make_params(m["epsilon"], m.get("c4", 1.0), startup, m.get("precision", "fp64"), history,
-                              energy_tol, m.get("stab", 0.0)) for m in members]
+                              energy_tol, m.get("stab", 0.0), m.get("beta", 0.0)) for m in members]
         self.stream = _stream_for(torch, stream, graph)
         nbytes = spfc_batch_workspace_bytes(grids, params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

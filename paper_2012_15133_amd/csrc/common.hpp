@@ -20,6 +20,7 @@ struct Geo {
     double pscale;        // |Omega| / N_total^2: inner product from two spectra (Parseval)
     double e1_const;      // (1 + 1/c4) |Omega|
     double stab;          // A of the stabilized scheme (0: plain scheme)
+    double beta;          // coefficient of the quartic term (beta/4) phi^4 (0: the SPFC energy)
 };
 
 // Device-resident scalars of the run.  Written by one lane only (vector stores),

@@ -2,5 +2,5 @@
 #include "kern_impl.hpp"
 
 namespace spfc {
-template hipError_t Kern<double>::real_pass(int, int, bool, const RealArgs<double>&, const LaunchShape&, hipStream_t);
+template hipError_t Kern<double>::real_pass(int, int, bool, bool, const RealArgs<double>&, const LaunchShape&, hipStream_t);
 }  // namespace spfc

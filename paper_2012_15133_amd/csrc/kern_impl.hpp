@@ -59,17 +59,20 @@ hipError_t Kern<T>::spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a
 }
 
 template <typename T>
-hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, const LaunchShape& s,
+hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, bool beta, const RealArgs<T>& a, const LaunchShape& s,
                               hipStream_t st) {
     return dispatch_ne(nx, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
+        const dim3 g(s.grid, s.members), b(s.block);
+#define SPFC_REAL(D, F, B) hipLaunchKernelGGL((k_real_pass<T, NN, EE, D, F, B>), g, b, s.shmem, st, a)
         if (dim == 2) {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, true>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 2, false>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            if (beta) { if (fwd) SPFC_REAL(2, true, true); else SPFC_REAL(2, false, true); }
+            else { if (fwd) SPFC_REAL(2, true, false); else SPFC_REAL(2, false, false); }
         } else {
-            if (fwd) hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, true>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
-            else hipLaunchKernelGGL((k_real_pass<T, NN, EE, 3, false>), dim3(s.grid, s.members), dim3(s.block), s.shmem, st, a);
+            if (beta) { if (fwd) SPFC_REAL(3, true, true); else SPFC_REAL(3, false, true); }
+            else { if (fwd) SPFC_REAL(3, true, false); else SPFC_REAL(3, false, false); }
         }
+#undef SPFC_REAL
         return hipGetLastError();
     });
 }

@@ -595,15 +595,21 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
 // g_x + i g_y.  3-D: two rows per group, lines (g_x + i g_y)(row 0),
 // (g_x + i g_y)(row 1), g_z(row 0) + i g_z(row 1).  kx(c): the real part of line c
 // is g_x, whose half row is i kappa1_x times the row of field 0.
-template <int DIM>
+//
+// BETA (the quartic term (beta/4) phi^4 of the energy, phi itself needed in real space):
+// two rows per group in both dimensions, and one more line, phi(row 0) + i phi(row 1)
+// from the rows of field 0 as they are (last line: 2-D line 2, 3-D line 3); 2-D lines
+// 0 and 1 are g_x + i g_y of rows 0 and 1.
+template <int DIM, bool BETA = false>
 struct RealPack {
-    static constexpr int C = DIM == 2 ? 1 : 3;
-    static constexpr int RPG = DIM == 2 ? 1 : 2;
-    __device__ static constexpr int fa(int c) { return DIM == 2 ? 0 : (c < 2 ? 0 : 2); }
-    __device__ static constexpr int fb(int c) { return DIM == 2 ? 1 : (c < 2 ? 1 : 2); }
-    __device__ static constexpr int ra(int c) { return DIM == 2 ? 0 : (c == 1 ? 1 : 0); }
-    __device__ static constexpr int rb(int c) { return DIM == 2 ? 0 : (c == 0 ? 0 : 1); }
-    __device__ static constexpr bool kx(int c) { return fa(c) == 0; }
+    static constexpr int C = (DIM == 2 ? 1 : 3) + (BETA ? (DIM == 2 ? 2 : 1) : 0);
+    static constexpr int RPG = (DIM == 2 && !BETA) ? 1 : 2;
+    static constexpr int PHI = BETA ? C - 1 : -1;   // the line of phi
+    __device__ static constexpr int fa(int c) { return c == PHI ? 0 : (DIM == 2 ? 0 : (c < 2 ? 0 : 2)); }
+    __device__ static constexpr int fb(int c) { return c == PHI ? 0 : (DIM == 2 ? 1 : (c < 2 ? 1 : 2)); }
+    __device__ static constexpr int ra(int c) { return c == PHI ? 0 : (c == 1 ? 1 : 0); }
+    __device__ static constexpr int rb(int c) { return c == PHI ? 1 : (DIM == 2 ? (c == 1 ? 1 : 0) : (c == 0 ? 0 : 1)); }
+    __device__ static constexpr bool kx(int c) { return c != PHI && fa(c) == 0; }
 };
 
 // i kappa1_x(k) z and -i kappa1_x(k) z for x wavenumber k <= N/2 (the odd-order symbol
@@ -714,9 +720,11 @@ __device__ inline void store_pair(cpx<T>* dst, cpx<T> a, cpx<T> b) {
 // R2C -> flux spectra written rotated [kx][rows]: -i kappa1_x Q_x (the x term of the
 // divergence in N, applied here where kx is known), Q_y and (3-D) Q_z.  FWD = false:
 // E_1 only.
-template <typename T, int NX, int EE, int DIM, bool FWD>
+// BETA: the rows of phi come along (RealPack), the E_1 partial gains (beta/4) phi^4 and
+// the x field written is -i kappa1_x Q_x + F(beta phi^3), i.e. N gains beta phi^3.
+template <typename T, int NX, int EE, int DIM, bool FWD, bool BETA>
 __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
-    using PK = RealPack<DIM>;
+    using PK = RealPack<DIM, BETA>;
     using PL = Plan<NX, EE>;
     constexpr int E = PL::E, P = PL::P, C = PK::C, RPG = PK::RPG;
     constexpr int NXH = NX / 2 + 1;
@@ -760,12 +768,26 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     tws.store(ltw);
     fft_run<T, PL, +1, C>(v, lds, t, ltw);
 
-    const T sc = T(geo.inv_npts), c4 = T(geo.c4);
-    const double qc4 = 0.25 * geo.c4;
+    const T sc = T(geo.inv_npts), c4 = T(geo.c4), bt = T(geo.beta);
+    const double qc4 = 0.25 * geo.c4, qb4 = 0.25 * geo.beta;
     double acc[1] = {0.0};
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        if constexpr (DIM == 2) {
+        if constexpr (BETA) {
+            // phi of the two rows: P = beta phi^3, E_1 density (beta/4) phi^4
+            const T f0 = v[PK::PHI][m].x * sc, f1 = v[PK::PHI][m].y * sc;
+            const T f02 = f0 * f0, f12 = f1 * f1;
+            acc[0] += qb4 * ((double)f02 * (double)f02 + (double)f12 * (double)f12);
+            v[PK::PHI][m] = mk<T>(bt * f02 * f0, bt * f12 * f1);
+        }
+        if constexpr (DIM == 2 && BETA) {
+            const T ax = v[0][m].x * sc, ay = v[0][m].y * sc, bx = v[1][m].x * sc, by = v[1][m].y * sc;
+            const T sa = ax * ax + ay * ay, sb = bx * bx + by * by;
+            acc[0] += qc4 * (double)sa * (double)sa - (double)sa + qc4 * (double)sb * (double)sb - (double)sb;
+            const T qa = c4 * sa, qb = c4 * sb;
+            v[0][m] = mk<T>(qa * ax, qa * ay);
+            v[1][m] = mk<T>(qb * bx, qb * by);
+        } else if constexpr (DIM == 2) {
             const T gx = v[0][m].x * sc, gy = v[0][m].y * sc;
             const T s = gx * gx + gy * gy;
             acc[0] += qc4 * (double)s * (double)s - (double)s;
@@ -833,6 +855,12 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                         split(1, k, rb[m], y);
                         ra[m] = mul_mikx(ra[m], k, NX, geo.k0x);
                         rb[m] = mul_mikx(rb[m], k, NX, geo.k0x);
+                        if constexpr (BETA) {   // + F(beta phi^3) of the two rows
+                            cpx<T> pa, pb;
+                            split(PK::PHI, k, pa, pb);
+                            ra[m] = ra[m] + pa;
+                            rb[m] = rb[m] + pb;
+                        }
                     } else {
                         split(0, k, x, ra[m]);
                         split(1, k, y, rb[m]);
@@ -876,10 +904,28 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
 #pragma unroll
                         for (int c = 0; c < C; ++c) split(c, k, q1[c], q2[c]);
                         const size_t o = mbase + (size_t)k * p.nrows + row0;
-                        store_pair(p.out[0] + o, mul_mikx(q1[0], k, NX, geo.k0x),
-                                   mul_mikx(q1[1], k, NX, geo.k0x));   // lines 0, 1: g_x of rows 0, 1
+                        cpx<T> r0 = mul_mikx(q1[0], k, NX, geo.k0x), r1 = mul_mikx(q1[1], k, NX, geo.k0x);
+                        if constexpr (BETA) {
+                            r0 = r0 + q1[PK::PHI];
+                            r1 = r1 + q2[PK::PHI];
+                        }
+                        store_pair(p.out[0] + o, r0, r1);         // lines 0, 1: g_x of rows 0, 1
                         store_pair(p.out[1] + o, q2[0], q2[1]);   // g_y of rows 0, 1
                         store_pair(p.out[2] + o, q1[2], q2[2]);   // line 2: g_z of rows 0, 1
+                    }
+                } else if constexpr (BETA) {
+                    // 2-D with phi: rows row0, row0 + 1 (even row0) are neighbours in both outputs
+#pragma unroll
+                    for (int m = 0; m <= E / 2; ++m) {
+                        const int k = t + P * m;
+                        if (m == E / 2 && t != 0) break;
+                        cpx<T> q1[C], q2[C];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) split(c, k, q1[c], q2[c]);
+                        const size_t o = mbase + (size_t)k * p.nrows + row0;
+                        store_pair(p.out[0] + o, mul_mikx(q1[0], k, NX, geo.k0x) + q1[PK::PHI],
+                                   mul_mikx(q1[1], k, NX, geo.k0x) + q2[PK::PHI]);
+                        store_pair(p.out[1] + o, q2[0], q2[1]);
                     }
                 } else {
 #pragma unroll

@@ -52,7 +52,7 @@ struct Kern {
     // stab: the stabilized-scheme variant (any member with a nonzero stabilization)
     static hipError_t spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a, const LaunchShape& s,
                                hipStream_t st);
-    static hipError_t real_pass(int nx, int dim, bool fwd, const RealArgs<T>& a, const LaunchShape& s,
+    static hipError_t real_pass(int nx, int dim, bool fwd, bool beta, const RealArgs<T>& a, const LaunchShape& s,
                                 hipStream_t st);
     static hipError_t spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwdArgs<T>& a,
                                const LaunchShape& s, hipStream_t st);

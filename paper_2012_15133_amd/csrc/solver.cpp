@@ -34,6 +34,7 @@ const char* const kRoleNames[R_COUNT] = {"spec_inv", "pass_y_inv", "real_pass", 
 struct Sizes {
     int dim, nx, ny, nz, nxh;
     size_t elem;
+    bool beta = false;   // the quartic term: the real-space pass carries the rows of phi
 };
 
 struct Shapes {
@@ -106,8 +107,11 @@ Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
     // the spectral passes carry two lines each (phihat and one derivative; two flux fields)
     h.A = line_shape(nl, 2, s.elem, nlines, tp.inv.E, tp.inv.T);
     h.Cf = line_shape(nl, 2, s.elem, nlines, tp.fwd.E, tp.fwd.T);
-    const int rowgroups = d == 2 ? s.ny : s.nz * s.ny / 2;
-    h.B = line_shape(s.nx, d == 2 ? 1 : 3, s.elem, rowgroups, tp.real.E, tp.real.T);
+    // real-space pass: lines per row group (2-D one row per group; 3-D and with the
+    // quartic term two rows, plus the line of phi)
+    const int rowgroups = (d == 2 && !s.beta) ? s.ny : s.nz * s.ny / 2;
+    const int cB = (d == 2 ? 1 : 3) + (s.beta ? (d == 2 ? 2 : 1) : 0);
+    h.B = line_shape(s.nx, cB, s.elem, rowgroups, tp.real.E, tp.real.T);
     if (d == 3) {
         h.midI = line_shape(s.ny, 3, s.elem, s.nz * s.nxh, tp.mid.E, tp.mid.T);
         h.midF = line_shape(s.ny, 3, s.elem, s.nxh * s.nz, tp.mid.E, tp.mid.T);
@@ -128,9 +132,11 @@ Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
 
 // Partial-sum buffers are sized for any launch plan (one line group per workgroup
 // gives the most workgroups), so that a context can change its plan in place.
-Layout layout_of(const Sizes& s, int64_t hist_cap, int M) {
+Layout layout_of(const Sizes& s0, int64_t hist_cap, int M) {
     TunePlan widest;
     widest.inv.T = widest.real.T = widest.fwd.T = widest.mid.T = 1;
+    Sizes s = s0;
+    s.beta = false;   // one real-space row per workgroup in 2-D: the most partials of either variant
     const Shapes h = shapes_of(s, M, widest);
     Layout L{};
     L.fs = (size_t)s.nxh * s.ny * s.nz;
@@ -171,6 +177,7 @@ int validate(const spfc_grid* g, const spfc_params* p) {
     if (p->history < 1) return SPFC_E_INVAL;
     if (!std::isfinite(p->energy_tol)) return SPFC_E_INVAL;
     if (!std::isfinite(p->stab) || p->stab < 0.0) return SPFC_E_INVAL;
+    if (!std::isfinite(p->beta) || p->beta < 0.0) return SPFC_E_INVAL;
     return SPFC_OK;
 }
 
@@ -195,6 +202,7 @@ Geo make_geo(const spfc_grid& g, const spfc_params& prm) {
     geo.pscale = vol / (npts * npts);
     geo.e1_const = (1.0 + 1.0 / prm.c4) * vol;
     geo.stab = prm.stab;
+    geo.beta = prm.beta;
     return geo;
 }
 
@@ -484,7 +492,7 @@ struct Pipe {
         a.geos = ctx->dgeos();
         Timed tm(ctx, R_REAL, timed);
         for (int r = 0; r < tm.reps(); ++r)
-            CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, a, ctx->sh.B, ctx->stream));
+            CK(Kern<T>::real_pass(ctx->sz.nx, ctx->sz.dim, fwd, ctx->sz.beta, a, ctx->sh.B, ctx->stream));
         return SPFC_OK;
     }
 
@@ -910,11 +918,14 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     ctx->prm = p0;
     ctx->M = M;
     ctx->stab = false;
+    bool beta = false;
     for (int m = 0; m < M; ++m) {
         ctx->geos.push_back(make_geo(grids[idx[m]], params[idx[m]]));
         ctx->stab = ctx->stab || params[idx[m]].stab != 0.0;
+        beta = beta || params[idx[m]].beta != 0.0;
     }
     ctx->sz = sizes_of(grids[idx[0]], p0.precision);
+    ctx->sz.beta = beta;   // some member has the quartic term: the class runs that variant
     ctx->plan = tune_plan();
     if (!plan_fits(ctx->sz, M, ctx->plan, device_lds_max())) {
         delete ctx;

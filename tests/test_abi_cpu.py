@@ -58,6 +58,8 @@ def test_workspace_and_validation():
         (g, B.make_params(0.25, history=0)),
         (g, B.make_params(0.25, stab=-1.0)),
         (g, B.make_params(0.25, stab=float("inf"))),
+        (g, B.make_params(0.25, beta=-0.5)),
+        (g, B.make_params(0.25, beta=float("nan"))),
     ]
     for gg, pp in bad:
         with pytest.raises(B.SpfcError) as ei:

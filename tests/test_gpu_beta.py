@@ -1,0 +1,146 @@
+"""The quartic term (beta/4) phi^4 (the standard PFC energy's term, Section 1, eq. energy-PFC)
+on the GPU path, against the oracle with the same beta.
+
+The real-space pass carries phi's own rows beside the gradient (two rows per workgroup
+group in 2-D as well), adds (beta/4) phi^4 to the E_1 partials and F(beta phi^3) to the x
+flux field.  Covered: 2-D and 3-D trajectories (FP64 to the trajectory bounds, FP32 to the
+report bounds), the ghost and copy start-ups (the ghost start evaluates N(phi^0) with the
+cubic term), the initial energies, every load and store path of the pass (lines within one
+wave and 1024-point lines, the tiled 3-D stores of 4 values per thread and the pair stores
+of 8), and a batch whose members mix beta = 0 and beta > 0.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from conftest import error_report
+from oracle import spfc_oracle as O
+from paper_2012_15133_amd.inputs import noise_ic
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(n, L, phi0, eps, **kw):
+    from paper_2012_15133_amd import Solver
+    return Solver(n, L, phi0, eps, **kw)
+
+
+def _smooth(g, mean, seed, amp=0.05, mmax=3):
+    rng = np.random.default_rng(seed)
+    axes = [np.arange(n) * h for n, h in zip(g.n, g.h)]
+    mesh = [np.transpose(c) for c in np.meshgrid(*axes, indexing="ij")]
+    phi = np.full(g.shape, float(mean))
+    for _ in range(6):
+        th = sum(2 * np.pi * int(rng.integers(-mmax, mmax + 1)) / Lj * xj for Lj, xj in zip(g.L, mesh))
+        phi += amp * rng.uniform(-1, 1) * np.cos(th + rng.uniform(0, 2 * np.pi))
+    return phi
+
+
+def _compare(n, L, beta, dt, steps, seed, mean, precision="fp64", startup="sav1", smooth=False, eps=0.25,
+             tol_phi=1e-11, tol_e=1e-12, name=None):
+    g = O.Grid(n, L)
+    prm = O.Params(eps, beta=beta)
+    phi0 = _smooth(g, mean, seed) if smooth else noise_ic(g.shape, mean, seed)
+    ref = O.run(g, prm, phi0, dt, steps, startup=startup)
+    s = _solver(n, L, phi0, eps, beta=beta, precision=precision, startup=startup, history=steps + 1)
+    s.step(dt, steps)
+    hist = s.history(0, steps + 1)
+    phi = s.phi().cpu().numpy()
+    flags = s.status()
+    s.close()
+    linf = float(np.max(np.abs(phi - ref["phi"])) / np.max(np.abs(ref["phi"])))
+    e_err = max(abs(h["energy"] - r["energy"]) / r["energy"] for h, r in zip(hist, ref["records"]))
+    r_err = max(abs(h["r"] - r["r"]) / r["r"] for h, r in zip(hist, ref["records"]))
+    m_err = max(abs(h["mean"] - r["mean"]) for h, r in zip(hist, ref["records"]))
+    if name:
+        error_report(name, rel_linf=linf, energy_rel=e_err)
+    assert linf <= tol_phi, (n, precision, linf)
+    assert e_err <= tol_e and r_err <= tol_e, (n, precision, e_err, r_err)
+    assert m_err <= (1e-13 if precision == "fp64" else 1e-6), m_err
+    assert flags & (~8 if precision == "fp32" else ~0) == 0, flags
+    # the modified energy does not rise (Theorem 3.1 holds for any E_1 >= |Omega|)
+    if precision == "fp64":
+        e = [h["energy"] for h in hist]
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:]))
+    return ref
+
+
+@pytest.mark.parametrize("n,L,beta,steps", [((64, 64), (8 * math.pi,) * 2, 1.0, 100),
+                                             ((64, 16), (8 * math.pi, 2 * math.pi), 0.5, 40),
+                                             ((1024, 16), (128 * math.pi, 2 * math.pi), 2.0, 10)])
+def test_beta_2d_trajectory_fp64(n, L, beta, steps):
+    _compare(n, L, beta, 0.01, steps, 41, -0.2, name=f"beta {beta} {n} fp64, {steps} steps")
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 8)])
+def test_beta_3d_trajectory_fp64(n):
+    L = tuple(v * math.pi / 8 for v in n)
+    _compare(n, L, 1.5, 0.005, 20, 42, -0.25, name=f"beta 1.5 {n} fp64, 20 steps")
+
+
+@pytest.mark.parametrize("n,L,dt,steps", [((64, 64), (8 * math.pi,) * 2, 0.01, 100),
+                                          ((32, 32, 32), (4 * math.pi,) * 3, 0.005, 20)])
+def test_beta_fp32_error_report(n, L, dt, steps):
+    _compare(n, L, 1.0, dt, steps, 43, -0.2, precision="fp32", tol_phi=1e-3, tol_e=1e-5,
+             name=f"beta 1.0 {n} fp32, {steps} steps")
+
+
+@pytest.mark.parametrize("startup", ["ghost", "copy"])
+def test_beta_startups(startup):
+    _compare((32, 32), (4 * math.pi,) * 2, 1.0, 0.02, 30, 44, -0.1, startup=startup, smooth=True)
+
+
+@pytest.mark.parametrize("plan", ["", "inv=8/256,mid=8/256,real=4/256,fwd=8/256",
+                                  "real=8/256", "real=16/128", "real=4/128"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_beta_thin_256_axis_plans(monkeypatch, plan, precision):
+    """x-axis 256 points: the real-space pass at the 256^3 run's line length, with the tiled
+    stores (4 values per thread) and the pair stores (8, 16)."""
+    if plan:
+        monkeypatch.setenv("SPFC_PLAN", plan)
+    n = (256, 16, 16)
+    L = tuple(v * math.pi / 8 for v in n)
+    tol = (1e-11, 1e-12) if precision == "fp64" else (1e-3, 1e-5)
+    _compare(n, L, 1.0, 0.005, 10, 45, -0.25, precision=precision, tol_phi=tol[0], tol_e=tol[1])
+
+
+@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16)])
+def test_beta_initial_energies(n):
+    L = tuple(2 * math.pi * v / 8 for v in n)
+    g = O.Grid(n, L)
+    prm = O.Params(0.25, beta=1.3)
+    phi0 = noise_ic(g.shape, -0.2, 46) + 0.3
+    s = _solver(n, L, phi0, 0.25, beta=1.3)
+    e = s.energy()
+    s.close()
+    E1 = O.E1(g, prm, phi0)
+    assert abs(e["E1"] - E1) <= 1e-13 * E1
+    EN = O.E_N(g, prm, phi0)
+    assert abs(e["energy"] - EN) <= 1e-12 * (abs(EN) + g.volume)
+    assert abs(e["r"] - math.sqrt(E1)) <= 1e-13 * math.sqrt(E1)
+
+
+def test_beta_batch_members_mix():
+    """A class with beta = 0 and beta > 0 members runs the kernels with phi's rows; each member
+    matches its single run to rounding and the oracle to the trajectory bounds."""
+    from paper_2012_15133_amd import Batch
+    n, L, dt, steps = (64, 64), (8 * math.pi,) * 2, 0.01, 40
+    g = O.Grid(n, L)
+    betas = [0.0, 1.0, 0.3]
+    members = [{"n": n, "L": L, "epsilon": 0.25, "beta": b, "phi0": noise_ic(g.shape, -0.2, 50 + k)}
+               for k, b in enumerate(betas)]
+    bt = Batch(members, history=steps + 1)
+    bt.step(dt, steps)
+    for k, m in enumerate(members):
+        got = bt.phi(k).cpu().numpy()
+        ref = O.run(g, O.Params(0.25, beta=m["beta"]), m["phi0"], dt, steps, energies=False)["phi"]
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= 1e-11, k
+        s = _solver(n, L, m["phi0"], 0.25, beta=m["beta"], history=steps + 1)
+        s.step(dt, steps)
+        single = s.phi().cpu().numpy()
+        s.close()
+        assert np.max(np.abs(got - single)) / np.max(np.abs(single)) <= 1e-13, k
+        assert bt.status(k) == 0
+    bt.close()
