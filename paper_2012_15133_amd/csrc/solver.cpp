@@ -276,12 +276,19 @@ struct spfc_ctx {
     int lineB() const { return sz.dim == 2 ? sz.nxh : sz.ny; }
 };
 
-// A batch: one context per (grid size, precision) class of members.
+// A batch: one context per (grid size, precision) class of members.  With several
+// classes each steps on a stream of its own (default priority), forked from the batch's
+// stream at the start of spfc_batch_step and joined back at its end, so that the classes'
+// kernels overlap on the device; every other call runs the classes on the batch's stream.
 struct spfc_batch {
     std::vector<spfc_ctx*> cls;
     std::vector<std::pair<int, int>> where;  // member -> (class, index within the class)
     std::vector<std::vector<int>> members;   // class -> member indices
     std::vector<size_t> npts;                // member -> grid points
+    hipStream_t stream = nullptr;            // the caller's stream
+    std::vector<hipStream_t> cstream;        // one per class (several classes only)
+    std::vector<hipEvent_t> join;            // one per class
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -1654,6 +1661,23 @@ int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params
         b->cls.push_back(ctx);
         b->members.push_back(idx);
     }
+    b->stream = stream;
+    const char* serial = std::getenv("SPFC_BATCH_SERIAL");   // 1: classes one after another (for A/B timing)
+    if (b->cls.size() > 1 && !(serial && serial[0] == '1')) {
+        bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+        for (size_t c = 0; ok && c < b->cls.size(); ++c) {
+            hipStream_t s = nullptr;
+            hipEvent_t e = nullptr;
+            ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+            if (ok) b->cstream.push_back(s);
+            ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+            if (ok) b->join.push_back(e);
+        }
+        if (!ok) {
+            spfc_batch_destroy(b);
+            return SPFC_E_DEVICE;
+        }
+    }
     *out = b;
     return SPFC_OK;
 }
@@ -1668,11 +1692,30 @@ int spfc_batch_step(spfc_batch* b, double dt, int64_t n) {
     const TraceRange trace_("spfc_batch_step");
     if (!b) return SPFC_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return SPFC_E_INVAL;
-    for (auto* c : b->cls) {
-        const int rc = ctx_step(c, dt, n);
-        if (rc) return rc;
+    if (b->cstream.empty() || n == 0) {
+        for (auto* c : b->cls) {
+            const int rc = ctx_step(c, dt, n);
+            if (rc) return rc;
+        }
+        return SPFC_OK;
     }
-    return SPFC_OK;
+    // fork: every class stream waits for what the caller queued before this call
+    if (hipEventRecord(b->fork, b->stream) != hipSuccess) return SPFC_E_DEVICE;
+    int rc = SPFC_OK;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        if (hipStreamWaitEvent(b->cstream[c], b->fork, 0) != hipSuccess) rc = SPFC_E_DEVICE;
+        b->cls[c]->stream = b->cstream[c];
+    }
+    for (size_t c = 0; c < b->cls.size() && rc == SPFC_OK; ++c) rc = ctx_step(b->cls[c], dt, n);
+    // join: the caller's stream waits for every class (also after an error, so that no
+    // class work is left behind the caller's back)
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        if (hipEventRecord(b->join[c], b->cstream[c]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->join[c], 0) != hipSuccess)
+            rc = SPFC_E_DEVICE;
+        b->cls[c]->stream = b->stream;
+    }
+    return rc;
 }
 
 int spfc_batch_step_count(spfc_batch* b, int64_t* n) {
@@ -1867,6 +1910,12 @@ int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out) {
 int spfc_batch_destroy(spfc_batch* b) {
     if (!b) return SPFC_E_INVAL;
     for (auto* c : b->cls) free_ctx(c);
+    for (auto s : b->cstream) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (auto e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return SPFC_OK;
 }
