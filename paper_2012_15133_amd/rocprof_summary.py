@@ -49,14 +49,21 @@ def _counter_means(d: str, with_counts: bool = False):
     return means
 
 
+def _targs(name: str):
+    """Template arguments of a kernel name, e.g. ['float', '256', '4', '3', 'true', 'false']."""
+    if "<" not in name:
+        return []
+    return [x.strip() for x in name.split("<", 1)[1].split(">")[0].split(",")]
+
+
 def _role(name: str):
     for k, v in ROLE.items():
         if k + "<" in name or k + "(" in name:
-            if k == "k_real_pass" and ", false>" in name:
+            if k == "k_real_pass" and _targs(name)[4] == "false":   # the E_1-only pass of queries
                 return None
             return v
-    if "k_pass<" in name and ", 3>" in name:
-        return "pass_y_inv" if ", 1, 1, 3>" in name else "pass_y_fwd"
+    if "k_ypass<" in name:
+        return "pass_y_inv" if _targs(name)[3] == "1" else "pass_y_fwd"
     return None
 
 
@@ -79,8 +86,7 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, workload, 
     copy_w = max(v for (k, c), v in cwr.items() if c == "WRITE_SIZE" and "copyBuffer" in k)
     kib = copy_bytes / 1024.0
     sf, sw = kib / copy_f, kib / copy_w
-    alg = {"spec_inv": (4 + dim) * F, "real_pass": 2 * dim * F, "spec_fwd": (3 + dim) * F,
-           "pass_y_inv": 6 * F, "pass_y_fwd": 6 * F}
+    alg = {"spec_inv": 6 * F, "real_pass": 2 * dim * F, "spec_fwd": 5 * F, "pass_y_inv": 5 * F, "pass_y_fwd": 5 * F}
     h = kernel_source_hash()
     # per role, the launch-plan variant with the most dispatches (the one the run used after
     # tuning; the tuner's trial variants appear a few times each)
@@ -110,7 +116,7 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, workload, 
     return summary
 
 
-STEP_KERNELS = ("k_spec_inv", "k_real_pass", "k_spec_fwd", "k_pass")
+STEP_KERNELS = ("k_spec_inv", "k_real_pass", "k_spec_fwd", "k_ypass")
 
 
 def counters(c1: str, c2: str, label: str):
@@ -125,7 +131,7 @@ def counters(c1: str, c2: str, label: str):
                 name = row["Kernel_Name"]
                 if not any(x in name for x in STEP_KERNELS):
                     continue
-                if "k_real_pass" in name and name.split(",")[-1].strip().startswith("false"):
+                if "k_real_pass" in name and _targs(name)[4] == "false":
                     continue
                 agg[name][row["Counter_Name"]] += float(row["Counter_Value"])
                 disp[(name, k)].add(row["Dispatch_Id"])
@@ -137,8 +143,8 @@ def counters(c1: str, c2: str, label: str):
             continue
         role = name.split("<")[0].replace("void spfc::", "")
         tmpl = [x.strip() for x in name.split("<")[1].split(">")[0].split(",")]
-        if role == "k_pass":
-            role += " (y, " + ("inverse" if tmpl[3] == "1" else "forward") + ")"
+        if role == "k_ypass":
+            role += " (" + ("inverse" if tmpl[3] == "1" else "forward") + ")"
         rows.append(f"| {label} | `{role}` | {tmpl[2]} | {c['SQ_WAVES'] / n2:.0f} | "
                     f"{c['SQ_WAVE_CYCLES'] / n1 / 1e6:.2f}M | {c['SQ_WAIT_ANY'] / n1 / 1e6:.2f}M | "
                     f"{c['SQ_WAIT_INST_LDS'] / n1 / 1e6:.2f}M | {c['SQ_INSTS_VALU'] / n2 / 1e6:.2f}M | "
