@@ -706,6 +706,48 @@ __device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int 
     }
 }
 
+// load_packed_once for lines that span several waves (P > 64): the entries each thread
+// loads (t + P m for m < E/2, and the self-conjugate bin N/2) are staged in the group's line
+// buffer, stage[0 .. N/2] (H1, with KX times i kappa1_x) and stage[N/2 + 1 .. N + 1] (H2),
+// and each thread reads the entries N - e of its mirrored elements from there.  The buffer
+// must hold N + 2 entries and be free; all threads of the workgroup must call it (barrier).
+// The next write to the buffer must follow a barrier (fft_run's second pass has one).
+template <typename T, typename PL, bool KX>
+__device__ inline void load_packed_staged(const cpx<T>* h1, const cpx<T>* h2, int t, cpx<T> (&w)[PL::E], double k0,
+                                          cpx<T>* stage, bool act) {
+    constexpr int E = PL::E, P = PL::P, N = PL::Nl, H = E / 2, NXH = N / 2 + 1;
+    static_assert(N + 2 <= LdsLine<N>::size, "staging needs N + 2 entries of the line buffer");
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        const int e = t + P * m;
+        cpx<T> a = h1[e], b = h2[e];
+        if constexpr (KX) a = mul_ikx(a, e, N, k0);
+        if (e == 0) {
+            a.y = T(0);
+            b.y = T(0);
+        }
+        stage[e] = a;
+        stage[NXH + e] = b;
+        w[m] = mk<T>(a.x - b.y, a.y + b.x);
+    }
+    if (t == 0) {
+        cpx<T> a = h1[N / 2], b = h2[N / 2];
+        stage[N / 2] = KX ? mk<T>(T(0), T(0)) : mk<T>(a.x, T(0));
+        stage[NXH + N / 2] = mk<T>(b.x, T(0));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = H; m < E; ++m) {
+        const int e = t + P * m, k = N - e;   // e >= N/2; k = N/2 only for t = 0, m = H
+        const cpx<T> a = stage[k], b = stage[NXH + k];
+        w[m] = e == N / 2 ? mk<T>(a.x, b.x) : mk<T>(a.x + b.y, b.x - a.y);   // conj H1 + i conj H2
+    }
+    if (!act) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) w[m] = mk<T>(T(0), T(0));
+    }
+}
+
 // Two neighbouring complex values in one store (dst aligned to twice the element).
 template <typename T>
 __device__ inline void store_pair(cpx<T>* dst, cpx<T> a, cpx<T> b) {
@@ -757,11 +799,10 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                 for (int m = 0; m < E; ++m) v[c][m] = mk<T>(0, 0);
             }
         } else {
-#pragma unroll
-            for (int m = 0; m < E; ++m)
-                v[c][m] = !act ? mk<T>(0, 0)
-                               : PK::kx(c) ? load_packed<T, NX, true>(h1, h2, t + P * m, geo.k0x)
-                                           : load_packed<T, NX, false>(h1, h2, t + P * m, 0.0);
+            // the group's line buffer c is free until the transform
+            cpx<T>* stage = lds + c * LdsLine<NX>::size;
+            if (PK::kx(c)) load_packed_staged<T, PL, true>(h1, h2, t, v[c], geo.k0x, stage, act);
+            else load_packed_staged<T, PL, false>(h1, h2, t, v[c], 0.0, stage, act);
         }
     }
     issue_barrier();
