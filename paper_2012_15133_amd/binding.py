@@ -666,8 +666,8 @@ class Batch:
         spfc_batch_reset(self.b, [d.data_ptr() for d in dev], r_shift)
         del dev
 
-    def energies(self):
-        return spfc_batch_energies(self.b, len(self.ns))
+    def energies(self, allow_nonfinite=False):
+        return spfc_batch_energies(self.b, len(self.ns), allow_nonfinite)
 
     def phi_all(self, out):
         """Every member's field into out[m] (float32 or float64 device tensor of shape

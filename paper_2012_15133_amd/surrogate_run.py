@@ -118,15 +118,19 @@ class Jumper:
         self.pred.copy_(self.net.forward(self.phi, self.eps))
         shift = [p["r"] - math.sqrt(p["E1"]) for p in before]
         after = None
-        try:
-            self.spare.reset(self.pred, shift)
-        except SpfcError as e:
-            if e.status != SPFC_E_INVAL:
-                raise
-            ok = False       # a shifted r not positive: no jump
+        if not bool(self.torch.isfinite(self.pred).all()):
+            ok = False       # a non-finite prediction: no jump (its E_1 could overflow to inf, r = inf)
         else:
-            after = self.spare.energies()
-            ok = self.decide(before, after)
+            try:
+                self.spare.reset(self.pred, shift)
+            except SpfcError as e:
+                if e.status != SPFC_E_INVAL:
+                    raise
+                ok = False       # a shifted r not positive: no jump
+            else:
+                # energies of every member even where one is not finite (decide() rejects those)
+                after = self.spare.energies(allow_nonfinite=True)
+                ok = self.decide(before, after)
         if ok:
             self.accepted += 1
             self.b, self.spare = self.spare, self.b

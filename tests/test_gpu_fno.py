@@ -77,8 +77,9 @@ def _well_conditioned_batch(b, seed):
 
 
 def test_gradients_match_oracle():
-    """Each block of the gradient within max(2e-2, 1.5 x the change bf16 rounding itself
-    makes to the oracle's gradient of that block) of the bf16 oracle; the loss to 1e-3."""
+    """Each block of the gradient within half the change bf16 rounding itself makes to the
+    oracle's gradient of that block, or within 2e-2 (unit-variance inputs; the reading of
+    the n = 256 tests below), of the bf16 oracle; the loss to 1e-3."""
     from paper_2012_15133_amd.surrogate import Surrogate, unflatten
     p = _params(3)
     phi, eps, tgt = _well_conditioned_batch(2, 4)
@@ -95,7 +96,7 @@ def test_gradients_match_oracle():
             continue
         e, sens = _rel(gg[k], r), _rel(ref64[k], r)
         print(f"  grad {k:5s} rel L2 {e:.2e}  (bf16 vs float64 oracle {sens:.2e})")
-        assert e <= max(2e-2, 1.5 * sens), k
+        assert e <= 0.5 * sens or e <= 2e-2, k
     a = torch.cat([gg[k].reshape(-1) for k in ref if k != "q2"])
     b = torch.cat([ref[k].reshape(-1) for k in ref if k != "q2"])
     cos = float(torch.dot(a, b) / (torch.linalg.norm(a) * torch.linalg.norm(b)))

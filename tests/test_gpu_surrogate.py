@@ -113,3 +113,38 @@ def test_jumps_are_accepted_accurate_and_faster(trained):
     print(f"50 plain steps {t_plain * 1e3:.2f} ms, one jump {t_jump * 1e3:.2f} ms (wall)")
     assert t_jump < t_plain
     net.close()
+
+
+class _BadNet:
+    """A stand-in network whose prediction is not finite (overflow or NaN in its output)."""
+
+    def __init__(self, value):
+        self.value = value
+
+    def forward(self, phi, eps):
+        # float64, so that a huge finite value stays finite and E_1 itself overflows
+        out = torch.full(phi.shape, self.value, dtype=torch.float64, device=phi.device)
+        out[:, 0, 0] = -self.value
+        return out
+
+
+@pytest.mark.parametrize("value", [float("inf"), float("nan"), 1e200])
+def test_nonfinite_or_overflowing_prediction_is_a_rejected_jump(value):
+    """A prediction that is not finite, or whose E_1 overflows, is rejected like any other
+    failed jump: the run takes the plain steps and stays bit for bit on the plain path."""
+    from paper_2012_15133_amd import Batch
+    from paper_2012_15133_amd import surrogate_run as R
+    test = R.members(6, seed=78)
+    eps = torch.tensor([m["epsilon"] for m in test], dtype=torch.float32, device="cuda")
+    b, plain = Batch(test, history=16), Batch(test, history=16)
+    for x in (b, plain):
+        x.step(R.DT, 20)
+    J = R.Jumper(b, Batch(test, history=16), _BadNet(value), eps)
+    assert not J.jump()
+    plain.step(R.DT, R.JUMP)
+    assert J.rejected == 1 and J.accepted == 0 and J.b is b
+    for m in range(6):
+        assert torch.equal(J.b.phi(m), plain.phi(m))
+        assert J.b.status(m) == 0
+    for x in (J.b, J.spare, plain):
+        x.close()
