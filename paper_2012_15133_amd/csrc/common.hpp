@@ -57,12 +57,15 @@ enum : unsigned int {
 
 // Partial sums per workgroup (FP64):
 //   P (forward pass): p1, p2, p_psi                                   3 per workgroup
+//                     When a separate kernel closes the step (k_finalize), a fourth: the
+//                     sum of a fixed slice of the real-space pass's E_1 partials
+//                     (workgroup w of W takes B[w nB / W, (w+1) nB / W))  4 per workgroup
 //   E (forward pass): ||L^1/2 X||^2, ||L^1/2 (2X - Y)||^2, ||X||^2,
 //                     ||Delta X||^2, Re X(0) (only the owner adds it),
 //                     <X - Y, -Delta_N (X - Y)>                         6 per workgroup
 //   B (real-space pass): E_1 density sum                              1 per workgroup
 //   Q (update / query passes): the same five as E for the pair they form
-constexpr int NPART_P = 3, NPART_E = 6;
+constexpr int NPART_P = 3, NPART_PF = 4, NPART_E = 6;
 
 // What a launch needs to finish the previous step (the SAV scalar) itself.  All
 // arrays are those of member 0; member m's part starts m * (count per member)
@@ -143,6 +146,8 @@ struct SpecFwdArgs {
     double a0, a1, a2, dt, e1, e2;
     double* partP;          // NPART_P per workgroup
     double* partE;          // NPART_E per workgroup
+    const double* partB;    // FOLD: the real-space pass's E_1 partials (nB per member), folded
+    int nB;                 // into partP (NPART_PF per workgroup)
     size_t fs;
     const Geo* geos;
     const cpx<T>* fhat;     // SOLVE_FORCED: forcing spectrum f^{n+1} of this step

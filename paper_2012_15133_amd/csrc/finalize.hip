@@ -15,13 +15,15 @@ __global__ void __launch_bounds__(1024) k_finalize(FinalizeArgs p) {
     const Geo geo = p.geos[mem];
     if (p.mode == FIN_STEP) {
         const FinishIn fi = member_fin(p.fi, mem);
-        double sBPE[1 + NPART_P + NPART_E];
-        block_sum_trio<1, NPART_P, NPART_E>(fi.partB, fi.nB, fi.partP, fi.nPE, fi.partE, fi.nPE, sBPE);
+        // the forward pass folded the real-space partials into its own (NPART_PF per
+        // workgroup: p1, p2, p_psi, the E_1 slice); E: the energy norms
+        double sPE[NPART_PF + NPART_E];
+        block_sum_pair<NPART_PF, NPART_E>(fi.partP, fi.nPE, fi.partE, fi.nPE, sPE);
         if (threadIdx.x == 0) {
-            const double sP[NPART_P] = {sBPE[1], sBPE[2], sBPE[3]};
+            const double sP[NPART_P] = {sPE[0], sPE[1], sPE[2]};
             double sE[NPART_E];
-            for (int i = 0; i < NPART_E; ++i) sE[i] = sBPE[1 + NPART_P + i];
-            finish_step(fi, sBPE[0], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
+            for (int i = 0; i < NPART_E; ++i) sE[i] = sPE[NPART_PF + i];
+            finish_step(fi, sPE[3], sE, sP, p.a0, p.a1, p.a2, p.dt, geo);
         }
         return;
     }

@@ -2,6 +2,6 @@
 #include "kern_impl.hpp"
 
 namespace spfc {
-template hipError_t Kern<double>::spec_fwd(int, int, int, bool, const SpecFwdArgs<double>&, const LaunchShape&,
+template hipError_t Kern<double>::spec_fwd(int, int, int, bool, bool, const SpecFwdArgs<double>&, const LaunchShape&,
                                           hipStream_t);
 }  // namespace spfc

@@ -78,24 +78,31 @@ hipError_t Kern<T>::real_pass(int nx, int dim, bool fwd, bool beta, const RealAr
 }
 
 template <typename T>
-hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwdArgs<T>& a, const LaunchShape& s,
-                             hipStream_t st) {
+hipError_t Kern<T>::spec_fwd(int nl, int dim, int mode, bool stab, bool fold, const SpecFwdArgs<T>& a,
+                             const LaunchShape& s, hipStream_t st) {
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
         const dim3 g(s.grid, s.members), b(s.block);
+#define SPFC_FWD(D, M, S, F) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, D, M, S, F>), g, b, s.shmem, st, a)
+#define SPFC_FWD_DIM(D)                                                                    \
+    if (mode == FWD_GHOST) SPFC_FWD(D, FWD_GHOST, false, false);                           \
+    else if (mode == FWD_SOLVE_FORCED) {                                                   \
+        if (fold) SPFC_FWD(D, FWD_SOLVE_FORCED, false, true);                              \
+        else SPFC_FWD(D, FWD_SOLVE_FORCED, false, false);                                  \
+    } else if (stab) {                                                                     \
+        if (fold) SPFC_FWD(D, FWD_SOLVE, true, true);                                      \
+        else SPFC_FWD(D, FWD_SOLVE, true, false);                                          \
+    } else {                                                                               \
+        if (fold) SPFC_FWD(D, FWD_SOLVE, false, true);                                     \
+        else SPFC_FWD(D, FWD_SOLVE, false, false);                                         \
+    }
         if (dim == 2) {
-            if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_GHOST, false>), g, b, s.shmem, st, a);
-            else if (mode == FWD_SOLVE_FORCED)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE_FORCED, false>), g, b, s.shmem, st, a);
-            else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, true>), g, b, s.shmem, st, a);
-            else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 2, FWD_SOLVE, false>), g, b, s.shmem, st, a);
+            SPFC_FWD_DIM(2)
         } else {
-            if (mode == FWD_GHOST) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_GHOST, false>), g, b, s.shmem, st, a);
-            else if (mode == FWD_SOLVE_FORCED)
-                hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE_FORCED, false>), g, b, s.shmem, st, a);
-            else if (stab) hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, true>), g, b, s.shmem, st, a);
-            else hipLaunchKernelGGL((k_spec_fwd<T, NN, EE, 3, FWD_SOLVE, false>), g, b, s.shmem, st, a);
+            SPFC_FWD_DIM(3)
         }
+#undef SPFC_FWD_DIM
+#undef SPFC_FWD
         return hipGetLastError();
     });
 }

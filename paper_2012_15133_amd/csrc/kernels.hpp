@@ -389,7 +389,7 @@ __device__ inline void finish_step(const FinishIn& fi, double E1sum, const doubl
 // FinishIn narrowed to member m of the batch.
 __device__ inline FinishIn member_fin(const FinishIn& f, int m) {
     FinishIn r = f;
-    r.partP = f.partP + (size_t)m * f.nPE * NPART_P;
+    r.partP = f.partP + (size_t)m * f.nPE * (f.nB > 0 ? NPART_P : NPART_PF);   // folded layout when nB = 0
     r.partE = f.partE + (size_t)m * f.nPE * NPART_E;
     r.partB = f.partB + (size_t)m * f.nB;
     r.sc_in = f.sc_in + m;
@@ -1128,7 +1128,9 @@ __global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
 // kernel forms the partial sums of p1, p2 and p_psi.
 // Stabilized scheme: A gains stab dt^2 |k|^4 and b2 = A^-1 (psi + stab dt^2 |k|^4 phi^n);
 // the r equation, and so p_psi, keeps psi.
-template <typename T, int NL, int EE, int DIM, int MODE, bool STAB>
+// FOLD (the step is closed by a separate kernel): each workgroup also adds its slice of the
+// real-space pass's E_1 partials and stores NPART_PF partials (else NPART_P).
+template <typename T, int NL, int EE, int DIM, int MODE, bool STAB, bool FOLD>
 __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     using PL = Plan<NL, EE>;
     constexpr int E = PL::E, P = PL::P, C = 2;
@@ -1147,6 +1149,18 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     // runs (lanes past the last line load line 0 of the member; nothing of theirs
     // reaches an output).  2-D: after it; there the early loads compete with the flux
     // loads the transform waits for and the step is slower (measured on 1024^2).
+    // this workgroup's fixed slice [bj0, bj1) of the real-space pass's E_1 partials: the
+    // first entry of each thread loaded ahead of everything (branch free: an index past the
+    // slice reads entry 0 and adds nothing), so that waiting for the field loads covers it
+    int bj = 0, bj1 = 0;
+    double bval = 0.0;
+    if constexpr (MODE != FWD_GHOST && FOLD) {
+        const int bj0 = (int)((long long)p.nB * blockIdx.x / gridDim.x);
+        bj1 = (int)((long long)p.nB * (blockIdx.x + 1) / gridDim.x);
+        bj = bj0 + (int)threadIdx.x;
+        bval = p.partB[(size_t)mem * p.nB + (bj < bj1 ? bj : 0)];
+        issue_barrier();
+    }
     cpx<T> v[C][E], Xs[E], Ys[E];
     auto load_pair = [&](bool all) {
 #pragma unroll
@@ -1168,8 +1182,14 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     fft_run<T, PL, -1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
     if constexpr (DIM == 2) load_pair(false);
 
-    double acc[NPART_P] = {0.0, 0.0, 0.0};
+    double acc[NPART_PF] = {0.0, 0.0, 0.0, 0.0};
     double accE[NPART_E] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (MODE != FWD_GHOST && FOLD) {
+        // the rest of this workgroup's slice of the real-space partials (when it is longer
+        // than the workgroup), then the entries loaded first
+        for (int j = bj + (int)blockDim.x; j < bj1; j += (int)blockDim.x) acc[3] += p.partB[(size_t)mem * p.nB + j];
+        acc[3] += bj < bj1 ? bval : 0.0;
+    }
     if (act) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -1209,7 +1229,12 @@ __global__ void __launch_bounds__(256) k_spec_fwd(SpecFwdArgs<T> p) {
     }
     if constexpr (MODE != FWD_GHOST) {
         const size_t wg = (size_t)mem * gridDim.x + blockIdx.x;
-        block_sum_store<NPART_P>(acc, p.partP + NPART_P * wg);
+        if constexpr (FOLD) {
+            block_sum_store<NPART_PF>(acc, p.partP + NPART_PF * wg);
+        } else {
+            double a3[NPART_P] = {acc[0], acc[1], acc[2]};
+            block_sum_store<NPART_P>(a3, p.partP + NPART_P * wg);
+        }
         store_energy_partials<STAB>(accE, p.partE + NPART_E * wg);
     }
 }

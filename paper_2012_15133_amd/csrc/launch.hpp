@@ -54,7 +54,8 @@ struct Kern {
                                hipStream_t st);
     static hipError_t real_pass(int nx, int dim, bool fwd, bool beta, const RealArgs<T>& a, const LaunchShape& s,
                                 hipStream_t st);
-    static hipError_t spec_fwd(int nl, int dim, int mode, bool stab, const SpecFwdArgs<T>& a,
+    // fold: also sum the real-space pass's E_1 partials into the forward partials (NPART_PF)
+    static hipError_t spec_fwd(int nl, int dim, int mode, bool stab, bool fold, const SpecFwdArgs<T>& a,
                                const LaunchShape& s, hipStream_t st);
     static hipError_t pass(int nl, int dir, int omode, int c, const PassArgs<T>& a, const LaunchShape& s,
                            hipStream_t st);

@@ -151,7 +151,7 @@ Layout layout_of(const Sizes& s0, int64_t hist_cap, int M) {
     L.ntab = std::max(s.nx, std::max(s.ny, s.nz));
     L.off_tw = o; o += align_up((size_t)L.ntab * s.elem);
     const int nQ = std::max(h.A.grid, h.updGrid);
-    L.off_partP = o; o += align_up((size_t)M * h.Cf.grid * NPART_P * sizeof(double));
+    L.off_partP = o; o += align_up((size_t)M * h.Cf.grid * NPART_PF * sizeof(double));
     L.off_partE = o; o += align_up((size_t)M * h.Cf.grid * NPART_E * sizeof(double));
     L.off_partB = o; o += align_up((size_t)M * h.B.grid * sizeof(double));
     L.off_partQ = o; o += align_up((size_t)M * nQ * NPART_E * sizeof(double));
@@ -378,13 +378,15 @@ size_t device_lds_max() {
 
 // Launch plan of a context: shapes of the step kernels and whether each step is
 // closed inside the next update kernel.  That makes every workgroup of the update
-// kernel read its member's partial sums: worth it while that re-read is small.
+// kernel read its member's partial sums: worth it while that re-read is small (the
+// update-and-inverse kernel's workgroups each step; the elementwise update that ends a
+// call re-reads them once per call).
 void set_plan(spfc_ctx* ctx, const TunePlan& tp) {
     drop_graph(ctx);
     ctx->plan = tp;
     ctx->sh = shapes_of(ctx->sz, ctx->M, tp);
     const Shapes& h = ctx->sh;
-    const double reread = (double)ctx->M * std::max(h.A.grid, h.updGrid) * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
+    const double reread = (double)ctx->M * h.A.grid * (h.B.grid + NPART_P * h.Cf.grid) * 8.0;
     ctx->fin_in = tp.fin_in_kernel != 0 && reread <= 48.0e6;
 }
 
@@ -412,8 +414,10 @@ struct Pipe {
         f.partP = ctx->partP();
         f.partE = ctx->partE();
         f.nPE = ctx->sh.Cf.grid;
+        // the real-space partials are read by the close itself inside the next kernel, and
+        // folded into the forward pass's partials when a separate kernel closes the step
         f.partB = ctx->partB();
-        f.nB = ctx->sh.B.grid;
+        f.nB = ctx->fin_in ? ctx->sh.B.grid : 0;
         f.sc_in = ctx->scb(ctx->cur_sc);
         f.sc_out = ctx->scb(1 - ctx->cur_sc);
         f.hist = ctx->hist();
@@ -525,11 +529,13 @@ struct Pipe {
         a.e2 = e2;
         a.partP = ctx->partP();
         a.partE = ctx->partE();
+        a.partB = ctx->partB();
+        a.nB = ctx->fin_in ? 0 : ctx->sh.B.grid;
         a.fs = ctx->lay.fs;
         a.geos = ctx->dgeos();
         Timed tm(ctx, R_SPEC_FWD, timed);
         for (int r = 0; r < tm.reps(); ++r)
-            CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, ctx->stab, a, ctx->sh.Cf, ctx->stream));
+            CK(Kern<T>::spec_fwd(ctx->nl(), ctx->sz.dim, mode, ctx->stab, a.nB > 0, a, ctx->sh.Cf, ctx->stream));
         return SPFC_OK;
     }
 
