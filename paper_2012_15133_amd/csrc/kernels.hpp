@@ -4,7 +4,8 @@
 // Spectral state: the half spectrum (x wavenumbers 0..nx/2) stored [kx][ky]
 // (2-D) or [kx][ky][kz] (3-D), last axis contiguous.  One step is
 //   2-D: spec_inv (along y) -> real_pass (along x) -> spec_fwd (along y)
-//   3-D: spec_inv (z) -> pass (y) -> real_pass (x) -> pass (y) -> spec_fwd (z)
+//   3-D: spec_inv (z) -> ypass (y) -> real_pass (x) -> ypass (y) -> spec_fwd (z)
+// Each symbol is applied by the pass along whose lines it is constant.
 // Every kernel reads whole lines along the contiguous axis of its input and
 // writes its output with the axes rotated so that the next kernel again reads
 // contiguous lines.  Nothing but the state, N and the transform
@@ -192,37 +193,6 @@ __device__ inline void block_sum_pair(const double* a, int na, const double* b, 
     PairSweep<NA, NB> first;
     first.load(a, na, b, nb, threadIdx.x);
     block_sum_pair_from<NA, NB>(first, a, na, b, nb, out);
-}
-
-// Three arrays of per-workgroup partials in one sweep (as block_sum_pair), result
-// NA + NB + NC sums in every thread.
-template <int NA, int NB, int NC>
-__device__ inline void block_sum_trio(const double* a, int na, const double* b, int nb, const double* c, int nc,
-                                      double (&out)[NA + NB + NC]) {
-    constexpr int U = 4, NV = NA + NB + NC;
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    int n = na > nb ? na : nb;
-    n = n > nc ? n : nc;
-    for (int j0 = threadIdx.x; j0 < n; j0 += U * blockDim.x) {
-        double v[U][NV];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int jj = j0 + q * blockDim.x;
-#pragma unroll
-            for (int i = 0; i < NA; ++i) v[q][i] = jj < na ? a[(size_t)jj * NA + i] : 0.0;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) v[q][NA + i] = jj < nb ? b[(size_t)jj * NB + i] : 0.0;
-#pragma unroll
-            for (int i = 0; i < NC; ++i) v[q][NA + NB + i] = jj < nc ? c[(size_t)jj * NC + i] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q)
-#pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] += v[q][i];
-    }
-    block_tree<NV>(acc, out);
 }
 
 template <int NV>
@@ -1013,21 +983,6 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
         for (int m = 0; m < E; ++m) v[c][m] = act ? p.in[c][mbase + lbase + t + P * m] : mk<T>(0, 0);
     stage_twiddles<T, PL>(ltw, p.tw, p.tws);
     fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
-    if constexpr (C == 3 && OMODE != OUT_KEEP) {
-        // the step's y passes: for each e the workgroup's lines are (mostly) neighbours
-        const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
-        tiled_line_store<T, PL, C>(v, lds, p.G, g, t, p.out, mbase, [&](int, int e, int gi) -> long long {
-            const int ln = line0 + gi;
-            if (ln >= p.nlines) return -1;
-            if constexpr (OMODE == OUT_SWAP) {
-                const int a = ln / p.B, b = ln - a * p.B;
-                return ((long long)a * NL + e) * p.B + b;
-            } else {
-                return (long long)e * p.nlines + ln;
-            }
-        });
-        return;
-    }
     if (!act) return;
     const int a = line / p.B, b = line - a * p.B;
 #pragma unroll
