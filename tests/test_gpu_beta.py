@@ -144,3 +144,22 @@ def test_beta_batch_members_mix():
         assert np.max(np.abs(got - single)) / np.max(np.abs(single)) <= 1e-13, k
         assert bt.status(k) == 0
     bt.close()
+
+
+def test_beta_with_the_stabilized_scheme():
+    """The quartic term together with the stabilization of the closing remarks of Section 5
+    (each variant of its own kernels): the oracle with both."""
+    n, L, dt, steps = (64, 64), (8 * math.pi,) * 2, 0.01, 40
+    g = O.Grid(n, L)
+    prm = O.Params(0.25, beta=1.0, stab=50.0)
+    phi0 = noise_ic(g.shape, -0.2, 47)
+    ref = O.run(g, prm, phi0, dt, steps)
+    s = _solver(n, L, phi0, 0.25, beta=1.0, stab=50.0, history=steps + 1)
+    s.step(dt, steps)
+    hist = s.history(0, steps + 1)
+    phi = s.phi().cpu().numpy()
+    assert s.status() == 0
+    s.close()
+    assert np.max(np.abs(phi - ref["phi"])) / np.max(np.abs(ref["phi"])) <= 1e-11
+    for h, r in zip(hist, ref["records"]):
+        assert abs(h["energy"] - r["energy"]) <= 1e-12 * r["energy"]
