@@ -270,7 +270,10 @@ int spfc_batch_workspace_bytes(int count, const spfc_grid* grids, const spfc_par
 int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params,
                     const double* const* phi0_dev, void* workspace_dev, size_t workspace_bytes,
                     void* hip_stream, spfc_batch** out);
-/* Advance every member n steps of size dt (as spfc_step; asynchronous). */
+/* Advance every member n steps of size dt (as spfc_step; asynchronous).  With several
+ * size classes each class steps on a stream of its own that waits for the work queued
+ * on the batch's stream before the call, and the batch's stream waits for every class
+ * at the end, so the caller sees the steps ordered on the batch's stream. */
 int spfc_batch_step(spfc_batch* b, double dt, int64_t n);
 /* Graph replay for every class (as spfc_set_graph). */
 int spfc_batch_set_graph(spfc_batch* b, int enable);
@@ -295,9 +298,12 @@ int spfc_batch_get_plan(spfc_batch* b, int member, int* plan8);
 int spfc_batch_time_kernels(spfc_batch* b, double dt, int reps, void* scratch_dev,
                             size_t scratch_bytes);
 /* Kernel timing as spfc_profile / spfc_kernel_times, summed over the classes: for
- * each step kernel, avg_ms is the sum over classes of its average launch time
- * (the time that kernel takes per step for the whole batch), bytes_per_launch the
- * algorithmic bytes of those launches together, launches the count per class. */
+ * each step kernel, avg_ms is the sum over classes of its average launch time,
+ * bytes_per_launch the algorithmic bytes of those launches together, launches the
+ * count per class.  In spfc_batch_step the classes of a batch with several grid
+ * sizes run on concurrent streams (forked from and joined to the batch's stream),
+ * so these sums can exceed the wall time of a step; spfc_batch_time_kernels times
+ * the classes one after another. */
 int spfc_batch_profile(spfc_batch* b, int enable);
 int spfc_batch_kernel_times(spfc_batch* b, int cap, const char** names, double* avg_ms,
                             int64_t* launches, double* bytes_per_launch, int* count);
