@@ -8,8 +8,9 @@
   can make for each kernel role, and with each step closed in a separate kernel
   (as 256^3 does).  Element by element, FP64 to the trajectory bounds (1e-11 on phi,
   1e-12 on the modified energy at every step), FP32 to the report bounds.
-* 1024^2 (side 128 pi, seed 2, dt 0.01) and 256^3 (side 32 pi, seed 3, dt 0.005)
-  against the oracle trajectories stored by tests/golden/make_golden.py: per-step
+* 1024^2 (side 128 pi, seed 2, dt 0.01, 2000 steps) and 256^3 (side 32 pi, seed 3,
+  dt 0.005, its first steps) against the oracle trajectories stored by
+  tests/golden/make_golden.py: per-step
   modified energy, mean and r, and phi^k on a sub-lattice, under the built-in plan and
   the plan the benchmark's tuner picks.  The 1024^2 run covers the full 2000 steps.
 
@@ -190,7 +191,7 @@ def test_c2_2000_steps_fp32_error_report(monkeypatch, plan):
 @pytest.mark.parametrize("plan", ["", PLAN_C3], ids=["builtin", "tuned"])
 def test_c3_first_steps_against_oracle(monkeypatch, plan, precision):
     phi_err, e_rel, r_rel, m_abs, flags, used = _against_golden(monkeypatch, "spfc3d_256_seed3.npz", precision, plan)
-    error_report(f"256^3 {precision} plan {used}, 3 steps",
+    error_report(f"256^3 {precision} plan {used}, {len(e_rel) - 1} steps",
                  rel_linf=max(phi_err.values()), energy_rel_max=float(e_rel.max()),
                  mean_abs_max=float(m_abs.max()))
     if precision == "fp64":
