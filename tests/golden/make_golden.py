@@ -4,7 +4,7 @@ Calls only the CPU oracle (oracle/spfc_oracle.py) and the seeded input generator
 (paper_2012_15133_amd/inputs.py, random numbers only).  Nothing here reads or runs
 the GPU path.
 
-  python tests/golden/make_golden.py --which c2   # 1024^2, 2000 steps (about 40 min, one core)
+  python tests/golden/make_golden.py --which c2   # 1024^2, 2000 steps (about three hours, one core)
   python tests/golden/make_golden.py --which c3   # 256^3, 3 steps (several minutes)
 
 Each file is an .npz holding, for the run it names:
