@@ -244,6 +244,7 @@ struct spfc_ctx {
     char* force_buf = nullptr;   // caller memory: the combined forcing spectrum, then its terms
     int force_terms = 0;
     std::vector<std::pair<std::tuple<double, int, int, int>, hipGraphExec_t>> graphs;  // newest last
+    int64_t graph_gen = 0;   // counts drop_graph calls: a batch graph records the values it was captured at
     // profiling
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
@@ -289,6 +290,11 @@ struct spfc_batch {
     std::vector<hipStream_t> cstream;        // one per class (several classes only)
     std::vector<hipEvent_t> join;            // one per class
     hipEvent_t fork = nullptr;
+    // graph replay with several classes: one graph holds two steady steps of every class,
+    // each class on a branch of its own; keyed by dt and every class's slot pair,
+    // scalar-block parity and graph generation
+    bool use_graph = false;
+    std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;  // newest last
 };
 
 namespace {
@@ -357,6 +363,12 @@ struct Timed {
 void drop_graph(spfc_ctx* ctx) {
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
+    ++ctx->graph_gen;
+}
+
+void drop_batch_graphs(spfc_batch* b) {
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    b->graphs.clear();
 }
 
 // Dynamic LDS of every launch shape of the plan within the device limit.
@@ -395,18 +407,26 @@ void set_plan(spfc_ctx* ctx, const TunePlan& tp) {
 // Weights of the steady BDF2 step (eq. scheme-SAV-1) and of the extrapolation 2X - Y.
 constexpr double kA0 = 1.5, kA1 = 2.0, kA2 = -0.5, kE1 = 2.0, kE2 = -1.0;
 
+// Pending step (weights, dt, rise check) whose scalar is still to be solved.
+struct Pending {
+    bool open = false;
+    double a0 = 0, a1 = 0, a2 = 0, dt = 0;
+    int check = 0;
+    bool forced = false;   // its right-hand side holds dt f (spectrum in force_buf)
+};
+
+// State of one call of n steps of size dt on a context (Pipe::run_begin ... run_end).
+struct StepRun {
+    Pending pend;
+    bool restart = false;
+    bool first_order = false;
+    int64_t i = 0;   // steps of this call issued so far
+};
+
 template <typename T>
 struct Pipe {
     using C = cpx<T>;
     spfc_ctx* ctx;
-
-    // Pending step (weights, dt, rise check) whose scalar is still to be solved.
-    struct Pending {
-        bool open = false;
-        double a0 = 0, a1 = 0, a2 = 0, dt = 0;
-        int check = 0;
-        bool forced = false;   // its right-hand side holds dt f (spectrum in force_buf)
-    };
 
     // What a launch needs to close the step whose N is pending (all members).
     FinishIn finish_in(int check_rise) {
@@ -713,45 +733,76 @@ struct Pipe {
         return SPFC_OK;
     }
 
-    // n steps of size dt; coef (device, n x force_terms, or null): the forcing
-    // coefficients of each step (its f^{n+1})
-    int steps(double dt, int64_t n, const double* coef = nullptr) {
+    // A call of n steps of size dt in phases: run_begin (restart at a new dt or at the
+    // start), run_one per step (or graph replays of steady pairs), run_end (the last
+    // update and the record of the state it reaches).
+    int run_begin(StepRun& s, double dt) {
         int rc;
-        const bool restart = !ctx->started || dt != ctx->dt_prev;
-        bool first_order = false;
-        if (restart) {
+        s = StepRun{};
+        s.restart = !ctx->started || dt != ctx->dt_prev;
+        if (s.restart) {
             if (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_GHOST) {
                 if ((rc = ghost(dt))) return rc;
             } else {
                 // phi^{-1} = phi^0, r^{-1} = r^0 = sqrt(E_1(phi^0))
                 ctx->slotY = ctx->slotX;
                 if ((rc = e1_pass(ctx->slot(ctx->slotX), ctx->slot(ctx->slotX), FIN_RESTART))) return rc;
-                first_order = (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_SAV1);
+                s.first_order = (ctx->step == 0 && !ctx->started && ctx->prm.startup == SPFC_STARTUP_SAV1);
             }
         }
+        return SPFC_OK;
+    }
+
+    // a pending BDF2 step of this dt whose rise check is on, two distinct slots: the
+    // next two steps then launch what the two before them did
+    bool run_steady(const StepRun& s, double dt) const {
+        const Pending& p = s.pend;
+        return p.open && p.a0 == kA0 && p.check == 1 && p.dt == dt && !p.forced && ctx->slotX != ctx->slotY;
+    }
+
+    // coef (device, force_terms values, or null): the forcing coefficients of this step
+    int run_one(StepRun& s, double dt, const double* coef) {
+        const bool sav1 = s.first_order && s.i == 0;
+        const int check = (s.i == 0 && s.restart) ? 0 : 1;
+        const bool timed = s.i >= ctx->timed_from;
+        int rc;
+        if (sav1) rc = body(s.pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, timed, coef);
+        else rc = body(s.pend, dt, kA0, kA1, kA2, kE1, kE2, check, timed, coef);
+        if (rc) return rc;
+        ++s.i;
+        return SPFC_OK;
+    }
+
+    // The launches of two steady steps (for a capture; the caller restores the state).
+    int steady_pair(StepRun& s, double dt) {
+        int rc = SPFC_OK;
+        for (int k = 0; k < 2 && rc == SPFC_OK; ++k) rc = body(s.pend, dt, kA0, kA1, kA2, kE1, kE2, 1, false);
+        return rc;
+    }
+
+    // n steps of size dt; coef (device, n x force_terms, or null): the forcing
+    // coefficients of each step (its f^{n+1})
+    int steps(double dt, int64_t n, const double* coef = nullptr) {
+        int rc;
+        StepRun s;
+        if ((rc = run_begin(s, dt))) return rc;
         const bool graphs = ctx->use_graph && !ctx->profiling && ctx->stream != nullptr && !coef;
-        Pending pend;
-        int64_t i = 0;
-        while (i < n) {
-            // steady: a pending BDF2 step of this dt whose rise check is on, two distinct slots
-            const bool steady = pend.open && pend.a0 == kA0 && pend.check == 1 && pend.dt == dt &&
-                                ctx->slotX != ctx->slotY;
-            if (graphs && steady && n - i >= 2) {
-                const int64_t pairs = (n - i) / 2;
-                if ((rc = graph_pairs(pend, dt, pairs))) return rc;
-                i += 2 * pairs;
+        while (s.i < n) {
+            if (graphs && run_steady(s, dt) && n - s.i >= 2) {
+                const int64_t pairs = (n - s.i) / 2;
+                if ((rc = graph_pairs(s.pend, dt, pairs))) return rc;
+                s.i += 2 * pairs;
                 continue;
             }
-            const bool sav1 = first_order && i == 0;
-            const int check = (i == 0 && restart) ? 0 : 1;
-            const bool timed = i >= ctx->timed_from;
-            const double* ci = coef ? coef + i * ctx->force_terms : nullptr;
-            if (sav1) rc = body(pend, dt, 1.0, 1.0, 0.0, 1.0, 0.0, check, timed, ci);
-            else rc = body(pend, dt, kA0, kA1, kA2, kE1, kE2, check, timed, ci);
-            if (rc) return rc;
-            ++i;
+            if ((rc = run_one(s, dt, coef ? coef + s.i * ctx->force_terms : nullptr))) return rc;
         }
-        // apply the last update and record the state it reaches
+        return run_end(s, dt);
+    }
+
+    // apply the last update and record the state it reaches
+    int run_end(StepRun& s, double dt) {
+        int rc;
+        const Pending& pend = s.pend;
         const int target = ctx->slotY != ctx->slotX ? ctx->slotY : 1 - ctx->slotX;
         UpdateArgs<T> u{};
         u.cur = (const C*)ctx->slot(ctx->slotX);
@@ -1025,6 +1076,134 @@ int ctx_step(spfc_ctx* ctx, double dt, int64_t n) {
     if (ctx->broken) return SPFC_E_DEVICE;
     if (n == 0) return SPFC_OK;
     return with_pipe(ctx, [&](auto& p) { return p.steps(dt, n); });
+}
+
+// Every class stream waits for the work queued on the batch's stream so far.
+int batch_fork(spfc_batch* b) {
+    if (hipEventRecord(b->fork, b->stream) != hipSuccess) return SPFC_E_DEVICE;
+    int rc = SPFC_OK;
+    for (auto s : b->cstream)
+        if (hipStreamWaitEvent(s, b->fork, 0) != hipSuccess) rc = SPFC_E_DEVICE;
+    return rc;
+}
+
+// The batch's stream waits for the work queued on every class stream so far.
+int batch_join(spfc_batch* b) {
+    int rc = SPFC_OK;
+    for (size_t c = 0; c < b->cstream.size(); ++c)
+        if (hipEventRecord(b->join[c], b->cstream[c]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->join[c], 0) != hipSuccess)
+            rc = SPFC_E_DEVICE;
+    return rc;
+}
+
+// `pairs` replays, on the batch's stream, of one graph holding two steady steps of every
+// class (each class a branch forked from and joined back into the batch's stream), so
+// the whole batch advances two steps per graph launch.  Captured on first use of its key
+// (the class states the two steps depend on) and kept (the last few keys).  Called with
+// the class streams forked from the batch's stream; they are forked again after the
+// replays.
+int batch_graph_pairs(spfc_batch* b, std::vector<StepRun>& runs, double dt, int64_t pairs) {
+    const size_t nc = b->cls.size();
+    std::vector<int64_t> key;
+    int64_t dbits = 0;
+    std::memcpy(&dbits, &dt, sizeof(dbits));
+    key.push_back(dbits);
+    for (auto* c : b->cls) {
+        key.push_back(c->slotX);
+        key.push_back(c->slotY);
+        key.push_back(c->cur_sc);
+        key.push_back(c->graph_gen);
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : b->graphs)
+        if (g.first == key) exec = g.second;
+    // the replays follow what the class streams hold so far
+    int rc = batch_join(b);
+    if (rc) return rc;
+    if (!exec) {
+        struct Saved {
+            int sx, sy, cs;
+            int64_t st;
+            Pending pend;
+        };
+        std::vector<Saved> saved(nc);
+        for (size_t c = 0; c < nc; ++c)
+            saved[c] = {b->cls[c]->slotX, b->cls[c]->slotY, b->cls[c]->cur_sc, b->cls[c]->step, runs[c].pend};
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SPFC_E_DEVICE;
+        rc = batch_fork(b);
+        for (size_t c = 0; c < nc && rc == SPFC_OK; ++c)
+            rc = with_pipe(b->cls[c], [&](auto& p) { return p.steady_pair(runs[c], dt); });
+        // join every branch before ending the capture, also after an error
+        const int rj = batch_join(b);
+        if (!rc) rc = rj;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+        // capture only recorded the launches: back to the states before them
+        for (size_t c = 0; c < nc; ++c) {
+            b->cls[c]->slotX = saved[c].sx;
+            b->cls[c]->slotY = saved[c].sy;
+            b->cls[c]->cur_sc = saved[c].cs;
+            b->cls[c]->step = saved[c].st;
+            runs[c].pend = saved[c].pend;
+        }
+        if (rc || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : SPFC_E_DEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return SPFC_E_DEVICE;
+        if (b->graphs.size() >= 4) {
+            (void)hipGraphExecDestroy(b->graphs.front().second);
+            b->graphs.erase(b->graphs.begin());
+        }
+        b->graphs.push_back({key, exec});
+    }
+    for (int64_t i = 0; i < pairs; ++i)
+        if (hipGraphLaunch(exec, b->stream) != hipSuccess) return SPFC_E_DEVICE;
+    for (size_t c = 0; c < nc; ++c) {
+        b->cls[c]->step += 2 * pairs;
+        runs[c].i += 2 * pairs;
+    }
+    return batch_fork(b);
+}
+
+// n steps of every class of a batch with class streams (forked already), replaying
+// steady pairs of steps of the whole batch from one graph.
+int batch_steps_graph(spfc_batch* b, double dt, int64_t n) {
+    const size_t nc = b->cls.size();
+    std::vector<StepRun> runs(nc);
+    int rc;
+    for (size_t c = 0; c < nc; ++c) {
+        if (b->cls[c]->broken) return SPFC_E_DEVICE;
+        if (b->cls[c]->profiling) {
+            // profiling times each launch: direct launches, class by class
+            for (auto* x : b->cls)
+                if ((rc = ctx_step(x, dt, n))) return rc;
+            return SPFC_OK;
+        }
+    }
+    for (size_t c = 0; c < nc; ++c)
+        if ((rc = with_pipe(b->cls[c], [&](auto& p) { return p.run_begin(runs[c], dt); }))) return rc;
+    int64_t i = 0;
+    while (i < n) {
+        bool steady = n - i >= 2;
+        for (size_t c = 0; c < nc && steady; ++c)
+            steady = with_pipe(b->cls[c], [&](auto& p) { return p.run_steady(runs[c], dt) ? 1 : 0; }) == 1;
+        if (steady) {
+            const int64_t pairs = (n - i) / 2;
+            if ((rc = batch_graph_pairs(b, runs, dt, pairs))) return rc;
+            i += 2 * pairs;
+            continue;
+        }
+        for (size_t c = 0; c < nc; ++c)
+            if ((rc = with_pipe(b->cls[c], [&](auto& p) { return p.run_one(runs[c], dt, nullptr); }))) return rc;
+        ++i;
+    }
+    for (size_t c = 0; c < nc; ++c)
+        if ((rc = with_pipe(b->cls[c], [&](auto& p) { return p.run_end(runs[c], dt); }))) return rc;
+    return SPFC_OK;
 }
 
 int ctx_status(spfc_ctx* ctx, int m, uint32_t* flags) {
@@ -1691,6 +1870,8 @@ int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params
 int spfc_batch_set_graph(spfc_batch* b, int enable) {
     if (!b) return SPFC_E_INVAL;
     for (auto* c : b->cls) spfc_set_graph(c, enable);
+    b->use_graph = enable != 0 && b->stream != nullptr;
+    if (!b->use_graph) drop_batch_graphs(b);
     return SPFC_OK;
 }
 
@@ -1706,21 +1887,20 @@ int spfc_batch_step(spfc_batch* b, double dt, int64_t n) {
         return SPFC_OK;
     }
     // fork: every class stream waits for what the caller queued before this call
-    if (hipEventRecord(b->fork, b->stream) != hipSuccess) return SPFC_E_DEVICE;
-    int rc = SPFC_OK;
-    for (size_t c = 0; c < b->cls.size(); ++c) {
-        if (hipStreamWaitEvent(b->cstream[c], b->fork, 0) != hipSuccess) rc = SPFC_E_DEVICE;
-        b->cls[c]->stream = b->cstream[c];
+    int rc = batch_fork(b);
+    for (size_t c = 0; c < b->cls.size(); ++c) b->cls[c]->stream = b->cstream[c];
+    if (rc == SPFC_OK) {
+        if (b->use_graph) {
+            rc = batch_steps_graph(b, dt, n);
+        } else {
+            for (size_t c = 0; c < b->cls.size() && rc == SPFC_OK; ++c) rc = ctx_step(b->cls[c], dt, n);
+        }
     }
-    for (size_t c = 0; c < b->cls.size() && rc == SPFC_OK; ++c) rc = ctx_step(b->cls[c], dt, n);
     // join: the caller's stream waits for every class (also after an error, so that no
     // class work is left behind the caller's back)
-    for (size_t c = 0; c < b->cls.size(); ++c) {
-        if (hipEventRecord(b->join[c], b->cstream[c]) != hipSuccess ||
-            hipStreamWaitEvent(b->stream, b->join[c], 0) != hipSuccess)
-            rc = SPFC_E_DEVICE;
-        b->cls[c]->stream = b->stream;
-    }
+    const int rj = batch_join(b);
+    if (!rc) rc = rj;
+    for (size_t c = 0; c < b->cls.size(); ++c) b->cls[c]->stream = b->stream;
     return rc;
 }
 
@@ -1915,6 +2095,7 @@ int spfc_batch_energies(spfc_batch* b, spfc_energy_t* out) {
 
 int spfc_batch_destroy(spfc_batch* b) {
     if (!b) return SPFC_E_INVAL;
+    drop_batch_graphs(b);
     for (auto* c : b->cls) free_ctx(c);
     for (auto s : b->cstream) {
         (void)hipStreamSynchronize(s);

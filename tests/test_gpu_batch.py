@@ -170,6 +170,53 @@ def test_graph_replay_batch_and_checkpoint():
     s.close()
 
 
+def _batch_snapshots(members, graph, script):
+    from paper_2012_15133_amd import Batch
+    b = Batch(members, history=96, graph=graph)
+    snaps = []
+    for what, arg in script:
+        if what == "step":
+            b.step(*arg)
+        elif what == "time":
+            b.time_kernels(0.01, reps=3)   # runs from a snapshot and restores the state
+        elif what == "profile":
+            b.profile(arg)                 # while profiling the steps launch directly
+        elif what == "reset":
+            b.reset([m["phi0"] for m in members])
+        # eager work and synchronizations between the replays
+        snaps.append([(b.phi(i).cpu().numpy(), b.energy(i)["modified_energy"], b.mass(i))
+                      for i in range(len(members))])
+    n = b.step_count()
+    out = (snaps, [b.history(i, 0, n + 1) for i in range(len(members))], [b.status(i) for i in range(len(members))])
+    b.close()
+    return out
+
+
+def test_graph_replay_whole_batch_equals_direct_launches():
+    """Several size classes with graph replay: one graph holds two steady steps of every
+    class (each class a branch of its own).  Equal bit for bit to direct launches over
+    calls with odd and even step counts, dt changes, kernel timing from a snapshot,
+    profiled steps and a reset."""
+    specs = [((64, 64), (8 * math.pi,) * 2, 0.25, -0.2, 21, "fp64"),
+             ((128, 128), (32 * math.pi,) * 2, 0.1, -0.3, 22, "fp64"),
+             ((32, 32), (4 * math.pi,) * 2, 0.4, -0.1, 23, "fp64"),
+             ((128, 128), (32 * math.pi,) * 2, 0.3, -0.25, 24, "fp64"),
+             ((64, 64), (8 * math.pi,) * 2, 0.2, -0.15, 25, "fp32"),
+             ((16, 16, 16), (4 * math.pi,) * 3, 0.25, -0.25, 26, "fp64")]
+    members = _members(specs)
+    script = [("step", (0.01, 1)), ("step", (0.01, 8)), ("step", (0.01, 7)), ("step", (0.02, 11)),
+              ("time", None), ("step", (0.02, 6)), ("profile", True), ("step", (0.02, 4)), ("profile", False),
+              ("step", (0.01, 5)), ("reset", None), ("step", (0.01, 9)), ("step", (0.01, 2))]
+    direct = _batch_snapshots(members, False, script)
+    replay = _batch_snapshots(members, True, script)
+    for k, (sa, sb) in enumerate(zip(direct[0], replay[0])):
+        for i, ((pa, ea, ma), (pb, eb, mb)) in enumerate(zip(sa, sb)):
+            assert np.array_equal(pa, pb), (k, i)
+            assert ea == eb and ma == mb, (k, i)
+    assert direct[1] == replay[1]
+    assert direct[2] == replay[2] == [0] * len(members)
+
+
 # ----------------------------------------------------------------- launch-plan tuner
 
 def test_tune_keeps_the_run_state():
