@@ -171,7 +171,9 @@ def test_c2_2000_steps_fp64_against_oracle(monkeypatch, plan):
     assert max(phi_err.values()) <= 1e-9, phi_err
     assert e_rel[:4].max() <= 1e-12 and e_rel.max() <= 1e-11
     assert r_rel.max() <= 1e-11
-    assert m_abs.max() <= 1e-13
+    # both sides keep the mean to rounding that grows with the step count (Theorem 2.1):
+    # at most 10 n eps |mean| each
+    assert m_abs.max() <= 2 * 10 * 2000 * np.finfo(np.float64).eps * 0.2
     assert flags == 0
 
 
