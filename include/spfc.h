@@ -275,7 +275,12 @@ int spfc_batch_init(int count, const spfc_grid* grids, const spfc_params* params
  * on the batch's stream before the call, and the batch's stream waits for every class
  * at the end, so the caller sees the steps ordered on the batch's stream. */
 int spfc_batch_step(spfc_batch* b, double dt, int64_t n);
-/* Graph replay for every class (as spfc_set_graph). */
+/* Graph replay (as spfc_set_graph).  With one size class the class's own graph is
+ * replayed.  With several, one graph holds two steady steps of every class, each class
+ * on a branch of its own (forked from the batch's stream and joined back into it), so
+ * each further pair of steps of the whole batch is a single graph launch on the batch's
+ * stream; it is captured again when dt, the plan or a class's state pair changes.
+ * Results are bit for bit those of direct launches. */
 int spfc_batch_set_graph(spfc_batch* b, int enable);
 int spfc_batch_step_count(spfc_batch* b, int64_t* n);
 /* Per-member queries, as their single-run counterparts; SPFC_E_INVAL for a member
