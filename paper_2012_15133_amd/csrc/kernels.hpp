@@ -640,22 +640,38 @@ __device__ inline cpx<T> lane_fetch(cpx<T> v, int src) {
 // W(e) = conj H1(N - e) + i conj H2(N - e) comes from entry N - e, is formed by the lane
 // that loaded N - e and moved across lanes: element m >= E/2 of thread t > 0 mirrors
 // element E - 1 - m of thread P - t, and thread 0's mirror its own element E - m.
-// Needs the P threads of a line within one wave (P <= 64).  All P lanes must call it.
-// With KX, H1 = i kappa1_x h1 (its Nyquist bin is zero).
-template <typename T, typename PL, bool KX>
-__device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int t, cpx<T> (&w)[PL::E], double k0) {
-    constexpr int E = PL::E, P = PL::P, N = PL::Nl, H = E / 2;
+// Needs the P threads of a line within one wave (P <= 64).  In two halves, so that a
+// kernel issues the loads of all its lines before the first exchange waits for any of
+// them: packed_fetch (the loads) and packed_mirror (all P lanes must call it; with KX,
+// H1 = i kappa1_x h1, whose Nyquist bin is zero).
+template <typename T, typename PL>
+struct PackedRaw {
+    cpx<T> a[PL::E / 2], b[PL::E / 2], an, bn;
+};
+
+template <typename T, typename PL>
+__device__ inline void packed_fetch(const cpx<T>* h1, const cpx<T>* h2, int t, PackedRaw<T, PL>& r) {
+    constexpr int H = PL::E / 2, P = PL::P, N = PL::Nl;
     static_assert(P <= 64, "a line must lie within one wave");
-    cpx<T> a[H], b[H];
 #pragma unroll
     for (int m = 0; m < H; ++m) {
-        a[m] = h1[t + P * m];
-        b[m] = h2[t + P * m];
-        if constexpr (KX) a[m] = mul_ikx(a[m], t + P * m, N, k0);
+        r.a[m] = h1[t + P * m];
+        r.b[m] = h2[t + P * m];
     }
-    cpx<T> an = h1[N / 2];
-    const cpx<T> bn = h2[N / 2];
-    if constexpr (KX) an = mk<T>(T(0), T(0));
+    r.an = h1[N / 2];
+    r.bn = h2[N / 2];
+}
+
+template <typename T, typename PL, bool KX>
+__device__ inline void packed_mirror(PackedRaw<T, PL>& r, int t, cpx<T> (&w)[PL::E], double k0) {
+    constexpr int E = PL::E, P = PL::P, N = PL::Nl, H = E / 2;
+    cpx<T>* a = r.a;
+    cpx<T>* b = r.b;
+    if constexpr (KX) {
+#pragma unroll
+        for (int m = 0; m < H; ++m) a[m] = mul_ikx(a[m], t + P * m, N, k0);
+        r.an = mk<T>(T(0), T(0));
+    }
     if (t == 0) {
         a[0].y = T(0);
         b[0].y = T(0);
@@ -670,13 +686,13 @@ __device__ inline void load_packed_once(const cpx<T>* h1, const cpx<T>* h2, int 
     const int src = lane - t + ((P - t) & (P - 1));
 #pragma unroll
     for (int m = H; m < E; ++m) {
-        const cpx<T> r = lane_fetch(mv[E - 1 - m], src);
-        if (t != 0) w[m] = r;
-        else w[m] = m == H ? mk<T>(an.x, bn.x) : mv[E - m];
+        const cpx<T> x = lane_fetch(mv[E - 1 - m], src);
+        if (t != 0) w[m] = x;
+        else w[m] = m == H ? mk<T>(r.an.x, r.bn.x) : mv[E - m];
     }
 }
 
-// load_packed_once for lines that span several waves (P > 64): the entries each thread
+// packed_fetch + packed_mirror for lines that span several waves (P > 64): the entries each thread
 // loads (t + P m for m < E/2, and the self-conjugate bin N/2) are staged in the group's line
 // buffer, stage[0 .. N/2] (H1, with KX times i kappa1_x) and stage[N/2 + 1 .. N + 1] (H2),
 // and each thread reads the entries N - e of its mirrored elements from there.  The buffer
@@ -756,19 +772,31 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
     tws.load(p.tw, p.tws);
     issue_barrier();
     cpx<T> v[C][E];
+    if constexpr (P <= 64) {
+        // every line's loads first, then the exchanges (c is a constant once the loops
+        // are unrolled)
+        PackedRaw<T, PL> raw[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
-        const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
-        if constexpr (P <= 64) {
-            // (c is a constant once the loop is unrolled)
-            if (PK::kx(c)) load_packed_once<T, PL, true>(h1, h2, t, v[c], geo.k0x);
-            else load_packed_once<T, PL, false>(h1, h2, t, v[c], 0.0);
+        for (int c = 0; c < C; ++c) {
+            const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
+            const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
+            packed_fetch<T, PL>(h1, h2, t, raw[c]);
+        }
+        issue_barrier();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (PK::kx(c)) packed_mirror<T, PL, true>(raw[c], t, v[c], geo.k0x);
+            else packed_mirror<T, PL, false>(raw[c], t, v[c], 0.0);
             if (!act) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) v[c][m] = mk<T>(0, 0);
             }
-        } else {
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const cpx<T>* h1 = p.in[PK::fa(c)] + mbase + (size_t)(act ? row0 + PK::ra(c) : 0) * NXH;
+            const cpx<T>* h2 = p.in[PK::fb(c)] + mbase + (size_t)(act ? row0 + PK::rb(c) : 0) * NXH;
             // the group's line buffer c is free until the transform
             cpx<T>* stage = lds + c * LdsLine<NX>::size;
             if (PK::kx(c)) load_packed_staged<T, PL, true>(h1, h2, t, v[c], geo.k0x, stage, act);
@@ -824,9 +852,10 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
         // Q2(k) = (V(k) - conj V(-k)) / (2 i).
         __syncthreads();
         const T half = T(0.5);
-        if constexpr (DIM == 3 && NX >= 32 && E <= 4) {
-            // (4 values per thread; with 8 the per-thread pair stores below measured faster:
-            // 175 against 181 us at 256^3, against 150 us here with 4.)
+        if constexpr (DIM == 3 && NX >= 32 && E <= 8) {
+            // (4 or 8 values per thread; at 256^3 the run length decides: 2G rows of 8-byte
+            // values per wavenumber, 64 bytes at 4 values and 256 threads, 128 bytes at 8,
+            // 94.5 against 104.3 us; 16 per thread keeps the per-thread pair stores below.)
             // Rotated output through an LDS tile, so that each wave writes whole lines: the
             // workgroup's 2G rows are neighbours in every output, [k][rows].  The lines go
             // line-major across the groups (line c of group g at (c G + g) LS); then one
@@ -851,6 +880,10 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                 q2 = mk<T>(half * (Vk.y + Vm.y), half * (Vm.x - Vk.x));
             };
             cpx<T>* const tile = lb + 2 * G * LS;
+            const int st_k0 = threadIdx.x / G, st_j = threadIdx.x - st_k0 * G;
+            const int st_row = row_base + RPG * st_j;
+            const bool st_ok = st_row < p.nrows;
+            const size_t st_off = mbase + (size_t)st_k0 * p.nrows + st_row, st_step = (size_t)P * p.nrows;
 #pragma unroll
             for (int f0 = 0; f0 < 3; ++f0) {
                 const int f = f0 == 0 ? 2 : f0 - 1;
@@ -886,12 +919,14 @@ __global__ void __launch_bounds__(256) k_real_pass(RealArgs<T> p) {
                     tile[k * R2 + 2 * jj + 1] = rb[m];
                 }
                 __syncthreads();
-                for (int q = threadIdx.x; q < NXH * G; q += blockDim.x) {
-                    const int k = q / G, j = q - k * G, jj = j ^ (k & sw);
-                    const int row = row_base + RPG * j;
-                    if (row < p.nrows)
-                        store_pair(p.out[f] + mbase + (size_t)k * p.nrows + row, tile[k * R2 + 2 * jj],
-                                   tile[k * R2 + 2 * jj + 1]);
+                // the workgroup is G P threads: thread (k0, j) stores pair j of wavenumbers
+                // k0, k0 + P, ... (no division in the loop)
+                if (st_ok) {
+                    cpx<T>* dst = p.out[f] + st_off;
+                    for (int k = st_k0; k < NXH; k += P, dst += st_step) {
+                        const int jj = st_j ^ (k & sw);
+                        store_pair(dst, tile[k * R2 + 2 * jj], tile[k * R2 + 2 * jj + 1]);
+                    }
                 }
             }
         } else {
