@@ -42,18 +42,24 @@ hipError_t dispatch_ne(int n, int e, F&& f) {
     constexpr int EE = decltype(ee)::value;
 
 template <typename T>
-hipError_t Kern<T>::spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a, const LaunchShape& s,
+hipError_t Kern<T>::spec_inv(int nl, int dim, bool stab, bool fin, const SpecInvArgs<T>& a, const LaunchShape& s,
                              hipStream_t st) {
     return dispatch_ne(nl, s.E, [&](auto nn, auto ee) -> hipError_t {
         SPFC_NE_CONSTS
         const dim3 g(s.grid, s.members), b(s.block);
+#define SPFC_INV(D, S, F) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, D, S, F>), g, b, s.shmem, st, a)
         if (dim == 2) {
-            if (stab) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2, true>), g, b, s.shmem, st, a);
-            else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 2, false>), g, b, s.shmem, st, a);
+            if (stab && fin) SPFC_INV(2, true, true);
+            else if (stab) SPFC_INV(2, true, false);
+            else if (fin) SPFC_INV(2, false, true);
+            else SPFC_INV(2, false, false);
         } else {
-            if (stab) hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3, true>), g, b, s.shmem, st, a);
-            else hipLaunchKernelGGL((k_spec_inv<T, NN, EE, 3, false>), g, b, s.shmem, st, a);
+            if (stab && fin) SPFC_INV(3, true, true);
+            else if (stab) SPFC_INV(3, true, false);
+            else if (fin) SPFC_INV(3, false, true);
+            else SPFC_INV(3, false, false);
         }
+#undef SPFC_INV
         return hipGetLastError();
     });
 }

@@ -455,7 +455,10 @@ __device__ inline void tiled_line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* til
 // line's own axis.  The symbols of the other axes are constant along the line, so
 // the later passes apply them (i kappa1_y before the y transform in 3-D, i kappa1_x
 // as the real-space pass loads its rows): two fields out instead of d.
-template <typename T, int NL, int EE, int DIM, bool STAB>
+// FIN: the variant that can close the pending step itself (p.fin); without it the
+// reduction's registers are not held (161 -> 106 VGPRs at 256 points, FP32), so a
+// separately closed step runs more waves per SIMD.
+template <typename T, int NL, int EE, int DIM, bool STAB, bool FIN>
 __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     using PL = Plan<NL, EE>;
     constexpr int E = PL::E, P = PL::P, C = 2;
@@ -474,7 +477,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     // must not wait behind earlier stores), the partial sums of xi before the
     // field values so that their reduction overlaps the field loads
     const FinishIn fi = member_fin(p.fi, mem);
-    const bool fin = p.update && p.fin;
+    const bool fin = FIN && p.update && p.fin;
     XiInputs xin;
     if (p.update) xin.load(fi, fin);
     issue_barrier();

@@ -50,7 +50,8 @@ inline LaunchShape line_shape(int N, int C, size_t elem, int ngroups, int E = 16
 template <typename T>
 struct Kern {
     // stab: the stabilized-scheme variant (any member with a nonzero stabilization)
-    static hipError_t spec_inv(int nl, int dim, bool stab, const SpecInvArgs<T>& a, const LaunchShape& s,
+    // fin: the variant that closes the pending step inside the kernel (a.fin set)
+    static hipError_t spec_inv(int nl, int dim, bool stab, bool fin, const SpecInvArgs<T>& a, const LaunchShape& s,
                                hipStream_t st);
     static hipError_t real_pass(int nx, int dim, bool fwd, bool beta, const RealArgs<T>& a, const LaunchShape& s,
                                 hipStream_t st);

@@ -480,7 +480,7 @@ struct Pipe {
         {
             Timed tm(ctx, R_SPEC_INV, timed);
             for (int r = 0; r < tm.reps(); ++r)
-                CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, ctx->stab, a, ctx->sh.A, ctx->stream));
+                CK(Kern<T>::spec_inv(ctx->nl(), ctx->sz.dim, ctx->stab, a.fin != 0, a, ctx->sh.A, ctx->stream));
         }
         if (a.fin) ctx->cur_sc = 1 - ctx->cur_sc;
         return SPFC_OK;
