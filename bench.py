@@ -16,8 +16,10 @@ Prints one JSON line: grid-point-steps/s, the roofline of the dominant kernel
 back-to-back launches of each kernel of a steady step on the solver stream,
 against 8 TB/s and against a device copy measured on the same box), the error of
 a fresh run under the tuned plan against the stored FP64 oracle trajectory of the
-same workload (tests/golden), and the CPU oracle timed on a bounded sample of the
-same workload, on one thread and on all host cores.
+same workload (tests/golden), the CPU oracle timed on a bounded sample of the
+same workload, on one thread and on all host cores, and (single-run workloads, unless
+--no-companions) the batched and surrogate speed-ups of the metric, each measured by
+this script in a child process with --workload ensemble64_fp64 / surrogate64_256.
 """
 
 from __future__ import annotations
@@ -27,6 +29,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -403,6 +406,47 @@ def run_surrogate(args):
     print(json.dumps(out))
 
 
+def _child_line(argv, timeout_s):
+    """Last JSON line this script prints when run with argv in a child process."""
+    r = subprocess.run([sys.executable, os.path.abspath(__file__)] + argv, cwd=ROOT, stdout=subprocess.PIPE,
+                       stderr=subprocess.PIPE, text=True, timeout=timeout_s)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        raise RuntimeError(f"exit {r.returncode}: {r.stderr.strip()[-300:]}")
+    return json.loads(lines[-1])
+
+
+def companions(timeout_s: int = 600):
+    """The other two parts of the metric, each measured by this script in a child process
+    (a failure there is reported, not fatal): the batched speed-up (the 64-run ensemble as
+    one batch against the same runs one after another, fields compared bit for bit) and
+    the surrogate speed-up (learned 50-step jumps judged by the SAV energy against the
+    plain steps, with the error of the jumped fields)."""
+    out = {}
+    try:
+        d = _child_line(["--workload", "ensemble64_fp64", "--steps", "200", "--warmup", "20"], timeout_s)
+        seq = d.get("sequential", {})
+        out["batched"] = {"workload": "ensemble64_fp64", "members": d["config"]["members"],
+                          "sizes": d["config"]["sizes"], "steps": d["steps"], "ms_per_step": d["ms_per_step"],
+                          "grid_point_steps_per_s": d["value"], "speedup_vs_sequential": seq.get("speedup"),
+                          "bitwise_equal_members": seq.get("bitwise_equal_members"),
+                          "max_rel_diff": seq.get("max_rel_diff"), "dominant_kernel": d["roofline"]["kernel"],
+                          "dominant_frac": d["roofline"]["frac"]}
+    except Exception as e:   # noqa: BLE001 - reported in the line
+        out["batched"] = {"workload": "ensemble64_fp64", "error": f"{type(e).__name__}: {e}"[:400]}
+    try:
+        d = _child_line(["--workload", "surrogate64_256", "--steps", "1000", "--warmup", "100"], timeout_s)
+        sg = d["surrogate"]
+        out["surrogate"] = {"workload": "surrogate64_256", "members": d["config"]["members"], "n": d["config"]["n"],
+                            "plain_steps": d["steps"], "jumps": sg["jumps"], "accepted": sg["accepted"],
+                            "rejected": sg["rejected"], "err_over_change_mean": sg["err_over_change_mean"],
+                            "err_over_change_max": sg["err_over_change_max"],
+                            "speedup_vs_plain": sg["speedup_vs_plain"], "grid_point_steps_per_s": d["value"]}
+    except Exception as e:   # noqa: BLE001 - reported in the line
+        out["surrogate"] = {"workload": "surrogate64_256", "error": f"{type(e).__name__}: {e}"[:400]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +463,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the run against the stored oracle trajectory")
     ap.add_argument("--graph", type=int, default=0, help="1: replay the steady steps from a captured HIP graph")
+    ap.add_argument("--no-companions", action="store_true",
+                    help="single-run workloads: skip the batched and surrogate speed-ups (child processes)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -523,6 +569,8 @@ def main():
             out["accuracy"] = acc
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if not args.no_companions:
+        out.update(companions())
     print(json.dumps(out))
 
 
