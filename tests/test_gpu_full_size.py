@@ -242,3 +242,21 @@ def test_c3_500_steps_fp32_against_fp64_path(monkeypatch):
     assert linf <= FP32_PHI and e_rel <= FP32_E and m_abs <= 1e-6
     assert all(b <= a * (1 + 1e-12) for a, b in zip(e64, e64[1:]))
     assert max(abs(h["mean"] - h64[0]["mean"]) for h in h64) <= 10 * steps * np.finfo(np.float64).eps * 0.25
+
+
+def test_c3_steps_are_deterministic(monkeypatch):
+    """Two runs of the 256^3 workload give the same bits: every reduction (the E_1 and inner
+    product partials of thousands of workgroups, the separate step close) adds in a fixed
+    order, with no floating-point atomics."""
+    meta, _ = _golden("spfc3d_256_seed3.npz")
+    _with_plan(monkeypatch, "")
+    n, L = tuple(meta["n"]), tuple(meta["L"])
+    phi0 = noise_ic(tuple(reversed(n)), meta["mean"], meta["seed"])
+    runs = []
+    for _ in range(2):
+        s = _solver(n, L, phi0, meta["epsilon"], precision="fp32", history=16)
+        s.step(meta["dt"], 12)
+        runs.append((s.phi().cpu().numpy(), s.history(0, 13)))
+        s.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
