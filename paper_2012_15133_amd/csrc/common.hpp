@@ -65,6 +65,9 @@ enum : unsigned int {
 //                     <X - Y, -Delta_N (X - Y)>                         6 per workgroup
 //   B (real-space pass): E_1 density sum                              1 per workgroup
 //   Q (update / query passes): the same five as E for the pair they form
+// Lines of a 3-D y-pass group that go through the transform's exchanges (and the output
+// tile) at a time.
+constexpr int YPASS_CH = 1;
 constexpr int NPART_P = 3, NPART_PF = 4, NPART_E = 6;
 
 // What a launch needs to finish the previous step (the SAV scalar) itself.  All

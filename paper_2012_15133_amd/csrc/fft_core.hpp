@@ -245,7 +245,9 @@ __host__ __device__ constexpr int xch_index(int i) {
     else return lds_pad<N>(i);
 }
 
-template <typename T, typename PL, int C, int PASS>
+// The exchange stores and loads of lines C0 .. C0 + CN - 1 of v, through buffer lines
+// 0 .. CN - 1.
+template <typename T, typename PL, int C, int PASS, int C0 = 0, int CN = C>
 __host__ __device__ inline void pass_store(const cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t) {
     constexpr int N = PL::Nl, E = PL::E, P = PL::P;
     constexpr int R = PL::radix(PASS), Ns = PL::span(PASS), NB = E / R;
@@ -254,14 +256,15 @@ __host__ __device__ inline void pass_store(const cpx<T> (&v)[C][PL::E], cpx<T>* 
         const int b = t + P * u;
         const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
+        for (int c = C0; c < C0 + CN; ++c) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[c * LdsLine<N>::size + xch_index<N, E>(base + r * Ns)] = v[c][u + r * NB];
+            for (int r = 0; r < R; ++r)
+                lds[(c - C0) * LdsLine<N>::size + xch_index<N, E>(base + r * Ns)] = v[c][u + r * NB];
         }
     }
 }
 
-template <typename T, typename PL, int C, int PASS>
+template <typename T, typename PL, int C, int PASS, int C0 = 0, int CN = C>
 __host__ __device__ inline void pass_load(cpx<T> (&v)[C][PL::E], const cpx<T>* lds, int t) {
     constexpr int N = PL::Nl, E = PL::E, P = PL::P;
     constexpr int R = PL::radix(PASS), NB = E / R;
@@ -269,9 +272,10 @@ __host__ __device__ inline void pass_load(cpx<T> (&v)[C][PL::E], const cpx<T>* l
     for (int u = 0; u < NB; ++u) {
         const int b = t + P * u;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
+        for (int c = C0; c < C0 + CN; ++c) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[c][u + r * NB] = lds[c * LdsLine<N>::size + xch_index<N, E>(b + r * (N / R))];
+            for (int r = 0; r < R; ++r)
+                v[c][u + r * NB] = lds[(c - C0) * LdsLine<N>::size + xch_index<N, E>(b + r * (N / R))];
         }
     }
 }
@@ -286,23 +290,29 @@ __host__ __device__ inline void line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* 
         for (int m = 0; m < PL::E; ++m) lds[c * LdsLine<N>::size + lds_pad<N>(t + PL::P * m)] = v[c][m];
 }
 
-// Whole transform on the device: all threads of the workgroup must call it
-// (it contains workgroup barriers).  lds points at this thread group's
-// C * LdsLine<N>::size elements.
-// ptw: the two twiddle tables of this line length (TwSplit, in LDS).
-template <typename T, typename PL, int DIR, int C, int PASS = 0>
-__device__ inline void fft_run(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ ptw) {
-    if constexpr (PASS == 0) {
-        pass_compute<T, PL, DIR, C, 0>(v, t, ptw);
-        if constexpr (PL::NP > 1) fft_run<T, PL, DIR, C, 1>(v, lds, t, ptw);
-    } else {
+// The exchange before pass PASS, CH of the C lines at a time through CH line buffers.
+template <typename T, typename PL, int C, int PASS, int CH, int C0 = 0>
+__device__ inline void pass_exchange(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t) {
+    if constexpr (C0 < C) {
+        constexpr int CN = C - C0 < CH ? C - C0 : CH;
         __syncthreads();
-        pass_store<T, PL, C, PASS - 1>(v, lds, t);
+        pass_store<T, PL, C, PASS - 1, C0, CN>(v, lds, t);
         __syncthreads();
-        pass_load<T, PL, C, PASS>(v, lds, t);
-        pass_compute<T, PL, DIR, C, PASS>(v, t, ptw);
-        if constexpr (PASS + 1 < PL::NP) fft_run<T, PL, DIR, C, PASS + 1>(v, lds, t, ptw);
+        pass_load<T, PL, C, PASS, C0, CN>(v, lds, t);
+        pass_exchange<T, PL, C, PASS, CH, C0 + CN>(v, lds, t);
     }
+}
+
+// Whole transform of C lines on the device: all threads of the workgroup must call it
+// (it contains workgroup barriers).  lds points at this thread group's
+// CH * LdsLine<N>::size elements: the lines go through the exchanges between passes CH at
+// a time (CH = C: all at once; fewer line buffers cost more barriers).
+// ptw: the two twiddle tables of this line length (TwSplit, in LDS).
+template <typename T, typename PL, int DIR, int C, int PASS = 0, int CH = C>
+__device__ inline void fft_run(cpx<T> (&v)[C][PL::E], cpx<T>* lds, int t, const cpx<T>* __restrict__ ptw) {
+    if constexpr (PASS > 0) pass_exchange<T, PL, C, PASS, CH>(v, lds, t);
+    pass_compute<T, PL, DIR, C, PASS>(v, t, ptw);
+    if constexpr (PASS + 1 < PL::NP) fft_run<T, PL, DIR, C, PASS + 1, CH>(v, lds, t, ptw);
 }
 
 // Stage this line length's two twiddle tables in LDS from the global natural table

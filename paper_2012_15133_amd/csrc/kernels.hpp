@@ -418,29 +418,37 @@ __device__ inline double finish_in_kernel(const FinishIn& fi, double a0, double 
 // Store of transform results held in registers (element t + P m of each of C lines of
 // the group) to outputs in which, for each element e, the workgroup's G lines are
 // neighbours: through an LDS tile [c][e][g] (the line buffers, free once the transform is
-// done: C NL G <= G C LdsLine entries) so that consecutive threads store consecutive
-// lines.  The line index is swizzled by e when G is a power of two (bank spread).
+// done) so that consecutive threads store consecutive lines, CH of the C lines per round
+// (a round's tile, CH NL G entries, fits in the workgroup's G CH line buffers).
+// The line index is swizzled by e when G is a power of two (bank spread).
 // idx(c, e, gi) gives the element's position in output c, or a negative value for a line
 // past the end.  All threads of the workgroup must call it.
-template <typename T, typename PL, int C, class Idx>
+template <typename T, typename PL, int C, int CH = C, class Idx>
 __device__ inline void tiled_line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* tile, int G, int g, int t,
                                         cpx<T>* const* out, size_t mbase, Idx idx) {
     constexpr int NL = PL::Nl, E = PL::E, P = PL::P;
     const int sw = (G & (G - 1)) == 0 ? G - 1 : 0;
-    __syncthreads();   // the transform's last reads of the line buffers are done
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int e = t + P * m;
-            tile[(c * NL + e) * G + (g ^ (e & sw))] = v[c][m];
-        }
-    __syncthreads();
     const int gi = threadIdx.x % G, step = blockDim.x / G;
-    for (int ce = threadIdx.x / G; ce < C * NL; ce += step) {
-        const int c = ce / NL, e = ce - c * NL;
-        const long long i = idx(c, e, gi);
-        if (i >= 0) out[c][mbase + (size_t)i] = tile[(c * NL + e) * G + (gi ^ (e & sw))];
+#pragma unroll
+    for (int c0 = 0; c0 < C; c0 += CH) {
+        const int cn = C - c0 < CH ? C - c0 : CH;
+        __syncthreads();   // the previous reads of the line buffers (transform or tile) are done
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (c < cn) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int e = t + P * m;
+                    tile[(c * NL + e) * G + (g ^ (e & sw))] = v[c0 + c][m];
+                }
+            }
+        }
+        __syncthreads();
+        for (int ce = threadIdx.x / G; ce < cn * NL; ce += step) {
+            const int c = ce / NL, e = ce - c * NL;
+            const long long i = idx(c0 + c, e, gi);
+            if (i >= 0) out[c0 + c][mbase + (size_t)i] = tile[(c * NL + e) * G + (gi ^ (e & sw))];
+        }
     }
 }
 
@@ -1048,13 +1056,18 @@ __global__ void __launch_bounds__(256) k_pass(PassArgs<T> p) {
 // of Psi_z (g_z).  Forward (DIR = -1): in[0..2] = -i kappa1_x Q_x, Q_y, Q_z after the
 // x transform; out[0] = V0 - i kappa1_y V1 and out[1] = V2 of their y transforms V0..V2,
 // so that only the z term of the divergence is left for the last pass.
+// The three lines of a group go through the transform's exchanges and the output tile
+// one at a time (YPASS_CH line buffers per group), so that a workgroup of up to 512
+// threads holds 16 lines of 256 points in 35 KB of LDS and writes runs of 16 neighbouring
+// entries (128 bytes in FP32): 256^3 y passes 89 -> 82 and 82 -> 75 us inside the step,
+// against 8 lines with all three lines exchanged at once.
 template <typename T, int NL, int EE, int DIR>
-__global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
+__global__ void __launch_bounds__(512) k_ypass(PassArgs<T> p) {
     using PL = Plan<NL, EE>;
-    constexpr int E = PL::E, P = PL::P, C = 3;
+    constexpr int E = PL::E, P = PL::P, C = 3, CH = YPASS_CH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
+    cpx<T>* ltw = lds + p.G * CH * LdsLine<NL>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
@@ -1085,7 +1098,7 @@ __global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
     // (lanes past the last line loaded line 0 of the member; they store nothing)
     issue_barrier();
     tws.store(ltw);
-    fft_run<T, PL, DIR, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
+    fft_run<T, PL, DIR, C, 0, CH>(v, lds + g * CH * LdsLine<NL>::size, t, ltw);
     const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
     auto idx = [&](int, int e, int gi) -> long long {
         const int ln = line0 + gi;
@@ -1094,7 +1107,7 @@ __global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
         return ((long long)a * NL + e) * p.B + b;
     };
     if constexpr (DIR > 0) {
-        tiled_line_store<T, PL, 3>(v, lds, p.G, g, t, p.out, mbase, idx);
+        tiled_line_store<T, PL, 3, CH>(v, lds, p.G, g, t, p.out, mbase, idx);
     } else {
         cpx<T> w[2][E];
 #pragma unroll
@@ -1103,7 +1116,7 @@ __global__ void __launch_bounds__(256) k_ypass(PassArgs<T> p) {
             w[0][m] = mk<T>(v[0][m].x + ky * v[1][m].y, v[0][m].y - ky * v[1][m].x);   // V0 - i kappa1_y V1
             w[1][m] = v[2][m];
         }
-        tiled_line_store<T, PL, 2>(w, lds, p.G, g, t, p.out, mbase, idx);
+        tiled_line_store<T, PL, 2, CH < 2 ? CH : 2>(w, lds, p.G, g, t, p.out, mbase, idx);
     }
 }
 

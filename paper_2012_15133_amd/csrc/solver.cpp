@@ -55,16 +55,18 @@ struct Layout {
 
 // Launch plan of the step kernels: values per thread (E) and target threads per
 // workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T"
-// (and "finsep" to close every step in a separate kernel).
+// (and "finsep" to close every step in a separate kernel).  The 3-D y passes (mid) take
+// workgroups of up to 512 threads, the other kernels up to 256.
+constexpr int MID_T_MAX = 512, T_MAX = 256;
 struct RolePlan {
     int E = 8, T = 256;
 };
 struct TunePlan {
-    RolePlan inv, real, fwd, mid;
+    RolePlan inv, real, fwd, mid{8, MID_T_MAX};
     int fin_in_kernel = 1;  // allow closing each step inside the next update kernel
 };
 
-void parse_role(const char* spec, const char* key, RolePlan& r) {
+void parse_role(const char* spec, const char* key, RolePlan& r, int tmax) {
     const char* p = std::strstr(spec, key);
     if (!p) return;
     p += std::strlen(key);
@@ -72,17 +74,17 @@ void parse_role(const char* spec, const char* key, RolePlan& r) {
     int e = 0, t = 0;
     if (std::sscanf(p + 1, "%d/%d", &e, &t) >= 1) {
         if (e == 4 || e == 8 || e == 16) r.E = e;
-        if (t >= 64 && t <= 256) r.T = t;
+        if (t >= 64 && t <= tmax) r.T = t;
     }
 }
 
 TunePlan tune_plan() {
     TunePlan tp;
     if (const char* env = std::getenv("SPFC_PLAN")) {
-        parse_role(env, "inv", tp.inv);
-        parse_role(env, "real", tp.real);
-        parse_role(env, "fwd", tp.fwd);
-        parse_role(env, "mid", tp.mid);
+        parse_role(env, "inv", tp.inv, T_MAX);
+        parse_role(env, "real", tp.real, T_MAX);
+        parse_role(env, "fwd", tp.fwd, T_MAX);
+        parse_role(env, "mid", tp.mid, MID_T_MAX);
         if (std::strstr(env, "finsep")) tp.fin_in_kernel = 0;
     }
     return tp;
@@ -113,8 +115,8 @@ Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
     const int cB = (d == 2 ? 1 : 3) + (s.beta ? (d == 2 ? 2 : 1) : 0);
     h.B = line_shape(s.nx, cB, s.elem, rowgroups, tp.real.E, tp.real.T);
     if (d == 3) {
-        h.midI = line_shape(s.ny, 3, s.elem, s.nz * s.nxh, tp.mid.E, tp.mid.T);
-        h.midF = line_shape(s.ny, 3, s.elem, s.nxh * s.nz, tp.mid.E, tp.mid.T);
+        h.midI = line_shape(s.ny, YPASS_CH, s.elem, s.nz * s.nxh, tp.mid.E, tp.mid.T);
+        h.midF = line_shape(s.ny, YPASS_CH, s.elem, s.nxh * s.nz, tp.mid.E, tp.mid.T);
         h.swapInit = line_shape(s.ny, 1, s.elem, s.nxh * s.nz);
         h.swapGet = line_shape(s.ny, 1, s.elem, s.nz * s.nxh);
     }
@@ -1400,8 +1402,10 @@ int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
     RolePlan TunePlan::*roles[4] = {&TunePlan::inv, &TunePlan::real, &TunePlan::fwd, &TunePlan::mid};
     const int nroles = ctx->sz.dim == 3 ? 4 : 3;
     for (int r = 0; r < nroles && !rc; ++r) {
+        const int tmax = r == 3 ? MID_T_MAX : T_MAX;   // roles[3]: the 3-D y passes
         for (int E : {4, 8, 16}) {
-            for (int T : {128, 256}) {
+            for (int T : {128, 256, 512}) {
+                if (T > tmax) continue;
                 TunePlan cand = best;
                 if ((cand.*roles[r]).E == E && (cand.*roles[r]).T == T) continue;
                 (cand.*roles[r]).E = E;

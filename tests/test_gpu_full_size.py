@@ -38,8 +38,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # The plans the benchmark's tuner has picked (values per thread / threads per workgroup).
-# At 256^3 it now keeps the built-in plan (8 / 256 for every role); PLAN_C3 is its earlier
-# pick (the real-space pass at 4 values per thread: the other store path of that pass).
+# At 256^3 it keeps the built-in plan (8 values per thread; 512 threads for the y passes,
+# 256 for the others); PLAN_C3 is an earlier pick (the real-space pass at 4 values per
+# thread and 256-thread y passes: the other store paths of those kernels).
 PLAN_C3 = "inv=8/256,mid=8/256,real=4/256,fwd=8/256"
 PLAN_C2 = "inv=4/256,real=4/256,fwd=8/128"
 
@@ -66,11 +67,12 @@ THIN_STEPS, THIN_DT = 20, 0.005
 
 
 def _role_plans():
-    """Every values-per-thread x workgroup-size choice of the tuner, one role at a time."""
+    """Every values-per-thread x workgroup-size choice of the tuner, one role at a time (the
+    y passes also take 512-thread workgroups)."""
     out = []
     for role in ("inv", "mid", "real", "fwd"):
         for e in (4, 8, 16):
-            for t in (128, 256):
+            for t in ((128, 256, 512) if role == "mid" else (128, 256)):
                 out.append(f"{role}={e}/{t}")
     return out
 

@@ -23,6 +23,8 @@ PLANS = [
     "inv=8/256,mid=8/256,real=8/256,fwd=8/256",
     "inv=16/256,mid=16/128,real=16/128,fwd=8/64",
     "inv=8/128,mid=4/256,real=4/128,fwd=4/128,finsep",
+    "inv=4/128,mid=8/512,real=8/128,fwd=8/128",
+    "mid=4/512",
 ]
 
 
