@@ -466,13 +466,16 @@ __device__ inline void tiled_line_store(const cpx<T> (&v)[C][PL::E], cpx<T>* til
 // FIN: the variant that can close the pending step itself (p.fin); without it the
 // reduction's registers are not held (161 -> 106 VGPRs at 256 points, FP32), so a
 // separately closed step runs more waves per SIMD.
+// 3-D: the two lines of a group go through the exchanges and the output tile one at a
+// time (one line buffer per group), so that workgroups of up to 512 threads (16 lines of
+// 256 points) write runs of 16 neighbouring entries; 2-D keeps both lines at once.
 template <typename T, int NL, int EE, int DIM, bool STAB, bool FIN>
-__global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
+__global__ void __launch_bounds__(DIM == 3 ? 512 : 256) k_spec_inv(SpecInvArgs<T> p) {
     using PL = Plan<NL, EE>;
-    constexpr int E = PL::E, P = PL::P, C = 2;
+    constexpr int E = PL::E, P = PL::P, C = 2, CH = DIM == 3 ? 1 : C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* ltw = lds + p.G * C * LdsLine<NL>::size;
+    cpx<T>* ltw = lds + p.G * CH * LdsLine<NL>::size;
     const int tid = threadIdx.x, g = tid / P, t = tid - g * P;
     const int line = xcd_block(blockIdx.x, gridDim.x) * p.G + g;
     const bool act = line < p.nlines;
@@ -549,11 +552,11 @@ __global__ void __launch_bounds__(256) k_spec_inv(SpecInvArgs<T> p) {
     if (!p.update) store_energy_partials<STAB>(acc, p.part + NPART_E * ((size_t)mem * gridDim.x + blockIdx.x));
     if (p.want_grad) {
         stage_twiddles<T, PL>(ltw, p.tw, p.tws);
-        fft_run<T, PL, +1, C>(v, lds + g * C * LdsLine<NL>::size, t, ltw);
+        fft_run<T, PL, +1, C, 0, CH>(v, lds + g * CH * LdsLine<NL>::size, t, ltw);
         if constexpr (DIM == 3) {
             // rotated output [e][lines]: the workgroup's lines are neighbours for each e
             const int line0 = xcd_block(blockIdx.x, gridDim.x) * p.G;
-            tiled_line_store<T, PL, C>(v, lds, p.G, g, t, p.out, mbase, [&](int, int e, int gi) -> long long {
+            tiled_line_store<T, PL, C, CH>(v, lds, p.G, g, t, p.out, mbase, [&](int, int e, int gi) -> long long {
                 const int ln = line0 + gi;
                 return ln < p.nlines ? (long long)e * p.nlines + ln : -1;
             });

@@ -55,16 +55,20 @@ struct Layout {
 
 // Launch plan of the step kernels: values per thread (E) and target threads per
 // workgroup for each role.  Overridable with SPFC_PLAN="inv=E/T,real=E/T,fwd=E/T,mid=E/T"
-// (and "finsep" to close every step in a separate kernel).  The 3-D y passes (mid) take
-// workgroups of up to 512 threads, the other kernels up to 256.
-constexpr int MID_T_MAX = 512, T_MAX = 256;
+// (and "finsep" to close every step in a separate kernel).  The 3-D inverse pass and y
+// passes take workgroups of up to 512 threads (their built-in size), the other kernels up
+// to 256.
+constexpr int WIDE_T_MAX = 512, T_MAX = 256;
 struct RolePlan {
     int E = 8, T = 256;
 };
 struct TunePlan {
-    RolePlan inv, real, fwd, mid{8, MID_T_MAX};
+    RolePlan inv, real, fwd, mid{8, WIDE_T_MAX};
     int fin_in_kernel = 1;  // allow closing each step inside the next update kernel
 };
+
+// largest workgroup of a role (0 inv, 1 real, 2 fwd, 3 mid) in `dim` dimensions
+constexpr int role_t_max(int role, int dim) { return (role == 3 || (role == 0 && dim == 3)) ? WIDE_T_MAX : T_MAX; }
 
 void parse_role(const char* spec, const char* key, RolePlan& r, int tmax) {
     const char* p = std::strstr(spec, key);
@@ -78,13 +82,14 @@ void parse_role(const char* spec, const char* key, RolePlan& r, int tmax) {
     }
 }
 
-TunePlan tune_plan() {
+TunePlan tune_plan(int dim) {
     TunePlan tp;
+    if (dim == 3) tp.inv.T = WIDE_T_MAX;
     if (const char* env = std::getenv("SPFC_PLAN")) {
-        parse_role(env, "inv", tp.inv, T_MAX);
-        parse_role(env, "real", tp.real, T_MAX);
-        parse_role(env, "fwd", tp.fwd, T_MAX);
-        parse_role(env, "mid", tp.mid, MID_T_MAX);
+        parse_role(env, "inv", tp.inv, role_t_max(0, dim));
+        parse_role(env, "real", tp.real, role_t_max(1, dim));
+        parse_role(env, "fwd", tp.fwd, role_t_max(2, dim));
+        parse_role(env, "mid", tp.mid, role_t_max(3, dim));
         if (std::strstr(env, "finsep")) tp.fin_in_kernel = 0;
     }
     return tp;
@@ -107,7 +112,7 @@ Shapes shapes_of(const Sizes& s, int M, const TunePlan& tp) {
     const int nl = d == 2 ? s.ny : s.nz;               // contiguous spectral axis
     const int nlines = d == 2 ? s.nxh : s.nxh * s.ny;  // spectral lines per member
     // the spectral passes carry two lines each (phihat and one derivative; two flux fields)
-    h.A = line_shape(nl, 2, s.elem, nlines, tp.inv.E, tp.inv.T);
+    h.A = line_shape(nl, d == 3 ? 1 : 2, s.elem, nlines, tp.inv.E, tp.inv.T);   // 3-D: one line buffer per group
     h.Cf = line_shape(nl, 2, s.elem, nlines, tp.fwd.E, tp.fwd.T);
     // real-space pass: lines per row group (2-D one row per group; 3-D and with the
     // quartic term two rows, plus the line of phi)
@@ -992,7 +997,7 @@ int make_ctx(const spfc_grid* grids, const spfc_params* params, const int* idx, 
     }
     ctx->sz = sizes_of(grids[idx[0]], p0.precision);
     ctx->sz.beta = beta;   // some member has the quartic term: the class runs that variant
-    ctx->plan = tune_plan();
+    ctx->plan = tune_plan(ctx->sz.dim);
     if (!plan_fits(ctx->sz, M, ctx->plan, device_lds_max())) {
         delete ctx;
         return SPFC_E_INVAL;
@@ -1402,7 +1407,7 @@ int tune_ctx(spfc_ctx* ctx, double dt, int64_t trial, char* snap) {
     RolePlan TunePlan::*roles[4] = {&TunePlan::inv, &TunePlan::real, &TunePlan::fwd, &TunePlan::mid};
     const int nroles = ctx->sz.dim == 3 ? 4 : 3;
     for (int r = 0; r < nroles && !rc; ++r) {
-        const int tmax = r == 3 ? MID_T_MAX : T_MAX;   // roles[3]: the 3-D y passes
+        const int tmax = role_t_max(r, ctx->sz.dim);
         for (int E : {4, 8, 16}) {
             for (int T : {128, 256, 512}) {
                 if (T > tmax) continue;

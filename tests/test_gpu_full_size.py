@@ -38,9 +38,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # The plans the benchmark's tuner has picked (values per thread / threads per workgroup).
-# At 256^3 it keeps the built-in plan (8 values per thread; 512 threads for the y passes,
-# 256 for the others); PLAN_C3 is an earlier pick (the real-space pass at 4 values per
-# thread and 256-thread y passes: the other store paths of those kernels).
+# At 256^3 it keeps the built-in plan (8 values per thread; 512 threads for the inverse
+# pass and the y passes, 256 for the others); PLAN_C3 is an earlier pick (the real-space
+# pass at 4 values per thread, 256-thread inverse and y passes: the other store paths).
 PLAN_C3 = "inv=8/256,mid=8/256,real=4/256,fwd=8/256"
 PLAN_C2 = "inv=4/256,real=4/256,fwd=8/128"
 
@@ -68,11 +68,11 @@ THIN_STEPS, THIN_DT = 20, 0.005
 
 def _role_plans():
     """Every values-per-thread x workgroup-size choice of the tuner, one role at a time (the
-    y passes also take 512-thread workgroups)."""
+    3-D inverse pass and y passes also take 512-thread workgroups)."""
     out = []
     for role in ("inv", "mid", "real", "fwd"):
         for e in (4, 8, 16):
-            for t in ((128, 256, 512) if role == "mid" else (128, 256)):
+            for t in ((128, 256, 512) if role in ("inv", "mid") else (128, 256)):
                 out.append(f"{role}={e}/{t}")
     return out
 

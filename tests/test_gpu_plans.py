@@ -24,7 +24,7 @@ PLANS = [
     "inv=16/256,mid=16/128,real=16/128,fwd=8/64",
     "inv=8/128,mid=4/256,real=4/128,fwd=4/128,finsep",
     "inv=4/128,mid=8/512,real=8/128,fwd=8/128",
-    "mid=4/512",
+    "inv=8/512,mid=4/512",
 ]
 
 
