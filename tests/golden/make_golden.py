@@ -5,7 +5,7 @@ Calls only the CPU oracle (oracle/spfc_oracle.py) and the seeded input generator
 the GPU path.
 
   python tests/golden/make_golden.py --which c2   # 1024^2, 2000 steps (about three hours, one core)
-  python tests/golden/make_golden.py --which c3   # 256^3, 20 steps (about an hour, one core)
+  python tests/golden/make_golden.py --which c3   # 256^3, 60 steps (about four and a half hours, one core)
 
 Each file is an .npz holding, for the run it names:
   meta          JSON text: grid, box, epsilon, dt, steps, seed, mean, start-up, sample stride
@@ -41,7 +41,7 @@ RUNS = {
     "c2": dict(file="spfc2d_1024_seed2.npz", n=(1024, 1024), L=(128 * math.pi,) * 2, epsilon=0.25, dt=0.01,
                steps=2000, seed=2, mean=-0.2, startup="sav1", stride=8, keep=(1, 3, 200, 1000, 2000)),
     "c3": dict(file="spfc3d_256_seed3.npz", n=(256, 256, 256), L=(32 * math.pi,) * 3, epsilon=0.25, dt=0.005,
-               steps=20, seed=3, mean=-0.25, startup="sav1", stride=8, keep=(1, 3, 20)),
+               steps=60, seed=3, mean=-0.25, startup="sav1", stride=8, keep=(1, 3, 20, 60)),
 }
 
 
