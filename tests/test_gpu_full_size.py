@@ -214,8 +214,8 @@ def test_c3_first_steps_against_oracle(monkeypatch, plan, precision):
 
 def test_c3_500_steps_fp32_against_fp64_path(monkeypatch):
     """The 256^3 run at its configured 500 steps.  One oracle step of 256^3 takes minutes on
-    the host, so the FP64 oracle stops at the stored 20 steps; over those the FP64 path
-    matches it to ~3e-15 (test_c3_first_steps_against_oracle), and here it stands in for it:
+    the host, so the FP64 oracle stops at the stored 60 steps; over those the FP64 path
+    matches it to ~4e-15 (test_c3_first_steps_against_oracle), and here it stands in for it:
     the FP32 path's error at step 500 against the FP64 path is its error against the FP64
     method up to that difference.  Also: the FP64 path keeps the mean and the modified
     energy does not rise over the 500 steps (Theorems 2.1 and 3.1)."""
